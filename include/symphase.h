@@ -1,0 +1,158 @@
+/*
+ * symphase.h -- C ABI of the phase-symbolization sampler for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The paper states the problem as: given a noisy stabilizer circuit C with a
+ * noise model P_C and a sample count, return that many samples of all
+ * measurements (Algorithm 1, its input/output lines).  Algorithm 1 splits it
+ * into Initialization(C) -> m_1..m_nm and Sampling(n_smp, P_C, m_1..m_nm) ->
+ * M_samples.  This library maps those to
+ *
+ *   sp_circuit_parse + sp_symbolize   Initialization, on the host
+ *                                     (Section 3.2.2: Init-C, Init-P, Init-M)
+ *   sp_model_upload                   make (M, c, P_C) resident on the GPU
+ *   sp_sample                         Sampling, on the GPU (Section 3.2.3, Eq. 4)
+ *
+ * Conventions
+ *   - Every function returns SP_OK (0) or a negative SP_E_* code; the message
+ *     is in sp_last_error() (thread-local, valid until the next call on the
+ *     same thread).  No C++ exception crosses this boundary.  Arguments are
+ *     validated before any device work is queued.
+ *   - Handles (sp_circuit, sp_model, sp_dmodel) are owned by the library and
+ *     released by the matching *_free function, which accepts NULL.
+ *   - The library allocates no device memory.  The device model lives in a
+ *     caller-provided device buffer; sample outputs are caller-provided device
+ *     buffers.  `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream); device work is queued on it asynchronously.
+ *
+ * Circuit text: one instruction per line, '#' comments.
+ *   H S X Y Z <q...>            Clifford / Pauli gates
+ *   CX <c t ...>                CNOT on (control, target) pairs
+ *   M <q...>   R <q...>   MR <q...>   measure / reset / measure-then-reset (Z basis)
+ *   X_ERROR(p) Y_ERROR(p) Z_ERROR(p) <q...>   Pauli fault with probability p
+ *   DEPOLARIZE1(p) <q...>       X, Y, Z each with probability p/3
+ *   DEPOLARIZE2(p) <a b ...>    each of the 15 non-identity two-qubit Paulis with p/15
+ *   TICK
+ * p is an exact decimal literal in [0, 1].
+ *
+ * Locations, variables and draws (the sampling contract)
+ *   - A location l is, in program order, each target of a one-qubit channel,
+ *     each pair of DEPOLARIZE2, and each target of M, R and MR.
+ *   - For shot index t (absolute: first_shot + i) and 64-bit seed,
+ *       u(l) = Philox4x32-10(ctr = (l/4, t mod 2^32, t / 2^32, 0),
+ *                            key = (seed mod 2^32, seed / 2^32))[l mod 4].
+ *   - A channel whose m non-identity outcomes each have probability p/m
+ *     (m = 1, 3, 15) has thresholds T_k = floor(k * p * 2^32 / m); it picks
+ *     code k when T_{k-1} <= u < T_k (T_0 = 0), identity when u >= T_m.
+ *     Code bits: X/Y/Z_ERROR fire on code 1; DEPOLARIZE1 code k is
+ *     X^(bit0) Z^(bit1); DEPOLARIZE2 code k is X^(bit0) Z^(bit1) on the first
+ *     qubit and X^(bit2) Z^(bit3) on the second.
+ *   - A measurement whose outcome is random (Init-M, first case) takes the
+ *     bit [u(l) < 2^31]; a determined one draws nothing.
+ *   - Variables (columns of M) are numbered in location order; a noise
+ *     location owns one variable per code bit (bit order), a random
+ *     measurement owns one, a determined measurement none.
+ *
+ * Output layout (M_samples of Eq. 4, packed 64 shots per word)
+ *   out[k * ld_words + w], bit b (LSB = 0) = outcome of recorded measurement k
+ *   (program order) in shot first_shot + 64 w + b.  Bits for shots >= `shots`
+ *   are written as 0; words w >= ceil(shots/64) are not written.
+ */
+#ifndef SYMPHASE_H
+#define SYMPHASE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SP_OK 0
+#define SP_E_INVALID (-1)     /* bad argument (null pointer, size, alignment) */
+#define SP_E_PARSE (-2)       /* malformed circuit text or probability */
+#define SP_E_UNSUPPORTED (-3) /* instruction outside the stabilizer gate set */
+#define SP_E_NOMEM (-4)       /* host allocation failed */
+#define SP_E_DEVICE (-5)      /* HIP runtime error (message included) */
+#define SP_E_LIMIT (-6)       /* a size exceeds what the kernels support */
+
+typedef struct sp_circuit sp_circuit; /* parsed circuit (host) */
+typedef struct sp_model sp_model;     /* (M, c) and the location table (host) */
+typedef struct sp_dmodel sp_dmodel;   /* device-resident model */
+
+typedef struct {
+  uint32_t n_qubits;
+  uint32_t n_meas;        /* recorded measurements = rows of M */
+  uint32_t n_locs;        /* locations */
+  uint32_t n_vars;        /* variables = columns of M (the constant excluded) */
+  uint32_t n_random_meas; /* M/R/MR locations whose outcome is random */
+  uint32_t n_drawn;       /* locations the sampler draws for (p > 0 or random) */
+  uint64_t nnz;           /* nonzero entries of M (the constant column excluded) */
+} sp_dims;
+
+/* Evaluation path of the sampling kernel for out = M s + c (Eq. 4). */
+enum {
+  SP_PATH_AUTO = 0,   /* chosen from the column density of M */
+  SP_PATH_SPARSE = 1, /* per fired variable, XOR into the rows of its column list */
+  SP_PATH_DENSE = 2   /* per fired variable, XOR into the rows set in its n_m-bit mask */
+};
+
+/* Parses circuit text (len bytes, need not be NUL-terminated).
+ * Errors: SP_E_INVALID (null), SP_E_PARSE, SP_E_UNSUPPORTED. */
+int sp_circuit_parse(const char* text, size_t len, sp_circuit** out);
+void sp_circuit_free(sp_circuit* circuit);
+
+/* Algorithm 1, Initialization: one forward pass of the tableau with symbolic
+ * phases (Section 3.2.2; Init-C for H/S/CNOT, Init-P for each fault variable,
+ * Init-M for measurements; reset is measure-then-conditional-X, the X
+ * exponent being the outcome's expression).  The noise model P_C is the set
+ * of channel instructions in the circuit.  Errors: SP_E_INVALID, SP_E_NOMEM,
+ * SP_E_LIMIT. */
+int sp_symbolize(const sp_circuit* circuit, sp_model** out);
+void sp_model_free(sp_model* model);
+
+int sp_model_dims(const sp_model* model, sp_dims* out);
+
+/* Dense export of M and c: M has n_meas rows of row_words uint64 words
+ * (row_words >= ceil(n_vars/64)); bit j of row k is M[k][j].  c (nullable):
+ * ceil(n_meas/64) words, bit k = constant term of measurement k.  Host memory. */
+int sp_model_export_dense(const sp_model* model, uint64_t* M, size_t row_words, uint64_t* c);
+
+/* Column-list (CSC) export: col_ptr has n_vars+1 entries, row_idx nnz entries
+ * (ascending rows within a column).  Host memory. */
+int sp_model_export_csc(const sp_model* model, uint32_t* col_ptr, uint32_t* row_idx);
+
+/* Variable j belongs to location var_loc[j], code bit var_bit[j].  Host memory. */
+int sp_model_export_vars(const sp_model* model, uint32_t* var_loc, uint8_t* var_bit);
+
+/* Bytes of device memory the resident model needs for `path`. */
+int sp_model_device_bytes(const sp_model* model, int path, size_t* bytes);
+
+/* Copies the model into the caller's device buffer d_buf (>= device_bytes,
+ * 256-byte aligned) on `stream` and returns a handle that refers to it.  The
+ * caller keeps d_buf alive and unmodified until sp_dmodel_free.  The copy is
+ * asynchronous on `stream`; the host model may be freed after the call
+ * returns (staging is internal and synchronous with respect to the host).
+ * Errors: SP_E_INVALID, SP_E_LIMIT (n_meas too large for one LDS slab),
+ * SP_E_DEVICE. */
+int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_bytes, void* stream,
+                    sp_dmodel** out);
+void sp_dmodel_free(sp_dmodel* dmodel);
+int sp_dmodel_dims(const sp_dmodel* dmodel, sp_dims* out);
+
+/* Algorithm 1, Sampling, for shots [first_shot, first_shot + shots): draws
+ * the variables of every drawn location from the keyed Philox stream, packs
+ * them 64 shots per word and writes out = M s + c over GF(2) into d_out
+ * (device, n_meas rows of ld_words words, 8-byte aligned,
+ * ld_words >= ceil(shots/64)).  Asynchronous on `stream`.  The result is a
+ * pure function of (model, seed, first_shot, shots).  shots = 0 is a no-op.
+ * Errors: SP_E_INVALID, SP_E_LIMIT, SP_E_DEVICE. */
+int sp_sample(const sp_dmodel* dmodel, uint64_t seed, uint64_t first_shot, uint64_t shots,
+              uint64_t* d_out, size_t ld_words, void* stream);
+
+const char* sp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,169 @@
+"""Phase-symbolization sampler for AMD Instinct MI355X.
+
+Thin Python binding over the C ABI (include/symphase.h).  The functions
+named like the C entry points forward their arguments; the classes below
+only own handles and torch buffers.  All computation happens in the native
+library: symbolize on the host, sampling in the HIP kernels.  There is no
+fallback: without the built library, importing the binding raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _capi
+from ._capi import (  # noqa: F401
+    EXPORTS,
+    SP_PATH_AUTO,
+    SP_PATH_DENSE,
+    SP_PATH_SPARSE,
+    SymphaseError,
+    check,
+    lib,
+    sp_dims,
+)
+
+_PATHS = {"auto": SP_PATH_AUTO, "sparse": SP_PATH_SPARSE, "dense": SP_PATH_DENSE}
+
+
+def _release(obj, fn: str):
+    h = getattr(obj, "_h", None)
+    L = _capi._lib
+    if h and L is not None:
+        try:
+            getattr(L, fn)(h)
+        except Exception:
+            pass
+    obj._h = None
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Circuit:
+    """Parsed circuit (sp_circuit_parse)."""
+
+    def __init__(self, text: str):
+        b = text.encode()
+        h = ctypes.c_void_p()
+        check(lib().sp_circuit_parse(b, len(b), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self, _rel=_release):
+        _rel(self, "sp_circuit_free")
+
+
+class Model:
+    """(M, c) and the location table (sp_symbolize): Algorithm 1, Initialization."""
+
+    def __init__(self, circuit: Circuit | str):
+        if isinstance(circuit, str):
+            circuit = Circuit(circuit)
+        h = ctypes.c_void_p()
+        check(lib().sp_symbolize(circuit.handle, ctypes.byref(h)))
+        self._h = h
+        d = sp_dims()
+        check(lib().sp_model_dims(h, ctypes.byref(d)))
+        self.dims = d
+        self.n_meas, self.n_vars, self.n_locs = d.n_meas, d.n_vars, d.n_locs
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self, _rel=_release):
+        _rel(self, "sp_model_free")
+
+    def export_dense(self):
+        """(M as a (n_meas, n_vars) uint8 0/1 array, c as a uint8 0/1 vector)."""
+        rw = max(1, (self.n_vars + 63) // 64)
+        M = np.zeros((max(self.n_meas, 1), rw), dtype=np.uint64)
+        c = np.zeros(max(1, (self.n_meas + 63) // 64), dtype=np.uint64)
+        check(lib().sp_model_export_dense(self._h, M.ctypes.data, rw, c.ctypes.data))
+        bits = np.unpackbits(M.view(np.uint8), axis=1, bitorder="little")[: self.n_meas, : self.n_vars]
+        cb = np.unpackbits(c.view(np.uint8), bitorder="little")[: self.n_meas]
+        return bits, cb
+
+    def export_csc(self):
+        cp = np.zeros(self.n_vars + 1, dtype=np.uint32)
+        ri = np.zeros(max(1, self.dims.nnz), dtype=np.uint32)
+        check(lib().sp_model_export_csc(self._h, cp.ctypes.data, ri.ctypes.data))
+        return cp, ri[: self.dims.nnz]
+
+    def export_vars(self):
+        vl = np.zeros(max(1, self.n_vars), dtype=np.uint32)
+        vb = np.zeros(max(1, self.n_vars), dtype=np.uint8)
+        check(lib().sp_model_export_vars(self._h, vl.ctypes.data, vb.ctypes.data))
+        return vl[: self.n_vars], vb[: self.n_vars]
+
+    def device_bytes(self, path: str = "auto") -> int:
+        n = ctypes.c_size_t()
+        check(lib().sp_model_device_bytes(self._h, _PATHS[path], ctypes.byref(n)))
+        return n.value
+
+
+class DeviceModel:
+    """Device-resident model (sp_model_upload) in a torch-owned buffer."""
+
+    def __init__(self, model: Model, path: str = "auto", device=None, stream=None):
+        if not torch.cuda.is_available():
+            raise SymphaseError(-5, "no GPU: the sampler runs only on the device")
+        device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        nbytes = model.device_bytes(path)
+        with torch.cuda.device(device):
+            self.buffer = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+            base = self.buffer.data_ptr()
+            off = (-base) % 256
+            h = ctypes.c_void_p()
+            check(lib().sp_model_upload(model.handle, _PATHS[path], ctypes.c_void_p(base + off), nbytes,
+                                        ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        self.n_meas = model.n_meas
+        d = sp_dims()
+        check(lib().sp_dmodel_dims(h, ctypes.byref(d)))
+        self.dims = d
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self, _rel=_release):
+        _rel(self, "sp_dmodel_free")
+
+    def sample(self, shots: int, seed: int = 0, first_shot: int = 0, out: torch.Tensor | None = None,
+               ld: int | None = None, stream=None) -> torch.Tensor:
+        """Packed outcomes (n_meas, ld) int64 (bit patterns of uint64 words)."""
+        words = (shots + 63) // 64
+        if out is None:
+            ld = max(words, 1) if ld is None else ld
+            out = torch.empty((max(self.n_meas, 1), ld), dtype=torch.int64, device=self.device)
+        else:
+            ld = out.stride(0) if ld is None else ld
+            if out.dtype != torch.int64 or out.device != self.device or out.stride(1) != 1:
+                raise SymphaseError(-1, "out must be a row-contiguous int64 tensor on the model's device")
+            if out.numel() and out.shape[0] < self.n_meas:
+                raise SymphaseError(-1, "out has fewer rows than measurements")
+        with torch.cuda.device(self.device):
+            check(lib().sp_sample(self._h, seed, first_shot, shots, ctypes.c_void_p(out.data_ptr()), ld,
+                                  ctypes.c_void_p(_stream_handle(stream))))
+        return out
+
+
+def sample(dmodel: DeviceModel, shots: int, seed: int = 0, first_shot: int = 0, **kw) -> torch.Tensor:
+    return dmodel.sample(shots, seed=seed, first_shot=first_shot, **kw)
+
+
+def to_numpy_bits(packed: torch.Tensor) -> np.ndarray:
+    """Packed int64 tensor -> uint64 numpy array."""
+    return packed.detach().cpu().numpy().view(np.uint64)

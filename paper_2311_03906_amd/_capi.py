@@ -1,0 +1,77 @@
+"""ctypes declarations of the C ABI in include/symphase.h (argument
+marshalling only).  Loading fails loudly when the library is not built."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+# torch first: it loads the HIP runtime that this library then shares
+# (same soname), so streams and device pointers from torch are valid here.
+import torch  # noqa: F401
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsymphase_hip.so")
+
+SP_OK = 0
+SP_E_INVALID, SP_E_PARSE, SP_E_UNSUPPORTED, SP_E_NOMEM, SP_E_DEVICE, SP_E_LIMIT = -1, -2, -3, -4, -5, -6
+SP_PATH_AUTO, SP_PATH_SPARSE, SP_PATH_DENSE = 0, 1, 2
+
+#: every function the header declares (checked by the tests)
+EXPORTS = (
+    "sp_circuit_parse", "sp_circuit_free", "sp_symbolize", "sp_model_free", "sp_model_dims",
+    "sp_model_export_dense", "sp_model_export_csc", "sp_model_export_vars", "sp_model_device_bytes",
+    "sp_model_upload", "sp_dmodel_free", "sp_dmodel_dims", "sp_sample", "sp_last_error",
+)
+
+
+class sp_dims(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_uint32), ("n_meas", ctypes.c_uint32), ("n_locs", ctypes.c_uint32),
+                ("n_vars", ctypes.c_uint32), ("n_random_meas", ctypes.c_uint32), ("n_drawn", ctypes.c_uint32),
+                ("nnz", ctypes.c_uint64)]
+
+
+class SymphaseError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2311_03906_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, u32, u64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint64
+    P = ctypes.POINTER
+    sig = {
+        "sp_circuit_parse": ([ctypes.c_char_p, sz, P(vp)], ctypes.c_int),
+        "sp_circuit_free": ([vp], None),
+        "sp_symbolize": ([vp, P(vp)], ctypes.c_int),
+        "sp_model_free": ([vp], None),
+        "sp_model_dims": ([vp, P(sp_dims)], ctypes.c_int),
+        "sp_model_export_dense": ([vp, vp, sz, vp], ctypes.c_int),
+        "sp_model_export_csc": ([vp, vp, vp], ctypes.c_int),
+        "sp_model_export_vars": ([vp, vp, vp], ctypes.c_int),
+        "sp_model_device_bytes": ([vp, ctypes.c_int, P(sz)], ctypes.c_int),
+        "sp_model_upload": ([vp, ctypes.c_int, vp, sz, vp, P(vp)], ctypes.c_int),
+        "sp_dmodel_free": ([vp], None),
+        "sp_dmodel_dims": ([vp, P(sp_dims)], ctypes.c_int),
+        "sp_sample": ([vp, u64, u64, u64, vp, sz, vp], ctypes.c_int),
+        "sp_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def check(rc: int):
+    if rc != SP_OK:
+        raise SymphaseError(rc, lib().sp_last_error().decode(errors="replace"))

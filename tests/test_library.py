@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(no device calls)."""
+
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declarations_are_exported():
+    import paper_2311_03906_amd as sp
+    L = sp.lib()
+    declared = _declared("symphase.h")
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(sp.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", sp._capi.LIB_PATH], capture_output=True, text=True).stdout
+    syms = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    assert set(declared) <= syms
+
+
+def test_library_has_gfx950_code_object():
+    import paper_2311_03906_amd as sp
+    data = open(sp._capi.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_errors_cross_the_boundary_as_codes():
+    import paper_2311_03906_amd as sp
+    L = sp.lib()
+    import ctypes
+    assert L.sp_symbolize(None, None) == sp._capi.SP_E_INVALID
+    assert b"null" in L.sp_last_error()
+    assert L.sp_sample(None, 0, 0, 10, None, 1, None) == sp._capi.SP_E_INVALID
+    h = ctypes.c_void_p()
+    assert L.sp_circuit_parse(b"FOO 1\n", 6, ctypes.byref(h)) == sp._capi.SP_E_UNSUPPORTED
+    assert h.value is None
+    L.sp_circuit_free(None)
+    L.sp_model_free(None)
+    L.sp_dmodel_free(None)
+
+
+def test_sampling_requires_a_gpu_and_has_no_fallback():
+    import torch
+    import paper_2311_03906_amd as sp
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    m = sp.Model("X_ERROR(0.1) 0\nM 0\n")
+    with pytest.raises(sp.SymphaseError):
+        sp.DeviceModel(m)

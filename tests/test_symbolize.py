@@ -1,0 +1,152 @@
+"""Initialization (sp_symbolize, host C++) against the oracle and the paper.
+
+Every expected value comes from the oracle or from the paper's printed
+examples; the symbolic model is never compared with itself."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import oracle
+import paper_2311_03906_amd as sp
+from golden_io import example
+from workloads import random_clifford_circuit, repetition_memory, surface_memory, random_layered_circuit
+
+
+def _assignment(model_vars, codes):
+    """Variable values b_j from per-location codes."""
+    var_loc, var_bit = model_vars
+    return ((codes[var_loc] >> var_bit) & 1).astype(np.uint8)
+
+
+def _evaluate(M, c, b):
+    return ((M.astype(np.int64) @ b.astype(np.int64)) + c) % 2
+
+
+@pytest.mark.parametrize("name", ["fig1.txt", "bell.txt"])
+def test_paper_examples_M_and_c(name):
+    text, symbols, outcomes = example(name)
+    m = sp.Model(text)
+    M, c = m.export_dense()
+    var_loc, var_bit = m.export_vars()
+    col_of = {(int(l), int(b)): j for j, (l, b) in enumerate(zip(var_loc, var_bit))}
+    assert m.n_vars == len(symbols)
+    want = np.zeros((len(outcomes), m.n_vars), dtype=np.uint8)
+    for k, terms in enumerate(outcomes):
+        for s in terms:
+            want[k, col_of[symbols[s]]] ^= 1
+    assert np.array_equal(M, want)
+    assert not c.any()
+
+
+def _probe(text):
+    """(M, c) read off the oracle: c = outcomes with every code 0; column j =
+    outcomes with only variable j's code bit set, plus c."""
+    oc = oracle.Circuit(text)
+    m = sp.Model(text)
+    var_loc, var_bit = m.export_vars()
+    zero = np.zeros(oc.n_locs, dtype=np.uint8)
+    c0, _ = oc.run_codes(zero)
+    cols = []
+    for l, b in zip(var_loc, var_bit):
+        codes = zero.copy()
+        codes[l] = 1 << b
+        o, _ = oc.run_codes(codes)
+        cols.append(o ^ c0)
+    M = np.array(cols, dtype=np.uint8).T if cols else np.zeros((oc.n_meas, 0), dtype=np.uint8)
+    return m, M, c0
+
+
+@pytest.mark.parametrize("circ", [repetition_memory(3, 3, 1e-3), repetition_memory(5, 5, "0.01"),
+                                  surface_memory(3, 3, 1e-3), surface_memory(5, 2, "0.002"),
+                                  random_layered_circuit(12, seed=1, cnot_pairs=6, p_dep="0.01")],
+                         ids=["rep3", "rep5", "surf3", "surf5r2", "layered12"])
+def test_model_equals_oracle_probing(circ):
+    text = circ.text()
+    m, M_or, c_or = _probe(text)
+    M, c = m.export_dense()
+    assert np.array_equal(M, M_or)
+    assert np.array_equal(c, c_or)
+
+
+def test_random_measurements_get_variables():
+    text = surface_memory(3, 3, 1e-3).text()
+    oc = oracle.Circuit(text)
+    m = sp.Model(text)
+    _, was_random = oc.run_codes(np.zeros(oc.n_locs, dtype=np.uint8))
+    var_loc, _ = m.export_vars()
+    kinds = oc.location_kinds()
+    rnd_locs = {int(l) for l in var_loc if kinds[l] in oracle.MEAS_KINDS}
+    assert rnd_locs == set(np.nonzero(was_random)[0].tolist())
+    assert m.dims.n_random_meas == len(rnd_locs) == 8   # 4 X checks in round 1, 4 among final data
+
+
+@settings(max_examples=200, deadline=None)
+@given(seed=st.integers(0, 2 ** 31), n=st.integers(1, 7), n_ops=st.integers(1, 60))
+def test_model_matches_oracle_on_random_circuits(seed, n, n_ops):
+    """M b + c equals the oracle's outcomes for random code assignments of
+    random noisy circuits (gates, M, R, MR, all channels)."""
+    text = random_clifford_circuit(seed, n, n_ops).text()
+    oc = oracle.Circuit(text)
+    m = sp.Model(text)
+    M, c = m.export_dense()
+    mv = m.export_vars()
+    kinds = oc.location_kinds()
+    rng = np.random.default_rng(seed)
+    for _ in range(4):
+        codes = np.array([rng.integers(0, 2 ** oracle.CODE_BITS[int(k)]) for k in kinds], dtype=np.uint8)
+        want, _ = oc.run_codes(codes)
+        got = _evaluate(M, c, _assignment(mv, codes))
+        assert np.array_equal(got, want)
+
+
+def test_surface_d5_random_shots():
+    text = surface_memory(5, 5, "0.01").text()
+    oc = oracle.Circuit(text)
+    m = sp.Model(text)
+    M, c = m.export_dense()
+    mv = m.export_vars()
+    for shot in range(40):
+        codes = oc.draw_codes(seed=17, shot=shot)
+        want, _ = oc.run_codes(codes)
+        assert np.array_equal(_evaluate(M, c, _assignment(mv, codes)), want)
+
+
+def test_dims_and_csc_consistent():
+    text = surface_memory(5, 3, 1e-3).text()
+    m = sp.Model(text)
+    oc = oracle.Circuit(text)
+    d = m.dims
+    assert (d.n_qubits, d.n_meas, d.n_locs) == (oc.n_qubits, oc.n_meas, oc.n_locs)
+    cp, ri = m.export_csc()
+    M, _ = m.export_dense()
+    assert cp[-1] == d.nnz == M.sum()
+    for j in range(0, m.n_vars, 37):
+        rows = ri[cp[j]:cp[j + 1]]
+        assert list(rows) == list(np.nonzero(M[:, j])[0])
+    kinds = oc.location_kinds()
+    noise = sum(1 for k in kinds if k in oracle.NOISE_KINDS)
+    assert d.n_drawn == noise + d.n_random_meas
+
+
+def test_zero_probability_locations_not_drawn():
+    m = sp.Model("X_ERROR(0) 0\nX_ERROR(0.5) 1\nH 2\nM 0 1 2\n")
+    assert m.dims.n_vars == 3 and m.dims.n_drawn == 2 and m.dims.n_random_meas == 1
+
+
+@pytest.mark.parametrize("text,code", [("T 0\n", sp._capi.SP_E_UNSUPPORTED), ("CX 0\n", sp._capi.SP_E_PARSE),
+                                       ("X_ERROR(1.5) 0\n", sp._capi.SP_E_PARSE), ("M x\n", sp._capi.SP_E_PARSE),
+                                       ("H(0.1) 0\n", sp._capi.SP_E_PARSE), ("DEPOLARIZE2(0.1) 3 3\n", sp._capi.SP_E_PARSE)])
+def test_parse_errors(text, code):
+    with pytest.raises(sp.SymphaseError) as ei:
+        sp.Circuit(text)
+    assert ei.value.code == code
+
+
+def test_empty_circuit():
+    m = sp.Model("")
+    assert (m.dims.n_meas, m.dims.n_vars, m.dims.n_locs) == (0, 0, 0)
+    m = sp.Model("TICK\n# only a comment\n")
+    assert m.dims.n_meas == 0
