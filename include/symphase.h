@@ -87,6 +87,8 @@ typedef struct {
   uint32_t n_vars;        /* variables = columns of M (the constant excluded) */
   uint32_t n_random_meas; /* M/R/MR locations whose outcome is random */
   uint32_t n_drawn;       /* locations the sampler draws for (p > 0 or random) */
+  uint32_t n_draw_blocks; /* distinct l/4 over drawn locations = Philox blocks per shot */
+  uint32_t reserved;
   uint64_t nnz;           /* nonzero entries of M (the constant column excluded) */
 } sp_dims;
 
@@ -149,6 +151,20 @@ int sp_dmodel_dims(const sp_dmodel* dmodel, sp_dims* out);
  * Errors: SP_E_INVALID, SP_E_LIMIT, SP_E_DEVICE. */
 int sp_sample(const sp_dmodel* dmodel, uint64_t seed, uint64_t first_shot, uint64_t shots,
               uint64_t* d_out, size_t ld_words, void* stream);
+
+/* Launch shape of the sampling kernel: a workgroup of waves_per_group
+ * wave64s (1..16) owns words_per_group (1, 2 or 4) consecutive 64-shot words,
+ * each with its own LDS slab of n_meas uint64 rows.  The output does not
+ * depend on the launch shape. */
+typedef struct {
+  uint32_t waves_per_group;
+  uint32_t words_per_group;
+} sp_launch;
+
+/* Read / set the launch shape used by sp_sample for this model (NULL resets
+ * the library default).  Errors: SP_E_INVALID, SP_E_LIMIT (slabs exceed LDS). */
+int sp_dmodel_get_launch(const sp_dmodel* dmodel, sp_launch* out);
+int sp_dmodel_set_launch(sp_dmodel* dmodel, const sp_launch* launch);
 
 const char* sp_last_error(void);
 

@@ -24,14 +24,15 @@ from ._capi import (  # noqa: F401
     check,
     lib,
     sp_dims,
+    sp_launch,
 )
 
 _PATHS = {"auto": SP_PATH_AUTO, "sparse": SP_PATH_SPARSE, "dense": SP_PATH_DENSE}
 
 
-def _release(obj, fn: str):
+def _release(obj, fn: str, _c=_capi):
     h = getattr(obj, "_h", None)
-    L = _capi._lib
+    L = _c._lib
     if h and L is not None:
         try:
             getattr(L, fn)(h)
@@ -140,6 +141,21 @@ class DeviceModel:
 
     def __del__(self, _rel=_release):
         _rel(self, "sp_dmodel_free")
+
+    @property
+    def launch(self):
+        L = sp_launch()
+        check(lib().sp_dmodel_get_launch(self._h, ctypes.byref(L)))
+        return (L.waves_per_group, L.words_per_group)
+
+    @launch.setter
+    def launch(self, value):
+        """(waves_per_group, words_per_group), or None for the default."""
+        if value is None:
+            check(lib().sp_dmodel_set_launch(self._h, None))
+        else:
+            L = sp_launch(int(value[0]), int(value[1]))
+            check(lib().sp_dmodel_set_launch(self._h, ctypes.byref(L)))
 
     def sample(self, shots: int, seed: int = 0, first_shot: int = 0, out: torch.Tensor | None = None,
                ld: int | None = None, stream=None) -> torch.Tensor:

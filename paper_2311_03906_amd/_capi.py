@@ -20,14 +20,19 @@ SP_PATH_AUTO, SP_PATH_SPARSE, SP_PATH_DENSE = 0, 1, 2
 EXPORTS = (
     "sp_circuit_parse", "sp_circuit_free", "sp_symbolize", "sp_model_free", "sp_model_dims",
     "sp_model_export_dense", "sp_model_export_csc", "sp_model_export_vars", "sp_model_device_bytes",
-    "sp_model_upload", "sp_dmodel_free", "sp_dmodel_dims", "sp_sample", "sp_last_error",
+    "sp_model_upload", "sp_dmodel_free", "sp_dmodel_dims", "sp_dmodel_get_launch", "sp_dmodel_set_launch",
+    "sp_sample", "sp_last_error",
 )
 
 
 class sp_dims(ctypes.Structure):
     _fields_ = [("n_qubits", ctypes.c_uint32), ("n_meas", ctypes.c_uint32), ("n_locs", ctypes.c_uint32),
                 ("n_vars", ctypes.c_uint32), ("n_random_meas", ctypes.c_uint32), ("n_drawn", ctypes.c_uint32),
-                ("nnz", ctypes.c_uint64)]
+                ("n_draw_blocks", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("nnz", ctypes.c_uint64)]
+
+
+class sp_launch(ctypes.Structure):
+    _fields_ = [("waves_per_group", ctypes.c_uint32), ("words_per_group", ctypes.c_uint32)]
 
 
 class SymphaseError(RuntimeError):
@@ -61,6 +66,8 @@ def lib():
         "sp_model_upload": ([vp, ctypes.c_int, vp, sz, vp, P(vp)], ctypes.c_int),
         "sp_dmodel_free": ([vp], None),
         "sp_dmodel_dims": ([vp, P(sp_dims)], ctypes.c_int),
+        "sp_dmodel_get_launch": ([vp, P(sp_launch)], ctypes.c_int),
+        "sp_dmodel_set_launch": ([vp, P(sp_launch)], ctypes.c_int),
         "sp_sample": ([vp, u64, u64, u64, vp, sz, vp], ctypes.c_int),
         "sp_last_error": ([], ctypes.c_char_p),
     }

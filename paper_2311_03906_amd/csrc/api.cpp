@@ -58,12 +58,21 @@ int sp_model_dims(const sp_model* m, sp_dims* d) {
   d->n_locs = m->n_locs;
   d->n_vars = m->n_vars;
   d->n_random_meas = m->n_random;
-  uint32_t drawn = 0;
+  uint32_t drawn = 0, blocks = 0;
+  int64_t last_block = -1;
   for (uint32_t l = 0; l < m->n_locs; ++l) {
     int32_t ch = m->loc_chan[l];
-    if (ch >= 0 && m->channels[ch].T[m->channels[ch].m] > 0) ++drawn;
+    if (ch >= 0 && m->channels[ch].T[m->channels[ch].m] > 0) {
+      ++drawn;
+      if ((int64_t)(l >> 2) != last_block) {
+        ++blocks;
+        last_block = l >> 2;
+      }
+    }
   }
   d->n_drawn = drawn;
+  d->n_draw_blocks = blocks;
+  d->reserved = 0;
   d->nnz = m->row_idx.size();
   return SP_OK;
 }

@@ -46,11 +46,9 @@ constexpr uint32_t kW1 = 0xBB67AE85u;
 
 // Device model: every section lives in the caller's buffer.
 struct DevModel {
-  const uint32_t* blk_ctr;   // [nb]      Philox block index l/4 of each block
-  const uint4* slots;        // [nb][2]   4 slots x (T_m - 1, meta); meta = var0<<8 | (chan+1), 0 = empty
-  const uint32_t* chans;     // [nch][16] kind, T_1..T_15
-  const uint32_t* col_ptr;   // [n_vars+1]
-  const uint32_t* row_idx;   // [nnz]
+  const uint4* blocks;       // [nb][4]: tm1[4] | meta[4] | lst[0..3] | (lst[4], blk, 0, 0)
+  const uint32_t* entries;   // merged (row << 2 | bit) lists, one per drawn location
+  const uint32_t* chans;     // [nch][16]: kind, T_1..T_15
   const uint64_t* c_mask;    // [ceil(n_meas/64)]
   const uint64_t* dense;     // [n_vars][dense_words] (dense path only)
   uint32_t nb, n_meas, dense_words;
@@ -63,7 +61,7 @@ struct LaunchArgs {
   uint64_t first_shot;
   uint64_t shots;
   uint32_t key0, key1;
-  uint32_t n_words;
+  uint32_t n_words, n_groups;
 };
 
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
@@ -89,38 +87,27 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// XOR the 64-lane mask s into the slab rows of variable v.
-template <int DENSE>
-__device__ __forceinline__ void xor_var(const DevModel& m, uint64_t* slab, uint32_t v, uint64_t s, uint32_t lane) {
-  if (DENSE) {
-    const uint64_t* col = m.dense + (size_t)v * m.dense_words;
-    for (uint32_t c = 0; c < m.dense_words; ++c) {
-      const uint64_t bits = col[c];
-      if (bits == 0) continue;
-      if ((bits >> lane) & 1ull) atomicXor((unsigned long long*)&slab[c * 64 + lane], (unsigned long long)s);
-    }
-  } else {
-    const uint32_t lo = m.col_ptr[v], hi = m.col_ptr[v + 1];
-    for (uint32_t i = lo + lane; i < hi; i += 64)
-      atomicXor((unsigned long long*)&slab[m.row_idx[i]], (unsigned long long)s);
-  }
+__device__ __forceinline__ uint32_t pick(const uint4& v, int s) {
+  return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
 }
 
-// A location fired in the lanes of `fire`: split into code-bit masks and
-// evaluate each variable.
-template <int DENSE>
-__device__ __noinline__ void fire_slot(const DevModel& m, uint64_t* slab, uint32_t u, uint64_t fire, uint32_t meta,
-                                       uint32_t lane) {
-  const uint32_t ch = (meta & 0xFFu) - 1u;
-  const uint32_t var0 = meta >> 8;
-  const uint32_t* T = m.chans + ch * 16u;
+// Code-bit masks of a fired location.  fire = lanes with u < T_m.  For a
+// channel with m codes, m_k = ballot(u < T_k) are nested (m_1 <= ... <= m_m),
+// so a lane with code k lies in exactly the m_j with j >= k; the XOR of the
+// m_j over the j where bit i of the code flips between j and j+1 (j = m
+// included, code m+1 read as 0) is therefore bit i of the lane's code.
+struct Masks {
+  uint64_t b0, b1, b2, b3;   // 64-lane masks of code bits 0..3
+};
+
+__device__ __forceinline__ Masks decode(const DevModel& m, uint32_t meta, uint32_t u, uint64_t fire) {
+  const uint32_t* T = m.chans + ((meta & 0xFFu) - 1u) * 16u;
   const uint32_t kind = T[0];
+  Masks r{fire, 0ull, 0ull, 0ull};   // X/Y/Z errors and the random-measurement coin
   if (kind == sp::CH_DEP1) {
     const uint64_t m1 = ballot(u < T[1]), m2 = ballot(u < T[2]);
-    const uint64_t bx = m1 ^ m2 ^ fire;   // codes 1, 3
-    const uint64_t bz = m1 ^ fire;        // codes 2, 3
-    if (bx) xor_var<DENSE>(m, slab, var0, bx, lane);
-    if (bz) xor_var<DENSE>(m, slab, var0 + 1, bz, lane);
+    r.b0 = m1 ^ m2 ^ fire;   // X part: codes 1 (X) and 3 (Y)
+    r.b1 = m1 ^ fire;        // Z part: codes 2 (Z) and 3 (Y)
   } else if (kind == sp::CH_DEP2) {
     uint64_t mk[16];
 #pragma unroll
@@ -132,78 +119,171 @@ __device__ __noinline__ void fire_slot(const DevModel& m, uint64_t* slab, uint32
       b0 ^= mk[k];
       if (k & 1) b1 ^= mk[k];
     }
-    const uint64_t b2 = mk[3] ^ mk[7] ^ mk[11] ^ mk[15];
-    const uint64_t b3 = mk[7] ^ mk[15];
-    if (b0) xor_var<DENSE>(m, slab, var0, b0, lane);
-    if (b1) xor_var<DENSE>(m, slab, var0 + 1, b1, lane);
-    if (b2) xor_var<DENSE>(m, slab, var0 + 2, b2, lane);
-    if (b3) xor_var<DENSE>(m, slab, var0 + 3, b3, lane);
-  } else {
-    xor_var<DENSE>(m, slab, var0, fire, lane);  // one-variable channels and the coin
+    r.b0 = b0;
+    r.b1 = b1;
+    r.b2 = mk[3] ^ mk[7] ^ mk[11] ^ mk[15];
+    r.b3 = mk[7] ^ mk[15];
+  }
+  return r;
+}
+
+// Evaluate a fired location: XOR its code-bit masks into the slab rows of
+// its variables' columns of M.
+__device__ __forceinline__ void xor_dense(const DevModel& m, uint64_t* slab, uint32_t var, uint64_t s, uint32_t lane) {
+  const uint64_t* col = m.dense + (size_t)var * m.dense_words;
+  for (uint32_t c = 0; c < m.dense_words; ++c) {
+    const uint64_t bits = col[c];
+    if ((bits >> lane) & 1ull) atomicXor((unsigned long long*)&slab[c * 64 + lane], (unsigned long long)s);
   }
 }
 
-// blockIdx -> word, keeping consecutive words on one XCD (workgroups are
+template <int DENSE>
+__device__ __forceinline__ void evaluate(const DevModel& m, uint64_t* slab, uint32_t meta, uint32_t lo, uint32_t hi,
+                                         const Masks& k, uint32_t lane) {
+  if (DENSE) {
+    const uint32_t var0 = meta >> 8;
+    if (k.b0) xor_dense(m, slab, var0, k.b0, lane);
+    if (k.b1) xor_dense(m, slab, var0 + 1, k.b1, lane);
+    if (k.b2) xor_dense(m, slab, var0 + 2, k.b2, lane);
+    if (k.b3) xor_dense(m, slab, var0 + 3, k.b3, lane);
+  } else {
+    for (uint32_t i = lo + lane; i < hi; i += 64) {
+      const uint32_t e = m.entries[i];
+      const uint64_t lo_pair = (e & 1u) ? k.b1 : k.b0;
+      const uint64_t hi_pair = (e & 1u) ? k.b3 : k.b2;
+      const uint64_t s = (e & 2u) ? hi_pair : lo_pair;
+      if (s) atomicXor((unsigned long long*)&slab[e >> 2], (unsigned long long)s);
+    }
+  }
+}
+
+// The draw-select-evaluate loop of one wave over its share of the blocks.
+// UHI: the high word of every lane's shot index is the same (the usual case),
+// which lets the first Philox rounds run on the scalar unit.
+template <int R, int DENSE, bool UHI>
+__device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, uint32_t g, uint32_t wave,
+                                           uint32_t n_waves, uint32_t lane) {
+  const DevModel& m = a.m;
+  uint32_t s_lo[R], s_hi[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t base = a.first_shot + (uint64_t)(g * R + r) * 64u;
+    if (UHI) {
+      s_lo[r] = (uint32_t)base + lane;
+      s_hi[r] = uniform((uint32_t)(base >> 32));
+    } else {
+      const uint64_t shot = base + lane;
+      s_lo[r] = (uint32_t)shot;
+      s_hi[r] = (uint32_t)(shot >> 32);
+    }
+  }
+  uint32_t b = wave;
+  if (b >= m.nb) return;
+  uint4 d0 = m.blocks[4 * b], d1 = m.blocks[4 * b + 1], d2 = m.blocks[4 * b + 2], d3 = m.blocks[4 * b + 3];
+  for (;;) {
+    const uint32_t bn = b + n_waves;
+    uint4 n0 = d0, n1 = d1, n2 = d2, n3 = d3;
+    if (bn < m.nb) {   // next descriptor in flight while this block computes
+      n0 = m.blocks[4 * bn];
+      n1 = m.blocks[4 * bn + 1];
+      n2 = m.blocks[4 * bn + 2];
+      n3 = m.blocks[4 * bn + 3];
+    }
+    uint4 u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = philox4x32_10(d3.y, s_lo[r], s_hi[r], 0u, a.key0, a.key1);
+    uint64_t f[R][4];
+    uint64_t any = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      f[r][0] = d1.x ? ballot(u[r].x <= d0.x) : 0ull;
+      f[r][1] = d1.y ? ballot(u[r].y <= d0.y) : 0ull;
+      f[r][2] = d1.z ? ballot(u[r].z <= d0.z) : 0ull;
+      f[r][3] = d1.w ? ballot(u[r].w <= d0.w) : 0ull;
+      any |= f[r][0] | f[r][1] | f[r][2] | f[r][3];
+    }
+    if (any) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          if (!f[r][s]) continue;
+          const uint32_t meta = pick(d1, s);
+          const Masks k = decode(m, meta, pick(u[r], s), f[r][s]);
+          const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
+          evaluate<DENSE>(m, slab + (size_t)r * m.n_meas, meta, lo, hi, k, lane);
+        }
+      }
+    }
+    if (bn >= m.nb) break;
+    b = bn;
+    d0 = n0;
+    d1 = n1;
+    d2 = n2;
+    d3 = n3;
+  }
+}
+
+// blockIdx -> group, keeping consecutive groups on one XCD (workgroups are
 // dealt round-robin over the 8 XCDs, each with its own L2).
-__device__ __forceinline__ uint32_t xcd_word(uint32_t b, uint32_t n) {
+__device__ __forceinline__ uint32_t xcd_group(uint32_t b, uint32_t n) {
   const uint32_t q = n / 8u, r = n % 8u;
   const uint32_t x = b % 8u, i = b / 8u;
   return x * q + min(x, r) + i;
 }
 
-template <int DENSE>
-__global__ void __launch_bounds__(512) sample_kernel(LaunchArgs a) {
+// One workgroup = R consecutive 64-shot words, each with its LDS slab of
+// n_meas rows.
+template <int R, int DENSE>
+__global__ void __launch_bounds__(1024) sample_kernel(LaunchArgs a) {
   extern __shared__ uint64_t slab[];
   const DevModel& m = a.m;
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
   const uint32_t wave = uniform(tid >> 6), n_waves = blockDim.x >> 6;
-  const uint32_t w = xcd_word(blockIdx.x, a.n_words);
+  const uint32_t g = xcd_group(blockIdx.x, a.n_groups);
 
-  for (uint32_t k = tid; k < m.n_meas; k += blockDim.x)
-    slab[k] = ((m.c_mask[k >> 6] >> (k & 63u)) & 1ull) ? ~0ull : 0ull;
-  __syncthreads();
-
-  const uint64_t shot = a.first_shot + (uint64_t)w * 64u + lane;
-  const uint32_t s_lo = (uint32_t)shot, s_hi = (uint32_t)(shot >> 32);
-
-  for (uint32_t b = wave; b < m.nb; b += n_waves) {
-    const uint32_t blk = m.blk_ctr[b];
-    const uint4 sa = m.slots[2 * b], sb = m.slots[2 * b + 1];
-    const uint4 u = philox4x32_10(blk, s_lo, s_hi, 0u, a.key0, a.key1);
-    const uint64_t f0 = sa.y ? ballot(u.x <= sa.x) : 0ull;
-    const uint64_t f1 = sa.w ? ballot(u.y <= sa.z) : 0ull;
-    const uint64_t f2 = sb.y ? ballot(u.z <= sb.x) : 0ull;
-    const uint64_t f3 = sb.w ? ballot(u.w <= sb.z) : 0ull;
-    if ((f0 | f1 | f2 | f3) == 0ull) continue;
-    if (f0) fire_slot<DENSE>(m, slab, u.x, f0, sa.y, lane);
-    if (f1) fire_slot<DENSE>(m, slab, u.y, f1, sa.w, lane);
-    if (f2) fire_slot<DENSE>(m, slab, u.z, f2, sb.y, lane);
-    if (f3) fire_slot<DENSE>(m, slab, u.w, f3, sb.w, lane);
+  for (uint32_t k = tid; k < m.n_meas; k += blockDim.x) {
+    const uint64_t v = ((m.c_mask[k >> 6] >> (k & 63u)) & 1ull) ? ~0ull : 0ull;
+#pragma unroll
+    for (int r = 0; r < R; ++r) slab[(size_t)r * m.n_meas + k] = v;
   }
   __syncthreads();
 
-  const uint64_t rem = a.shots - (uint64_t)w * 64u;
-  const uint64_t valid = rem >= 64u ? ~0ull : ((1ull << rem) - 1ull);
-  uint64_t* col = a.out + w;
-  for (uint32_t k = tid; k < m.n_meas; k += blockDim.x) col[(size_t)k * a.ld] = slab[k] & valid;
+  // Do the R words' shot indices share one high word?
+  const uint64_t first = a.first_shot + (uint64_t)g * R * 64u;
+  const uint64_t last = first + (uint64_t)R * 64u - 1u;
+  if ((first >> 32) == (last >> 32)) run_blocks<R, DENSE, true>(a, slab, g, wave, n_waves, lane);
+  else run_blocks<R, DENSE, false>(a, slab, g, wave, n_waves, lane);
+  __syncthreads();
+
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t w = g * R + r;
+    if (w >= a.n_words) break;
+    const uint64_t rem = a.shots - (uint64_t)w * 64u;
+    const uint64_t valid = rem >= 64u ? ~0ull : ((1ull << rem) - 1ull);
+    uint64_t* col = a.out + w;
+    for (uint32_t k = tid; k < m.n_meas; k += blockDim.x) col[(size_t)k * a.ld] = slab[(size_t)r * m.n_meas + k] & valid;
+  }
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-struct Layout {
-  size_t blk_ctr, slots, chans, col_ptr, row_idx, c_mask, dense, total;
-  uint32_t nb, nch, dense_words;
-};
-
 // Drawn locations grouped by Philox block (l/4); blocks without a drawn
-// location are left out.
-struct Blocks {
-  std::vector<uint32_t> ctr;
-  std::vector<uint32_t> slots;  // 8 words per block
+// location are left out.  16 words per block:
+//   [0..3]  T_m - 1 per slot (fire when u <= T_m - 1, i.e. u < T_m)
+//   [4..7]  meta per slot: var0 << 8 | (channel + 1); 0 = no drawn location
+//   [8..11] start of the slot's entry list; [12] end of slot 3's list
+//   [13]    the Philox block index l/4
+// Entry lists: for every variable of the location (bit b), for every row k
+// of its column of M, the word k << 2 | b.
+struct HostBlocks {
+  std::vector<uint32_t> words;
+  std::vector<uint32_t> entries;
 };
 
-Blocks build_blocks(const sp_model& m) {
-  Blocks B;
+HostBlocks build_blocks(const sp_model& m) {
+  HostBlocks H;
   int64_t cur = -1;
   for (uint32_t l = 0; l < m.n_locs; ++l) {
     const int32_t ch = m.loc_chan[l];
@@ -213,37 +293,49 @@ Blocks build_blocks(const sp_model& m) {
     if (Tm == 0) continue;  // never fires
     const int64_t blk = l >> 2;
     if (blk != cur) {
-      B.ctr.push_back((uint32_t)blk);
-      B.slots.insert(B.slots.end(), 8, 0u);
+      H.words.insert(H.words.end(), 16, 0u);
+      uint32_t* w = &H.words[H.words.size() - 16];
+      for (int i = 8; i <= 12; ++i) w[i] = (uint32_t)H.entries.size();
+      w[13] = (uint32_t)blk;
       cur = blk;
     }
-    uint32_t* s = &B.slots[B.slots.size() - 8 + 2 * (l & 3u)];
-    s[0] = (uint32_t)(Tm - 1);
-    s[1] = ((uint32_t)m.loc_var0[l] << 8) | (uint32_t)(ch + 1);
+    uint32_t* w = &H.words[H.words.size() - 16];
+    const uint32_t s = l & 3u, var0 = (uint32_t)m.loc_var0[l];
+    w[s] = (uint32_t)(Tm - 1);
+    w[4 + s] = (var0 << 8) | (uint32_t)(ch + 1);
+    w[8 + s] = (uint32_t)H.entries.size();
+    for (uint32_t b = 0; b < sp::loc_bits(m.loc_kind[l]); ++b)
+      for (uint32_t i = m.col_ptr[var0 + b]; i < m.col_ptr[var0 + b + 1]; ++i)
+        H.entries.push_back((m.row_idx[i] << 2) | b);
+    if (H.entries.size() >= (1ull << 32)) throw sp::Error(SP_E_LIMIT, "more than 2^32 entries in M");
+    for (uint32_t t = s + 1; t <= 4; ++t) w[8 + t] = (uint32_t)H.entries.size();
   }
-  return B;
+  return H;
 }
 
 int choose_path(const sp_model& m, int path) {
   if (path != SP_PATH_AUTO) return path;
   // Dense costs ceil(n_meas/64) LDS operations per fired variable, sparse
-  // ceil(|column|/64) plus a dependent index load: pick dense only when the
-  // columns are long compared with the slab.
+  // ceil(|location list|/64): pick dense only when columns are long compared
+  // with the slab.
   const double avg = m.n_vars ? (double)m.row_idx.size() / m.n_vars : 0.0;
   return (avg * 4.0 > (double)m.n_meas) ? SP_PATH_DENSE : SP_PATH_SPARSE;
 }
 
-Layout plan(const sp_model& m, int path, uint32_t nb) {
+struct Layout {
+  size_t blocks, entries, chans, c_mask, dense, total;
+  uint32_t nb, nch, dense_words;
+};
+
+Layout plan(const sp_model& m, int path, const HostBlocks& H) {
   Layout L{};
-  L.nb = nb;
+  L.nb = (uint32_t)(H.words.size() / 16);
   L.nch = (uint32_t)m.channels.size();
   L.dense_words = (m.n_meas + 63) / 64;
   size_t off = 0;
-  L.blk_ctr = off; off = align256(off + sizeof(uint32_t) * std::max<size_t>(nb, 1));
-  L.slots = off;   off = align256(off + 32 * std::max<size_t>(nb, 1));
+  L.blocks = off;  off = align256(off + 64 * std::max<size_t>(L.nb, 1));
+  L.entries = off; off = align256(off + 4 * std::max<size_t>(H.entries.size(), 1));
   L.chans = off;   off = align256(off + 64 * (size_t)L.nch);
-  L.col_ptr = off; off = align256(off + sizeof(uint32_t) * (m.n_vars + 1));
-  L.row_idx = off; off = align256(off + sizeof(uint32_t) * std::max<size_t>(m.row_idx.size(), 1));
   L.c_mask = off;  off = align256(off + 8 * std::max<size_t>(L.dense_words, 1));
   L.dense = off;
   if (path == SP_PATH_DENSE) off = align256(off + 8 * (size_t)m.n_vars * L.dense_words);
@@ -257,14 +349,49 @@ Layout plan(const sp_model& m, int path, uint32_t nb) {
     if (e_ != hipSuccess) return set_error(SP_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+using KernelFn = void (*)(LaunchArgs);
+
+KernelFn kernel_for(int path, uint32_t words_per_group) {
+  const bool dense = path == SP_PATH_DENSE;
+  switch (words_per_group) {
+    case 1: return dense ? sample_kernel<1, 1> : sample_kernel<1, 0>;
+    case 2: return dense ? sample_kernel<2, 1> : sample_kernel<2, 0>;
+    case 4: return dense ? sample_kernel<4, 1> : sample_kernel<4, 0>;
+    default: return nullptr;
+  }
+}
+
 }  // namespace
 
 struct sp_dmodel {
   DevModel m;
   int path;
   int device;
+  size_t lds_max;
+  sp_launch launch;
   sp_dims dims;
 };
+
+namespace {
+
+// Default launch: 8 waves per group; two words per group when two slabs fit
+// in a third of the LDS (more shots per descriptor fetch), else one.
+sp_launch default_launch(const sp_dmodel& dm) {
+  sp_launch L;
+  L.waves_per_group = 8;
+  L.words_per_group = ((size_t)dm.m.n_meas * 8 * 2 * 3 <= dm.lds_max) ? 2 : 1;
+  return L;
+}
+
+int validate_launch(const sp_dmodel& dm, const sp_launch& L) {
+  if (L.waves_per_group < 1 || L.waves_per_group > 16) return set_error(SP_E_INVALID, "waves_per_group must be 1..16");
+  if (!kernel_for(dm.path, L.words_per_group)) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
+  if ((size_t)dm.m.n_meas * 8 * L.words_per_group > dm.lds_max)
+    return set_error(SP_E_LIMIT, "words_per_group slabs exceed the LDS of one workgroup");
+  return SP_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -272,8 +399,10 @@ int sp_model_device_bytes(const sp_model* model, int path, size_t* bytes) {
   if (!model || !bytes) return set_error(SP_E_INVALID, "null argument");
   if (path < SP_PATH_AUTO || path > SP_PATH_DENSE) return set_error(SP_E_INVALID, "unknown path");
   try {
-    Blocks B = build_blocks(*model);
-    *bytes = plan(*model, choose_path(*model, path), (uint32_t)B.ctr.size()).total;
+    HostBlocks H = build_blocks(*model);
+    *bytes = plan(*model, choose_path(*model, path), H).total;
+  } catch (const sp::Error& e) {
+    return set_error(e.code, e.what());
   } catch (const std::bad_alloc&) {
     return set_error(SP_E_NOMEM, "out of host memory");
   }
@@ -298,24 +427,20 @@ int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_byt
   std::vector<uint8_t> host;
   Layout L;
   try {
-    Blocks B = build_blocks(*model);
-    L = plan(*model, p, (uint32_t)B.ctr.size());
+    HostBlocks H = build_blocks(*model);
+    L = plan(*model, p, H);
     if (buf_bytes < L.total)
       return set_error(SP_E_INVALID, "device buffer of " + std::to_string(buf_bytes) + " bytes, need " +
                                          std::to_string(L.total));
     host.assign(L.total, 0);
-    if (!B.ctr.empty()) {
-      std::memcpy(&host[L.blk_ctr], B.ctr.data(), 4 * B.ctr.size());
-      std::memcpy(&host[L.slots], B.slots.data(), 4 * B.slots.size());
-    }
+    if (!H.words.empty()) std::memcpy(&host[L.blocks], H.words.data(), 4 * H.words.size());
+    if (!H.entries.empty()) std::memcpy(&host[L.entries], H.entries.data(), 4 * H.entries.size());
     for (uint32_t c = 0; c < L.nch; ++c) {
       uint32_t* t = reinterpret_cast<uint32_t*>(&host[L.chans + 64 * (size_t)c]);
       const sp::Channel& ch = model->channels[c];
       t[0] = ch.kind;
       for (uint32_t k = 1; k < 16; ++k) t[k] = (uint32_t)std::min<uint64_t>(ch.T[k], 0xFFFFFFFFull);
     }
-    std::memcpy(&host[L.col_ptr], model->col_ptr.data(), 4 * model->col_ptr.size());
-    if (!model->row_idx.empty()) std::memcpy(&host[L.row_idx], model->row_idx.data(), 4 * model->row_idx.size());
     std::memcpy(&host[L.c_mask], model->c_bits.data(), 8 * L.dense_words);
     if (p == SP_PATH_DENSE) {
       uint64_t* d = reinterpret_cast<uint64_t*>(&host[L.dense]);
@@ -325,6 +450,8 @@ int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_byt
           d[(size_t)j * L.dense_words + (k >> 6)] |= 1ull << (k & 63);
         }
     }
+  } catch (const sp::Error& e) {
+    return set_error(e.code, e.what());
   } catch (const std::bad_alloc&) {
     return set_error(SP_E_NOMEM, "out of host memory");
   }
@@ -335,11 +462,9 @@ int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_byt
   auto* dm = new (std::nothrow) sp_dmodel();
   if (!dm) return set_error(SP_E_NOMEM, "out of host memory");
   const uint8_t* base = (const uint8_t*)d_buf;
-  dm->m.blk_ctr = (const uint32_t*)(base + L.blk_ctr);
-  dm->m.slots = (const uint4*)(base + L.slots);
+  dm->m.blocks = (const uint4*)(base + L.blocks);
+  dm->m.entries = (const uint32_t*)(base + L.entries);
   dm->m.chans = (const uint32_t*)(base + L.chans);
-  dm->m.col_ptr = (const uint32_t*)(base + L.col_ptr);
-  dm->m.row_idx = (const uint32_t*)(base + L.row_idx);
   dm->m.c_mask = (const uint64_t*)(base + L.c_mask);
   dm->m.dense = p == SP_PATH_DENSE ? (const uint64_t*)(base + L.dense) : nullptr;
   dm->m.nb = L.nb;
@@ -347,7 +472,9 @@ int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_byt
   dm->m.dense_words = L.dense_words;
   dm->path = p;
   dm->device = dev;
+  dm->lds_max = (size_t)lds_max;
   sp_model_dims(model, &dm->dims);
+  dm->launch = default_launch(*dm);
   *out = dm;
   return SP_OK;
 }
@@ -357,6 +484,21 @@ void sp_dmodel_free(sp_dmodel* dm) { delete dm; }
 int sp_dmodel_dims(const sp_dmodel* dm, sp_dims* out) {
   if (!dm || !out) return set_error(SP_E_INVALID, "null argument");
   *out = dm->dims;
+  return SP_OK;
+}
+
+int sp_dmodel_get_launch(const sp_dmodel* dm, sp_launch* out) {
+  if (!dm || !out) return set_error(SP_E_INVALID, "null argument");
+  *out = dm->launch;
+  return SP_OK;
+}
+
+int sp_dmodel_set_launch(sp_dmodel* dm, const sp_launch* launch) {
+  if (!dm) return set_error(SP_E_INVALID, "null model");
+  const sp_launch L = launch ? *launch : default_launch(*dm);
+  int rc = validate_launch(*dm, L);
+  if (rc) return rc;
+  dm->launch = L;
   return SP_OK;
 }
 
@@ -373,6 +515,7 @@ int sp_sample(const sp_dmodel* dm, uint64_t seed, uint64_t first_shot, uint64_t 
   int dev = -1;
   HIP_TRY(hipGetDevice(&dev));
   if (dev != dm->device) return set_error(SP_E_INVALID, "current device differs from the model's device");
+  const sp_launch& L = dm->launch;
 
   LaunchArgs a;
   a.m = dm->m;
@@ -383,17 +526,11 @@ int sp_sample(const sp_dmodel* dm, uint64_t seed, uint64_t first_shot, uint64_t 
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
   a.n_words = (uint32_t)words;
-  const size_t lds = (size_t)dm->m.n_meas * 8;
-  const unsigned threads = 512;
-  hipStream_t s = (hipStream_t)stream;
-  static std::once_flag once[2];
-  if (dm->path == SP_PATH_DENSE) {
-    std::call_once(once[1], [] { (void)hipFuncSetAttribute((const void*)sample_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); });
-    hipLaunchKernelGGL(sample_kernel<1>, dim3((unsigned)words), dim3(threads), lds, s, a);
-  } else {
-    std::call_once(once[0], [] { (void)hipFuncSetAttribute((const void*)sample_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); });
-    hipLaunchKernelGGL(sample_kernel<0>, dim3((unsigned)words), dim3(threads), lds, s, a);
-  }
+  a.n_groups = (uint32_t)((words + L.words_per_group - 1) / L.words_per_group);
+  const size_t lds = (size_t)dm->m.n_meas * 8 * L.words_per_group;
+  KernelFn k = kernel_for(dm->path, L.words_per_group);
+  if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k, dim3(a.n_groups), dim3(64 * L.waves_per_group), lds, (hipStream_t)stream, a);
   HIP_TRY(hipGetLastError());
   return SP_OK;
 }

@@ -126,8 +126,22 @@ def test_surface_d15_last_partial_batch_sampled():
     want = oc.sample_shots(0, first + idx)
     for i, s in enumerate(idx):
         assert np.array_equal(_column(got, int(s)), want[i]), int(s)
+    assert shots % 64 == 0 and got.shape[1] == shots // 64
+
+
+def test_surface_d7_ragged_batch():
+    """A batch whose size is not a multiple of 64: the bits past the last
+    shot are 0 and the live ones equal the oracle."""
+    text = surface_memory(7, 7, "0.002").text()
+    _, dm, oc = _models(text)
+    shots = 100_003
+    got = _gpu(dm, shots, seed=6, first_shot=5)
     rem = shots % 64
-    assert rem and (got[:, -1] >> np.uint64(rem) == 0).all()
+    assert (got[:, -1] >> np.uint64(rem) == 0).all()
+    idx = np.array([0, 1, shots - 1, shots - rem, shots - rem - 1, 77_777])
+    want = oc.sample_shots(6, 5 + idx)
+    for i, s in enumerate(idx):
+        assert np.array_equal(_column(got, int(s)), want[i]), int(s)
 
 
 # ------------------------------------------------------------- invariants --
@@ -225,3 +239,27 @@ def test_fault_frequencies_match_channel_laws():
         for r in rows:
             z = abs(ones[r] - N * q) / math.sqrt(N * q * (1 - q))
             assert z < 5, (r, ones[r], N * q)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (4, 1), (8, 2), (16, 4), (3, 2), (16, 1)])
+def test_launch_shape_invariance(shape):
+    """The output depends only on (model, seed, first_shot, shots), never on
+    the launch shape (waves per group, words per group)."""
+    text = surface_memory(5, 3, "0.01").text()
+    m, dm, oc = _models(text)
+    ref = oc.sample(seed=12, first_shot=70, shots=5000)
+    old = dm.launch
+    try:
+        dm.launch = shape
+        got = _gpu(dm, 5000, seed=12, first_shot=70)
+    finally:
+        dm.launch = old
+    assert np.array_equal(got, ref)
+
+
+def test_launch_shape_rejects_oversized_slabs():
+    m, dm, _ = _models(surface_memory(15, 15, "0.001").text())
+    with pytest.raises(sp.SymphaseError):
+        dm.launch = (8, 8)       # words_per_group must be 1, 2 or 4
+    with pytest.raises(sp.SymphaseError):
+        dm.launch = (0, 1)
