@@ -166,6 +166,59 @@ typedef struct {
 int sp_dmodel_get_launch(const sp_dmodel* dmodel, sp_launch* out);
 int sp_dmodel_set_launch(sp_dmodel* dmodel, const sp_launch* launch);
 
+/* ---- many circuits per launch (multi-circuit scheduling) ------------------ */
+
+/* One sampling job: the same arguments as sp_sample. */
+typedef struct {
+  const sp_dmodel* model;
+  uint64_t seed;
+  uint64_t first_shot;
+  uint64_t shots;
+  uint64_t* d_out;
+  size_t ld_words;
+} sp_batch_item;
+
+typedef struct sp_batch sp_batch;
+typedef struct sp_graph sp_graph;
+
+/* How a batched launch distributes word groups over workgroups. */
+enum {
+  SP_SCHED_PERSISTENT = 0, /* a device-filling grid; workgroups take tasks (runs of groups of one job)
+                              from a device counter until none is left */
+  SP_SCHED_FLAT = 1        /* one workgroup per group; the hardware dispatcher hands them out */
+};
+
+/* Device work memory (job table, task list or group-to-job map, counters)
+ * for a batch of these items with the given launch shape (NULL = default)
+ * and schedule.  Items with zero shots are dropped. */
+int sp_batch_work_bytes(const sp_batch_item* items, size_t n, const sp_launch* launch, int schedule, size_t* bytes);
+
+/* Builds a batch: every item's output is exactly what sp_sample would write
+ * for it, and all items of one evaluation path are sampled by a single
+ * launch (a batch mixing sparse- and dense-path models issues two).  Jobs
+ * are ordered heaviest first.  d_work: caller's device buffer (>= work_bytes,
+ * 256-byte aligned), written here on `stream` (synchronously with respect to
+ * the host) and owned by the batch until sp_batch_free.  The models and
+ * outputs must outlive the batch.  Errors: SP_E_INVALID, SP_E_LIMIT,
+ * SP_E_DEVICE. */
+int sp_batch_create(const sp_batch_item* items, size_t n, const sp_launch* launch, int schedule, void* d_work,
+                    size_t work_bytes, void* stream, sp_batch** out);
+/* Jobs kept, total word groups, persistent grid size, launch shape. */
+int sp_batch_info(const sp_batch* batch, uint32_t* n_jobs, uint32_t* total_groups, uint32_t* grid, sp_launch* launch);
+/* Queues the batched launch on `stream`.  The kernel resets its own work
+ * counters, so a batch may be launched any number of times and replayed from
+ * a captured graph; launches of one batch must not overlap in time. */
+int sp_batch_launch(const sp_batch* batch, void* stream);
+void sp_batch_free(sp_batch* batch);
+
+/* Captured launch sequences (HIP graphs).  capture_batch records one
+ * sp_batch_launch; capture_plain records one sp_sample per item, in order.
+ * Capture happens on a private stream; sp_graph_launch replays on `stream`. */
+int sp_graph_capture_batch(const sp_batch* batch, sp_graph** out);
+int sp_graph_capture_plain(const sp_batch_item* items, size_t n, sp_graph** out);
+int sp_graph_launch(const sp_graph* graph, void* stream);
+void sp_graph_free(sp_graph* graph);
+
 const char* sp_last_error(void);
 
 #ifdef __cplusplus

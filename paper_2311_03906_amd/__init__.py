@@ -20,9 +20,12 @@ from ._capi import (  # noqa: F401
     SP_PATH_AUTO,
     SP_PATH_DENSE,
     SP_PATH_SPARSE,
+    SP_SCHED_FLAT,
+    SP_SCHED_PERSISTENT,
     SymphaseError,
     check,
     lib,
+    sp_batch_item,
     sp_dims,
     sp_launch,
 )
@@ -174,6 +177,98 @@ class DeviceModel:
             check(lib().sp_sample(self._h, seed, first_shot, shots, ctypes.c_void_p(out.data_ptr()), ld,
                                   ctypes.c_void_p(_stream_handle(stream))))
         return out
+
+
+class Job:
+    """One sampling job of a batch: the arguments of DeviceModel.sample."""
+
+    def __init__(self, model: DeviceModel, shots: int, seed: int = 0, first_shot: int = 0,
+                 out: torch.Tensor | None = None):
+        self.model, self.shots, self.seed, self.first_shot = model, shots, seed, first_shot
+        words = max((shots + 63) // 64, 1)
+        if out is None:
+            out = torch.empty((max(model.n_meas, 1), words), dtype=torch.int64, device=model.device)
+        if out.dtype != torch.int64 or out.stride(1) != 1 or out.shape[0] < model.n_meas or out.shape[1] < (shots + 63) // 64:
+            raise SymphaseError(-1, "job output must be a row-contiguous int64 (n_meas, >= words) tensor")
+        self.out = out
+
+    def item(self) -> sp_batch_item:
+        return sp_batch_item(self.model.handle.value, self.seed, self.first_shot, self.shots,
+                             self.out.data_ptr(), self.out.stride(0))
+
+
+def _items(jobs):
+    arr = (sp_batch_item * max(len(jobs), 1))()
+    for i, j in enumerate(jobs):
+        arr[i] = j.item()
+    return arr
+
+
+class Batch:
+    """Many jobs in one persistent launch (sp_batch_create / sp_batch_launch)."""
+
+    def __init__(self, jobs: list, launch=None, schedule: str = "persistent", stream=None):
+        self.jobs = list(jobs)
+        items = _items(self.jobs)
+        L = None if launch is None else ctypes.byref(sp_launch(int(launch[0]), int(launch[1])))
+        sched = {"persistent": SP_SCHED_PERSISTENT, "flat": SP_SCHED_FLAT}[schedule]
+        self.schedule = schedule
+        n = ctypes.c_size_t()
+        check(lib().sp_batch_work_bytes(items, len(self.jobs), L, sched, ctypes.byref(n)))
+        dev = self.jobs[0].model.device if self.jobs else torch.device("cuda", torch.cuda.current_device())
+        self.work = torch.empty(n.value + 256, dtype=torch.uint8, device=dev)
+        base = self.work.data_ptr()
+        off = (-base) % 256
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            check(lib().sp_batch_create(items, len(self.jobs), L, sched, ctypes.c_void_p(base + off), n.value,
+                                        ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))
+        self._h = h
+        self.device = dev
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        nj, tg, gr, L = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), sp_launch()
+        check(lib().sp_batch_info(self._h, ctypes.byref(nj), ctypes.byref(tg), ctypes.byref(gr), ctypes.byref(L)))
+        return {"jobs": nj.value, "groups": tg.value, "grid": gr.value,
+                "launch": (L.waves_per_group, L.words_per_group)}
+
+    def launch(self, stream=None):
+        with torch.cuda.device(self.device):
+            check(lib().sp_batch_launch(self._h, ctypes.c_void_p(_stream_handle(stream))))
+
+    def __del__(self, _rel=_release):
+        _rel(self, "sp_batch_free")
+
+
+class Graph:
+    """A captured launch sequence (sp_graph_capture_batch / _plain)."""
+
+    def __init__(self, handle, keep):
+        self._h, self._keep = handle, keep
+
+    @classmethod
+    def capture_batch(cls, batch: Batch) -> "Graph":
+        h = ctypes.c_void_p()
+        with torch.cuda.device(batch.device):
+            check(lib().sp_graph_capture_batch(batch.handle, ctypes.byref(h)))
+        return cls(h, batch)
+
+    @classmethod
+    def capture_plain(cls, jobs: list) -> "Graph":
+        items = _items(jobs)
+        h = ctypes.c_void_p()
+        check(lib().sp_graph_capture_plain(items, len(jobs), ctypes.byref(h)))
+        return cls(h, list(jobs))
+
+    def launch(self, stream=None):
+        check(lib().sp_graph_launch(self._h, ctypes.c_void_p(_stream_handle(stream))))
+
+    def __del__(self, _rel=_release):
+        _rel(self, "sp_graph_free")
 
 
 def sample(dmodel: DeviceModel, shots: int, seed: int = 0, first_shot: int = 0, **kw) -> torch.Tensor:

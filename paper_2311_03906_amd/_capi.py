@@ -15,13 +15,15 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsymphase
 SP_OK = 0
 SP_E_INVALID, SP_E_PARSE, SP_E_UNSUPPORTED, SP_E_NOMEM, SP_E_DEVICE, SP_E_LIMIT = -1, -2, -3, -4, -5, -6
 SP_PATH_AUTO, SP_PATH_SPARSE, SP_PATH_DENSE = 0, 1, 2
+SP_SCHED_PERSISTENT, SP_SCHED_FLAT = 0, 1
 
 #: every function the header declares (checked by the tests)
 EXPORTS = (
     "sp_circuit_parse", "sp_circuit_free", "sp_symbolize", "sp_model_free", "sp_model_dims",
     "sp_model_export_dense", "sp_model_export_csc", "sp_model_export_vars", "sp_model_device_bytes",
     "sp_model_upload", "sp_dmodel_free", "sp_dmodel_dims", "sp_dmodel_get_launch", "sp_dmodel_set_launch",
-    "sp_sample", "sp_last_error",
+    "sp_sample", "sp_batch_work_bytes", "sp_batch_create", "sp_batch_info", "sp_batch_launch", "sp_batch_free",
+    "sp_graph_capture_batch", "sp_graph_capture_plain", "sp_graph_launch", "sp_graph_free", "sp_last_error",
 )
 
 
@@ -33,6 +35,11 @@ class sp_dims(ctypes.Structure):
 
 class sp_launch(ctypes.Structure):
     _fields_ = [("waves_per_group", ctypes.c_uint32), ("words_per_group", ctypes.c_uint32)]
+
+
+class sp_batch_item(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("first_shot", ctypes.c_uint64),
+                ("shots", ctypes.c_uint64), ("d_out", ctypes.c_void_p), ("ld_words", ctypes.c_size_t)]
 
 
 class SymphaseError(RuntimeError):
@@ -69,6 +76,15 @@ def lib():
         "sp_dmodel_get_launch": ([vp, P(sp_launch)], ctypes.c_int),
         "sp_dmodel_set_launch": ([vp, P(sp_launch)], ctypes.c_int),
         "sp_sample": ([vp, u64, u64, u64, vp, sz, vp], ctypes.c_int),
+        "sp_batch_work_bytes": ([vp, sz, vp, ctypes.c_int, P(sz)], ctypes.c_int),
+        "sp_batch_create": ([vp, sz, vp, ctypes.c_int, vp, sz, vp, P(vp)], ctypes.c_int),
+        "sp_batch_info": ([vp, P(u32), P(u32), P(u32), P(sp_launch)], ctypes.c_int),
+        "sp_batch_launch": ([vp, vp], ctypes.c_int),
+        "sp_batch_free": ([vp], None),
+        "sp_graph_capture_batch": ([vp, P(vp)], ctypes.c_int),
+        "sp_graph_capture_plain": ([vp, sz, P(vp)], ctypes.c_int),
+        "sp_graph_launch": ([vp, vp], ctypes.c_int),
+        "sp_graph_free": ([vp], None),
         "sp_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():

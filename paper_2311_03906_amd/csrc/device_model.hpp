@@ -1,0 +1,79 @@
+// Device-side model and launch descriptors shared by the sampling kernels
+// and the host code that builds and launches them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sp_internal.hpp"
+
+namespace sp {
+
+// Device model: every section lives in the caller's buffer.
+struct DevModel {
+  const uint4* blocks;       // [nb][4]: tm1[4] | meta[4] | lst[0..3] | (lst[4], blk, 0, 0)
+  const uint32_t* entries;   // merged (row << 2 | bit) lists, one per drawn location
+  const uint32_t* chans;     // [nch][16]: kind, T_1..T_15
+  const uint64_t* c_mask;    // [ceil(n_meas/64)]
+  const uint64_t* dense;     // [n_vars][dense_words] (dense path only)
+  uint32_t nb, n_meas, dense_words;
+};
+
+// One sampling job: a model, an output and a shot range.
+struct LaunchArgs {
+  DevModel m;
+  uint64_t* out;
+  uint64_t ld;
+  uint64_t first_shot;
+  uint64_t shots;
+  uint32_t key0, key1;
+  uint32_t n_words, n_groups;
+};
+
+// A job inside a batched launch (device memory).
+struct BatchJob {
+  LaunchArgs a;
+  uint32_t group_base;   // global index of the job's first group
+  uint32_t pad[3];
+};
+
+// A unit of hand-out in the persistent schedule: `count` consecutive groups
+// of one job, starting at its local group `first`.
+struct BatchTask {
+  uint32_t job, first, count, pad;
+};
+
+// Work counters of a batched launch: `next` hands out groups, `done` counts
+// workgroups that found no more work; the last one resets both.
+struct BatchCounters {
+  uint32_t next;
+  uint32_t done;
+  uint32_t pad[62];
+};
+
+int set_error(int code, const std::string& msg);
+
+// Kernel launchers (sample.hip).
+int launch_sample(const LaunchArgs& a, int path, const sp_launch& L, hipStream_t s);
+// Persistent schedule: `grid` workgroups take tasks from ctr until none is left.
+int launch_batch_persistent(const BatchJob* jobs, const BatchTask* tasks, uint32_t n_tasks, BatchCounters* ctr,
+                            uint32_t n_meas_max, int path, const sp_launch& L, uint32_t grid, hipStream_t s);
+// Flat schedule: one workgroup per group, group_job[g] names its job.
+int launch_batch_flat(const BatchJob* jobs, const uint32_t* group_job, uint32_t total_groups, uint32_t n_meas_max,
+                      int path, const sp_launch& L, hipStream_t s);
+// Workgroups of the persistent kernel that fit on the device at once.
+int batch_grid(const sp_launch& L, uint32_t n_meas_max, int path, uint32_t* grid);
+
+}  // namespace sp
+
+struct sp_dmodel {
+  sp::DevModel m;
+  int path;
+  int device;
+  size_t lds_max;
+  sp_launch launch;
+  sp_dims dims;
+};

@@ -30,12 +30,13 @@
 #include <string>
 #include <vector>
 
-#include "sp_internal.hpp"
+#include "device_model.hpp"
 
-namespace sp {
-int set_error(int code, const std::string& msg);
-}
 using sp::set_error;
+using sp::DevModel;
+using sp::LaunchArgs;
+using sp::BatchJob;
+using sp::BatchCounters;
 
 namespace {
 
@@ -43,26 +44,6 @@ constexpr uint32_t kM0 = 0xD2511F53u;   // Philox4x32 round multipliers
 constexpr uint32_t kM1 = 0xCD9E8D57u;
 constexpr uint32_t kW0 = 0x9E3779B9u;   // Philox key increments
 constexpr uint32_t kW1 = 0xBB67AE85u;
-
-// Device model: every section lives in the caller's buffer.
-struct DevModel {
-  const uint4* blocks;       // [nb][4]: tm1[4] | meta[4] | lst[0..3] | (lst[4], blk, 0, 0)
-  const uint32_t* entries;   // merged (row << 2 | bit) lists, one per drawn location
-  const uint32_t* chans;     // [nch][16]: kind, T_1..T_15
-  const uint64_t* c_mask;    // [ceil(n_meas/64)]
-  const uint64_t* dense;     // [n_vars][dense_words] (dense path only)
-  uint32_t nb, n_meas, dense_words;
-};
-
-struct LaunchArgs {
-  DevModel m;
-  uint64_t* out;
-  uint64_t ld;
-  uint64_t first_shot;
-  uint64_t shots;
-  uint32_t key0, key1;
-  uint32_t n_words, n_groups;
-};
 
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1) {
@@ -232,16 +213,12 @@ __device__ __forceinline__ uint32_t xcd_group(uint32_t b, uint32_t n) {
   return x * q + min(x, r) + i;
 }
 
-// One workgroup = R consecutive 64-shot words, each with its LDS slab of
-// n_meas rows.
+// One group = R consecutive 64-shot words of one job, each with its LDS
+// slab of n_meas rows: initialise from c, draw and evaluate, store.
 template <int R, int DENSE>
-__global__ void __launch_bounds__(1024) sample_kernel(LaunchArgs a) {
-  extern __shared__ uint64_t slab[];
+__device__ __forceinline__ void process_group(const LaunchArgs& a, uint64_t* slab, uint32_t g, uint32_t tid,
+                                              uint32_t lane, uint32_t wave, uint32_t n_waves) {
   const DevModel& m = a.m;
-  const uint32_t tid = threadIdx.x, lane = tid & 63u;
-  const uint32_t wave = uniform(tid >> 6), n_waves = blockDim.x >> 6;
-  const uint32_t g = xcd_group(blockIdx.x, a.n_groups);
-
   for (uint32_t k = tid; k < m.n_meas; k += blockDim.x) {
     const uint64_t v = ((m.c_mask[k >> 6] >> (k & 63u)) & 1ull) ? ~0ull : 0ull;
 #pragma unroll
@@ -265,6 +242,68 @@ __global__ void __launch_bounds__(1024) sample_kernel(LaunchArgs a) {
     uint64_t* col = a.out + w;
     for (uint32_t k = tid; k < m.n_meas; k += blockDim.x) col[(size_t)k * a.ld] = slab[(size_t)r * m.n_meas + k] & valid;
   }
+}
+
+// One job per launch: workgroup b owns group xcd_group(b).
+template <int R, int DENSE>
+__global__ void __launch_bounds__(1024) sample_kernel(LaunchArgs a) {
+  extern __shared__ uint64_t slab[];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  const uint32_t wave = uniform(tid >> 6), n_waves = blockDim.x >> 6;
+  process_group<R, DENSE>(a, slab, xcd_group(blockIdx.x, a.n_groups), tid, lane, wave, n_waves);
+}
+
+// Many jobs per launch, persistent schedule: workgroups take tasks (runs of
+// consecutive groups of one job) from a device counter until all are handed
+// out.  The workgroup that finishes last resets the counters, so the launch
+// can be replayed (for example from a captured graph) without any host-side
+// reset.
+template <int R, int DENSE>
+__global__ void __launch_bounds__(1024) batch_persistent_kernel(const BatchJob* __restrict__ jobs,
+                                                                const sp::BatchTask* __restrict__ tasks,
+                                                                uint32_t n_tasks, BatchCounters* ctr) {
+  extern __shared__ uint64_t slab[];
+  __shared__ uint32_t s_next;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  const uint32_t wave = uniform(tid >> 6), n_waves = blockDim.x >> 6;
+  if (tid == 0) s_next = atomicAdd(&ctr->next, 1u);
+  __syncthreads();
+  uint32_t t = uniform(s_next);
+  while (t < n_tasks) {
+    uint32_t nxt = 0;
+    if (tid == 0) nxt = atomicAdd(&ctr->next, 1u);   // next task, in flight during this one
+    const sp::BatchTask task = tasks[t];
+    const BatchJob& job = jobs[task.job];
+    for (uint32_t i = 0; i < task.count; ++i) {
+      process_group<R, DENSE>(job.a, slab, task.first + i, tid, lane, wave, n_waves);
+      __syncthreads();
+    }
+    if (tid == 0) s_next = nxt;
+    __syncthreads();
+    t = uniform(s_next);
+  }
+  if (tid == 0) {
+    __threadfence();
+    if (atomicAdd(&ctr->done, 1u) == gridDim.x - 1u) {
+      atomicExch(&ctr->next, 0u);
+      atomicExch(&ctr->done, 0u);
+      __threadfence();
+    }
+  }
+}
+
+// Many jobs per launch, flat schedule: workgroup b owns global group b (jobs
+// are ordered heaviest first, so the hardware dispatcher hands out the
+// expensive groups first).
+template <int R, int DENSE>
+__global__ void __launch_bounds__(1024) batch_flat_kernel(const BatchJob* __restrict__ jobs,
+                                                          const uint32_t* __restrict__ group_job) {
+  extern __shared__ uint64_t slab[];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  const uint32_t wave = uniform(tid >> 6), n_waves = blockDim.x >> 6;
+  const uint32_t g = blockIdx.x;
+  const BatchJob& job = jobs[group_job[g]];
+  process_group<R, DENSE>(job.a, slab, g - job.group_base, tid, lane, wave, n_waves);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -350,6 +389,8 @@ Layout plan(const sp_model& m, int path, const HostBlocks& H) {
   } while (0)
 
 using KernelFn = void (*)(LaunchArgs);
+using PersistentFn = void (*)(const BatchJob*, const sp::BatchTask*, uint32_t, BatchCounters*);
+using FlatFn = void (*)(const BatchJob*, const uint32_t*);
 
 KernelFn kernel_for(int path, uint32_t words_per_group) {
   const bool dense = path == SP_PATH_DENSE;
@@ -361,16 +402,77 @@ KernelFn kernel_for(int path, uint32_t words_per_group) {
   }
 }
 
+PersistentFn persistent_for(int path, uint32_t words_per_group) {
+  const bool dense = path == SP_PATH_DENSE;
+  switch (words_per_group) {
+    case 1: return dense ? batch_persistent_kernel<1, 1> : batch_persistent_kernel<1, 0>;
+    case 2: return dense ? batch_persistent_kernel<2, 1> : batch_persistent_kernel<2, 0>;
+    case 4: return dense ? batch_persistent_kernel<4, 1> : batch_persistent_kernel<4, 0>;
+    default: return nullptr;
+  }
+}
+
+FlatFn flat_for(int path, uint32_t words_per_group) {
+  const bool dense = path == SP_PATH_DENSE;
+  switch (words_per_group) {
+    case 1: return dense ? batch_flat_kernel<1, 1> : batch_flat_kernel<1, 0>;
+    case 2: return dense ? batch_flat_kernel<2, 1> : batch_flat_kernel<2, 0>;
+    case 4: return dense ? batch_flat_kernel<4, 1> : batch_flat_kernel<4, 0>;
+    default: return nullptr;
+  }
+}
+
 }  // namespace
 
-struct sp_dmodel {
-  DevModel m;
-  int path;
-  int device;
-  size_t lds_max;
-  sp_launch launch;
-  sp_dims dims;
-};
+namespace sp {
+
+int launch_sample(const LaunchArgs& a, int path, const sp_launch& L, hipStream_t s) {
+  const size_t lds = (size_t)a.m.n_meas * 8 * L.words_per_group;
+  KernelFn k = kernel_for(path, L.words_per_group);
+  if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
+  if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k, dim3(a.n_groups), dim3(64 * L.waves_per_group), lds, s, a);
+  HIP_TRY(hipGetLastError());
+  return SP_OK;
+}
+
+int batch_grid(const sp_launch& L, uint32_t n_meas_max, int path, uint32_t* grid) {
+  PersistentFn k = persistent_for(path, L.words_per_group);
+  if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
+  const size_t lds = (size_t)n_meas_max * 8 * L.words_per_group;
+  if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int dev = 0, cus = 0, per_cu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, 64 * L.waves_per_group, lds));
+  if (per_cu < 1) return set_error(SP_E_LIMIT, "batched kernel does not fit on a CU with this launch shape");
+  *grid = (uint32_t)(cus * per_cu);
+  return SP_OK;
+}
+
+int launch_batch_persistent(const BatchJob* jobs, const BatchTask* tasks, uint32_t n_tasks, BatchCounters* ctr,
+                            uint32_t n_meas_max, int path, const sp_launch& L, uint32_t grid, hipStream_t s) {
+  PersistentFn k = persistent_for(path, L.words_per_group);
+  if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
+  const size_t lds = (size_t)n_meas_max * 8 * L.words_per_group;
+  if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * L.waves_per_group), lds, s, jobs, tasks, n_tasks, ctr);
+  HIP_TRY(hipGetLastError());
+  return SP_OK;
+}
+
+int launch_batch_flat(const BatchJob* jobs, const uint32_t* group_job, uint32_t total_groups, uint32_t n_meas_max,
+                      int path, const sp_launch& L, hipStream_t s) {
+  FlatFn k = flat_for(path, L.words_per_group);
+  if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
+  const size_t lds = (size_t)n_meas_max * 8 * L.words_per_group;
+  if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k, dim3(total_groups), dim3(64 * L.waves_per_group), lds, s, jobs, group_job);
+  HIP_TRY(hipGetLastError());
+  return SP_OK;
+}
+
+}  // namespace sp
 
 namespace {
 
@@ -527,12 +629,7 @@ int sp_sample(const sp_dmodel* dm, uint64_t seed, uint64_t first_shot, uint64_t 
   a.key1 = (uint32_t)(seed >> 32);
   a.n_words = (uint32_t)words;
   a.n_groups = (uint32_t)((words + L.words_per_group - 1) / L.words_per_group);
-  const size_t lds = (size_t)dm->m.n_meas * 8 * L.words_per_group;
-  KernelFn k = kernel_for(dm->path, L.words_per_group);
-  if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k, dim3(a.n_groups), dim3(64 * L.waves_per_group), lds, (hipStream_t)stream, a);
-  HIP_TRY(hipGetLastError());
-  return SP_OK;
+  return sp::launch_sample(a, dm->path, L, (hipStream_t)stream);
 }
 
 }  // extern "C"
