@@ -115,6 +115,12 @@ void sp_model_free(sp_model* model);
 
 int sp_model_dims(const sp_model* model, sp_dims* out);
 
+/* Expected work of one 64-shot word: fired locations (sum over drawn
+ * locations of 1 - (1 - q)^64, q = T_m / 2^32) and the (row, variable)
+ * entries they touch on the sparse path.  Used to size and key launch
+ * tuning; exact arithmetic is not needed here. */
+int sp_model_expected_work(const sp_model* model, double* fired_per_word, double* entries_per_word);
+
 /* Dense export of M and c: M has n_meas rows of row_words uint64 words
  * (row_words >= ceil(n_vars/64)); bit j of row k is M[k][j].  c (nullable):
  * ceil(n_meas/64) words, bit k = constant term of measurement k.  Host memory. */

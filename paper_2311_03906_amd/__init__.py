@@ -88,6 +88,12 @@ class Model:
     def __del__(self, _rel=_release):
         _rel(self, "sp_model_free")
 
+    def expected_work(self) -> tuple:
+        """(fired locations, touched sparse entries) per 64-shot word."""
+        f, e = ctypes.c_double(), ctypes.c_double()
+        check(lib().sp_model_expected_work(self._h, ctypes.byref(f), ctypes.byref(e)))
+        return f.value, e.value
+
     def export_dense(self):
         """(M as a (n_meas, n_vars) uint8 0/1 array, c as a uint8 0/1 vector)."""
         rw = max(1, (self.n_vars + 63) // 64)
@@ -134,6 +140,8 @@ class DeviceModel:
         self._h = h
         self.device = device
         self.n_meas = model.n_meas
+        self.path = path
+        self.expected_work = model.expected_work()
         d = sp_dims()
         check(lib().sp_dmodel_dims(h, ctypes.byref(d)))
         self.dims = d

@@ -20,6 +20,7 @@ SP_SCHED_PERSISTENT, SP_SCHED_FLAT = 0, 1
 #: every function the header declares (checked by the tests)
 EXPORTS = (
     "sp_circuit_parse", "sp_circuit_free", "sp_symbolize", "sp_model_free", "sp_model_dims",
+    "sp_model_expected_work",
     "sp_model_export_dense", "sp_model_export_csc", "sp_model_export_vars", "sp_model_device_bytes",
     "sp_model_upload", "sp_dmodel_free", "sp_dmodel_dims", "sp_dmodel_get_launch", "sp_dmodel_set_launch",
     "sp_sample", "sp_batch_work_bytes", "sp_batch_create", "sp_batch_info", "sp_batch_launch", "sp_batch_free",
@@ -66,6 +67,7 @@ def lib():
         "sp_symbolize": ([vp, P(vp)], ctypes.c_int),
         "sp_model_free": ([vp], None),
         "sp_model_dims": ([vp, P(sp_dims)], ctypes.c_int),
+        "sp_model_expected_work": ([vp, P(ctypes.c_double), P(ctypes.c_double)], ctypes.c_int),
         "sp_model_export_dense": ([vp, vp, sz, vp], ctypes.c_int),
         "sp_model_export_csc": ([vp, vp, vp], ctypes.c_int),
         "sp_model_export_vars": ([vp, vp, vp], ctypes.c_int),

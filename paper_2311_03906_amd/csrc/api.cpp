@@ -1,4 +1,5 @@
 // C ABI entry points for the host-side stages (parse, symbolize, exports).
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -74,6 +75,26 @@ int sp_model_dims(const sp_model* m, sp_dims* d) {
   d->n_draw_blocks = blocks;
   d->reserved = 0;
   d->nnz = m->row_idx.size();
+  return SP_OK;
+}
+
+int sp_model_expected_work(const sp_model* m, double* fired_per_word, double* entries_per_word) {
+  if (!m) return set_error(SP_E_INVALID, "null model");
+  double fired = 0, entries = 0;
+  for (uint32_t l = 0; l < m->n_locs; ++l) {
+    const int32_t ch = m->loc_chan[l];
+    if (ch < 0) continue;
+    const sp::Channel& c = m->channels[ch];
+    const double q = (double)c.T[c.m] / 4294967296.0;
+    if (q <= 0) continue;
+    const double f = 1.0 - std::pow(1.0 - q, 64.0);
+    fired += f;
+    const uint32_t v0 = (uint32_t)m->loc_var0[l];
+    const uint32_t nv = sp::loc_bits(m->loc_kind[l]);
+    entries += f * (double)(m->col_ptr[v0 + nv] - m->col_ptr[v0]);
+  }
+  if (fired_per_word) *fired_per_word = fired;
+  if (entries_per_word) *entries_per_word = entries;
   return SP_OK;
 }
 

@@ -19,7 +19,7 @@ struct DevModel {
   const uint32_t* chans;     // [nch][16]: kind, T_1..T_15
   const uint64_t* c_mask;    // [ceil(n_meas/64)]
   const uint64_t* dense;     // [n_vars][dense_words] (dense path only)
-  uint32_t nb, n_meas, dense_words;
+  uint32_t nb, n_meas, dense_words, nch;
 };
 
 // One sampling job: a model, an output and a shot range.
@@ -56,16 +56,20 @@ struct BatchCounters {
 
 int set_error(int code, const std::string& msg);
 
+// LDS bytes of one workgroup (its slabs).
+size_t lds_bytes(uint32_t n_meas, uint32_t nch, uint32_t words_per_group);
+
 // Kernel launchers (sample.hip).
 int launch_sample(const LaunchArgs& a, int path, const sp_launch& L, hipStream_t s);
 // Persistent schedule: `grid` workgroups take tasks from ctr until none is left.
 int launch_batch_persistent(const BatchJob* jobs, const BatchTask* tasks, uint32_t n_tasks, BatchCounters* ctr,
-                            uint32_t n_meas_max, int path, const sp_launch& L, uint32_t grid, hipStream_t s);
+                            uint32_t n_meas_max, uint32_t nch_max, int path, const sp_launch& L, uint32_t grid,
+                            hipStream_t s);
 // Flat schedule: one workgroup per group, group_job[g] names its job.
 int launch_batch_flat(const BatchJob* jobs, const uint32_t* group_job, uint32_t total_groups, uint32_t n_meas_max,
-                      int path, const sp_launch& L, hipStream_t s);
+                      uint32_t nch_max, int path, const sp_launch& L, hipStream_t s);
 // Workgroups of the persistent kernel that fit on the device at once.
-int batch_grid(const sp_launch& L, uint32_t n_meas_max, int path, uint32_t* grid);
+int batch_grid(const sp_launch& L, uint32_t n_meas_max, uint32_t nch_max, int path, uint32_t* grid);
 
 }  // namespace sp
 

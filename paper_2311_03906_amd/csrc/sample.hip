@@ -45,22 +45,43 @@ constexpr uint32_t kM1 = 0xCD9E8D57u;
 constexpr uint32_t kW0 = 0x9E3779B9u;   // Philox key increments
 constexpr uint32_t kW1 = 0xBB67AE85u;
 
-__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                               uint32_t k0, uint32_t k1) {
+// Round keys of Philox4x32-10 for one seed: round r uses (key0 + r*W0,
+// key1 + r*W1).  They are wave-uniform and stay in SGPRs: each round's
+// three-input XOR then reads two VGPRs and one SGPR.
+struct RoundKeys {
+  uint32_t k0[10], k1[10];
+};
+
+__device__ __forceinline__ RoundKeys round_keys(uint32_t key0, uint32_t key1) {
+  RoundKeys k;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint64_t p0 = (uint64_t)kM0 * c0;
-    const uint64_t p1 = (uint64_t)kM1 * c2;
-    // three-input XOR in one v_bitop3_b32 (truth table 0x96 = a ^ b ^ c)
-    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
-    const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
-    c1 = (uint32_t)p1;
-    c3 = (uint32_t)p0;
-    c0 = n0;
-    c2 = n2;
-    k0 += kW0;
-    k1 += kW1;
+    k.k0[r] = key0 + (uint32_t)r * kW0;
+    k.k1[r] = key1 + (uint32_t)r * kW1;
   }
+  return k;
+}
+
+__device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0,
+                                             uint32_t k1) {
+  const uint64_t p0 = (uint64_t)kM0 * c0;
+  const uint64_t p1 = (uint64_t)kM1 * c2;
+  // three-input XOR in one v_bitop3_b32 (truth table 0x96 = a ^ b ^ c)
+  const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+  const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
+  c1 = (uint32_t)p1;
+  c3 = (uint32_t)p0;
+  c0 = n0;
+  c2 = n2;
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
+// products on words 0 and 2, then (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0);
+// the key advances by (W0, W1) between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               const RoundKeys& k) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) philox_round(c0, c1, c2, c3, k.k0[r], k.k1[r]);
   return make_uint4(c0, c1, c2, c3);
 }
 
@@ -79,17 +100,20 @@ __device__ __forceinline__ uint32_t pick(const uint4& v, int s) {
 // included, code m+1 read as 0) is therefore bit i of the lane's code.
 struct Masks {
   uint64_t b0, b1, b2, b3;   // 64-lane masks of code bits 0..3
+  uint32_t nbits;            // code bits of the channel: 1, 2 or 4
 };
 
-__device__ __forceinline__ Masks decode(const DevModel& m, uint32_t meta, uint32_t u, uint64_t fire) {
-  const uint32_t* T = m.chans + ((meta & 0xFFu) - 1u) * 16u;
+__device__ __forceinline__ Masks decode(const uint32_t* chans, uint32_t meta, uint32_t u, uint64_t fire) {
+  const uint32_t* T = chans + ((meta & 0xFFu) - 1u) * 16u;   // uniform address: scalar loads, no VALU
   const uint32_t kind = T[0];
-  Masks r{fire, 0ull, 0ull, 0ull};   // X/Y/Z errors and the random-measurement coin
+  Masks r{fire, 0ull, 0ull, 0ull, 1u};   // X/Y/Z errors and the random-measurement coin
   if (kind == sp::CH_DEP1) {
+    r.nbits = 2;
     const uint64_t m1 = ballot(u < T[1]), m2 = ballot(u < T[2]);
     r.b0 = m1 ^ m2 ^ fire;   // X part: codes 1 (X) and 3 (Y)
     r.b1 = m1 ^ fire;        // Z part: codes 2 (Z) and 3 (Y)
   } else if (kind == sp::CH_DEP2) {
+    r.nbits = 4;
     uint64_t mk[16];
 #pragma unroll
     for (int k = 1; k < 15; ++k) mk[k] = ballot(u < T[k]);
@@ -118,24 +142,45 @@ __device__ __forceinline__ void xor_dense(const DevModel& m, uint64_t* slab, uin
   }
 }
 
-template <int DENSE>
-__device__ __forceinline__ void evaluate(const DevModel& m, uint64_t* slab, uint32_t meta, uint32_t lo, uint32_t hi,
-                                         const Masks& k, uint32_t lane) {
-  if (DENSE) {
-    const uint32_t var0 = meta >> 8;
-    if (k.b0) xor_dense(m, slab, var0, k.b0, lane);
-    if (k.b1) xor_dense(m, slab, var0 + 1, k.b1, lane);
-    if (k.b2) xor_dense(m, slab, var0 + 2, k.b2, lane);
-    if (k.b3) xor_dense(m, slab, var0 + 3, k.b3, lane);
-  } else {
-    for (uint32_t i = lo + lane; i < hi; i += 64) {
-      const uint32_t e = m.entries[i];
-      const uint64_t lo_pair = (e & 1u) ? k.b1 : k.b0;
-      const uint64_t hi_pair = (e & 1u) ? k.b3 : k.b2;
-      const uint64_t s = (e & 2u) ? hi_pair : lo_pair;
-      if (s) atomicXor((unsigned long long*)&slab[e >> 2], (unsigned long long)s);
-    }
+constexpr uint32_t kNoEntry = 0xFFFFFFFFu;
+
+// Mask of the code bit named by entry e (low two bits) among the first NB.
+// Written as masked XORs rather than selects: the uniform masks stay scalar
+// operands and no lookup table is formed.
+template <int NB>
+__device__ __forceinline__ uint64_t select_mask(uint32_t e, const Masks& k) {
+  if (NB == 1) return k.b0;
+  const uint64_t m0 = (uint64_t)(int64_t)(int32_t)(0u - (e & 1u));          // all ones when bit 0 of e is set
+  const uint64_t lo = k.b0 ^ ((k.b0 ^ k.b1) & m0);
+  if (NB == 2) return lo;
+  const uint64_t hi = k.b2 ^ ((k.b2 ^ k.b3) & m0);
+  const uint64_t m1 = (uint64_t)(int64_t)(int32_t)(0u - ((e >> 1) & 1u));   // bit 1 of e
+  return lo ^ ((lo ^ hi) & m1);
+}
+
+// Sparse evaluate of a fired location whose list is entries[lo, hi); `first`
+// is this lane's entry lo + lane, already loaded (kNoEntry past the end).
+template <int NB>
+__device__ __forceinline__ void evaluate_sparse(const DevModel& m, uint64_t* slab, uint32_t lo, uint32_t hi,
+                                                uint32_t first, const Masks& k, uint32_t lane) {
+  if (first != kNoEntry) {
+    const uint64_t s = select_mask<NB>(first, k);
+    if (NB == 1 || s) atomicXor((unsigned long long*)&slab[first >> 2], (unsigned long long)s);
   }
+  for (uint32_t i = lo + 64u + lane; i < hi; i += 64) {
+    const uint32_t e = m.entries[i];
+    const uint64_t s = select_mask<NB>(e, k);
+    if (NB == 1 || s) atomicXor((unsigned long long*)&slab[e >> 2], (unsigned long long)s);
+  }
+}
+
+__device__ __forceinline__ void evaluate_dense(const DevModel& m, uint64_t* slab, uint32_t meta, const Masks& k,
+                                               uint32_t lane) {
+  const uint32_t var0 = meta >> 8;
+  if (k.b0) xor_dense(m, slab, var0, k.b0, lane);
+  if (k.b1) xor_dense(m, slab, var0 + 1, k.b1, lane);
+  if (k.b2) xor_dense(m, slab, var0 + 2, k.b2, lane);
+  if (k.b3) xor_dense(m, slab, var0 + 3, k.b3, lane);
 }
 
 // The draw-select-evaluate loop of one wave over its share of the blocks.
@@ -160,6 +205,7 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
   }
   uint32_t b = wave;
   if (b >= m.nb) return;
+  const RoundKeys keys = round_keys(a.key0, a.key1);
   uint4 d0 = m.blocks[4 * b], d1 = m.blocks[4 * b + 1], d2 = m.blocks[4 * b + 2], d3 = m.blocks[4 * b + 3];
   for (;;) {
     const uint32_t bn = b + n_waves;
@@ -172,7 +218,7 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
     }
     uint4 u[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) u[r] = philox4x32_10(d3.y, s_lo[r], s_hi[r], 0u, a.key0, a.key1);
+    for (int r = 0; r < R; ++r) u[r] = philox4x32_10(d3.y, s_lo[r], s_hi[r], 0u, keys);
     uint64_t f[R][4];
     uint64_t any = 0;
 #pragma unroll
@@ -184,15 +230,37 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
       any |= f[r][0] | f[r][1] | f[r][2] | f[r][3];
     }
     if (any) {
+      // Issue the entry loads of every fired location of the block first, so
+      // their latencies overlap, then decode and XOR.  (Measured: the fired
+      // path is bound by its VALU work -- decode compares and one list pass
+      // per fired location -- not by these latencies.)
+      uint32_t first[4] = {kNoEntry, kNoEntry, kNoEntry, kNoEntry};
+      if (!DENSE) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          uint64_t fs = 0;
+#pragma unroll
+          for (int r = 0; r < R; ++r) fs |= f[r][s];
+          const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
+          if (fs && lo + lane < hi) first[s] = m.entries[lo + lane];
+        }
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           if (!f[r][s]) continue;
           const uint32_t meta = pick(d1, s);
-          const Masks k = decode(m, meta, pick(u[r], s), f[r][s]);
-          const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
-          evaluate<DENSE>(m, slab + (size_t)r * m.n_meas, meta, lo, hi, k, lane);
+          const Masks k = decode(m.chans, meta, pick(u[r], s), f[r][s]);
+          uint64_t* sl = slab + (size_t)r * m.n_meas;
+          if (DENSE) {
+            evaluate_dense(m, sl, meta, k, lane);
+          } else {
+            const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
+            if (k.nbits == 1) evaluate_sparse<1>(m, sl, lo, hi, first[s], k, lane);
+            else if (k.nbits == 2) evaluate_sparse<2>(m, sl, lo, hi, first[s], k, lane);
+            else evaluate_sparse<4>(m, sl, lo, hi, first[s], k, lane);
+          }
         }
       }
     }
@@ -426,8 +494,13 @@ FlatFn flat_for(int path, uint32_t words_per_group) {
 
 namespace sp {
 
+size_t lds_bytes(uint32_t n_meas, uint32_t nch, uint32_t words_per_group) {
+  (void)nch;   // the channel table is read through the scalar cache
+  return (size_t)n_meas * 8 * words_per_group;
+}
+
 int launch_sample(const LaunchArgs& a, int path, const sp_launch& L, hipStream_t s) {
-  const size_t lds = (size_t)a.m.n_meas * 8 * L.words_per_group;
+  const size_t lds = lds_bytes(a.m.n_meas, a.m.nch, L.words_per_group);
   KernelFn k = kernel_for(path, L.words_per_group);
   if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
   if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -436,10 +509,10 @@ int launch_sample(const LaunchArgs& a, int path, const sp_launch& L, hipStream_t
   return SP_OK;
 }
 
-int batch_grid(const sp_launch& L, uint32_t n_meas_max, int path, uint32_t* grid) {
+int batch_grid(const sp_launch& L, uint32_t n_meas_max, uint32_t nch_max, int path, uint32_t* grid) {
   PersistentFn k = persistent_for(path, L.words_per_group);
   if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
-  const size_t lds = (size_t)n_meas_max * 8 * L.words_per_group;
+  const size_t lds = lds_bytes(n_meas_max, nch_max, L.words_per_group);
   if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   int dev = 0, cus = 0, per_cu = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -451,10 +524,11 @@ int batch_grid(const sp_launch& L, uint32_t n_meas_max, int path, uint32_t* grid
 }
 
 int launch_batch_persistent(const BatchJob* jobs, const BatchTask* tasks, uint32_t n_tasks, BatchCounters* ctr,
-                            uint32_t n_meas_max, int path, const sp_launch& L, uint32_t grid, hipStream_t s) {
+                            uint32_t n_meas_max, uint32_t nch_max, int path, const sp_launch& L, uint32_t grid,
+                            hipStream_t s) {
   PersistentFn k = persistent_for(path, L.words_per_group);
   if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
-  const size_t lds = (size_t)n_meas_max * 8 * L.words_per_group;
+  const size_t lds = lds_bytes(n_meas_max, nch_max, L.words_per_group);
   if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k, dim3(grid), dim3(64 * L.waves_per_group), lds, s, jobs, tasks, n_tasks, ctr);
   HIP_TRY(hipGetLastError());
@@ -462,10 +536,10 @@ int launch_batch_persistent(const BatchJob* jobs, const BatchTask* tasks, uint32
 }
 
 int launch_batch_flat(const BatchJob* jobs, const uint32_t* group_job, uint32_t total_groups, uint32_t n_meas_max,
-                      int path, const sp_launch& L, hipStream_t s) {
+                      uint32_t nch_max, int path, const sp_launch& L, hipStream_t s) {
   FlatFn k = flat_for(path, L.words_per_group);
   if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
-  const size_t lds = (size_t)n_meas_max * 8 * L.words_per_group;
+  const size_t lds = lds_bytes(n_meas_max, nch_max, L.words_per_group);
   if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k, dim3(total_groups), dim3(64 * L.waves_per_group), lds, s, jobs, group_job);
   HIP_TRY(hipGetLastError());
@@ -481,14 +555,14 @@ namespace {
 sp_launch default_launch(const sp_dmodel& dm) {
   sp_launch L;
   L.waves_per_group = 8;
-  L.words_per_group = ((size_t)dm.m.n_meas * 8 * 2 * 3 <= dm.lds_max) ? 2 : 1;
+  L.words_per_group = (sp::lds_bytes(dm.m.n_meas, dm.m.nch, 2) * 3 <= dm.lds_max) ? 2 : 1;
   return L;
 }
 
 int validate_launch(const sp_dmodel& dm, const sp_launch& L) {
   if (L.waves_per_group < 1 || L.waves_per_group > 16) return set_error(SP_E_INVALID, "waves_per_group must be 1..16");
   if (!kernel_for(dm.path, L.words_per_group)) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
-  if ((size_t)dm.m.n_meas * 8 * L.words_per_group > dm.lds_max)
+  if (sp::lds_bytes(dm.m.n_meas, dm.m.nch, L.words_per_group) > dm.lds_max)
     return set_error(SP_E_LIMIT, "words_per_group slabs exceed the LDS of one workgroup");
   return SP_OK;
 }
@@ -521,10 +595,10 @@ int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_byt
   HIP_TRY(hipGetDevice(&dev));
   int lds_max = 0;
   HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  if ((size_t)model->n_meas * 8 > (size_t)lds_max)
+  if (sp::lds_bytes(model->n_meas, (uint32_t)model->channels.size(), 1) > (size_t)lds_max)
     return set_error(SP_E_LIMIT, "n_meas " + std::to_string(model->n_meas) + " needs " +
-                                     std::to_string((size_t)model->n_meas * 8) + " bytes of LDS; the device allows " +
-                                     std::to_string(lds_max));
+                                     std::to_string(sp::lds_bytes(model->n_meas, (uint32_t)model->channels.size(), 1)) +
+                                     " bytes of LDS; the device allows " + std::to_string(lds_max));
   const int p = choose_path(*model, path);
   std::vector<uint8_t> host;
   Layout L;
@@ -570,6 +644,7 @@ int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_byt
   dm->m.c_mask = (const uint64_t*)(base + L.c_mask);
   dm->m.dense = p == SP_PATH_DENSE ? (const uint64_t*)(base + L.dense) : nullptr;
   dm->m.nb = L.nb;
+  dm->m.nch = L.nch;
   dm->m.n_meas = model->n_meas;
   dm->m.dense_words = L.dense_words;
   dm->path = p;
