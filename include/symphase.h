@@ -75,6 +75,8 @@ extern "C" {
 #define SP_E_NOMEM (-4)       /* host allocation failed */
 #define SP_E_DEVICE (-5)      /* HIP runtime error (message included) */
 #define SP_E_LIMIT (-6)       /* a size exceeds what the kernels support */
+#define SP_E_BUDGET (-7)      /* a server request can never fit, or its queue is full */
+#define SP_E_TIMEOUT (-8)     /* a wait ended before the request finished */
 
 typedef struct sp_circuit sp_circuit; /* parsed circuit (host) */
 typedef struct sp_model sp_model;     /* (M, c) and the location table (host) */
@@ -224,6 +226,70 @@ int sp_graph_capture_batch(const sp_batch* batch, sp_graph** out);
 int sp_graph_capture_plain(const sp_batch_item* items, size_t n, sp_graph** out);
 int sp_graph_launch(const sp_graph* graph, void* stream);
 void sp_graph_free(sp_graph* graph);
+
+/* ---- serving: resident models, HBM-budget admission, continuous batching --- */
+
+typedef struct sp_server sp_server;
+
+typedef struct {
+  uint32_t max_active; /* requests sampled concurrently ("slots"), >= 1 */
+  uint32_t max_queued; /* waiting requests before submit refuses (0 = 2^20) */
+  uint64_t tick_cost;  /* work per launch tick in Philox block-words, i.e. the
+                          model's blocks times 64-shot words (0 = 2^24) */
+  sp_launch launch;    /* launch shape of the tick kernels ({0,0} = {8,1}) */
+} sp_server_config;
+
+enum { SP_REQ_QUEUED = 0, SP_REQ_ACTIVE = 1, SP_REQ_DONE = 2, SP_REQ_FAILED = 3 };
+
+typedef struct {
+  int state;              /* SP_REQ_* */
+  uint32_t n_meas;
+  uint64_t* d_out;        /* the request's output in the arena once admitted:
+                             n_meas rows of ld_words words, layout of sp_sample
+                             with first_shot as submitted; valid until release */
+  uint64_t ld_words;      /* ceil(shots / 64) */
+  uint64_t t_submit_ns;   /* host steady clock at submit */
+  uint64_t t_admit_ns;    /* ... when the request got a slot and arena space */
+  uint64_t t_done_ns;     /* ... when the scheduler saw its last words written */
+} sp_request_status;
+
+typedef struct {
+  uint32_t queued, active;
+  uint64_t arena_in_use, arena_capacity;
+  uint64_t ticks, groups_launched, words_launched;
+} sp_server_counters;
+
+/* Device work memory the server needs for its per-tick job tables. */
+int sp_server_work_bytes(const sp_server_config* cfg, size_t* bytes);
+
+/* Starts a server on the current device.  d_arena (caller's device buffer,
+ * 256-byte aligned) holds request outputs; a request is admitted, first in
+ * first out, when a slot is free and its output (n_meas * ceil(shots/64) *
+ * 8 bytes) fits.  A scheduler thread launches ticks on a private stream:
+ * each tick samples a fair share of every active request's remaining words
+ * with one batched launch per evaluation path, two ticks in flight.  Both
+ * buffers are owned by the server until sp_server_destroy.  Models submitted
+ * must stay alive until their requests are released.  Errors: SP_E_INVALID,
+ * SP_E_NOMEM, SP_E_DEVICE. */
+int sp_server_create(const sp_server_config* cfg, void* d_arena, size_t arena_bytes, void* d_work, size_t work_bytes,
+                     sp_server** out);
+/* Queues a request (thread-safe, does not block on the device).  Its output
+ * is bit for bit what sp_sample(model, seed, first_shot, shots) writes.
+ * Errors: SP_E_INVALID, SP_E_LIMIT, SP_E_BUDGET (can never fit the arena, or
+ * the queue is full). */
+int sp_server_submit(sp_server* server, const sp_dmodel* model, uint64_t seed, uint64_t first_shot, uint64_t shots,
+                     uint64_t* ticket);
+int sp_server_status(sp_server* server, uint64_t ticket, sp_request_status* out);
+/* Blocks until the request is done or failed (timeout_ms < 0: no limit).
+ * Errors: SP_E_TIMEOUT, SP_E_DEVICE (the request failed), SP_E_INVALID. */
+int sp_server_wait(sp_server* server, uint64_t ticket, int64_t timeout_ms, sp_request_status* out);
+/* Frees a finished request's arena space; its output pointer is invalid
+ * afterwards. */
+int sp_server_release(sp_server* server, uint64_t ticket);
+int sp_server_stats(sp_server* server, sp_server_counters* out);
+/* Finishes the ticks in flight, fails requests that never ran, stops the
+ * thread and frees the server's host resources. */
+void sp_server_destroy(sp_server* server);
 
 const char* sp_last_error(void);
 

@@ -25,9 +25,16 @@ from ._capi import (  # noqa: F401
     SymphaseError,
     check,
     lib,
+    SP_REQ_ACTIVE,
+    SP_REQ_DONE,
+    SP_REQ_FAILED,
+    SP_REQ_QUEUED,
     sp_batch_item,
     sp_dims,
     sp_launch,
+    sp_request_status,
+    sp_server_config,
+    sp_server_counters,
 )
 
 _PATHS = {"auto": SP_PATH_AUTO, "sparse": SP_PATH_SPARSE, "dense": SP_PATH_DENSE}
@@ -277,6 +284,77 @@ class Graph:
 
     def __del__(self, _rel=_release):
         _rel(self, "sp_graph_free")
+
+
+class Server:
+    """Continuous-batching sampling server (sp_server_*).  Outputs live in an
+    HBM arena of `arena_bytes`; requests are admitted first in first out as
+    slots and arena space free up."""
+
+    STATES = {SP_REQ_QUEUED: "queued", SP_REQ_ACTIVE: "active", SP_REQ_DONE: "done", SP_REQ_FAILED: "failed"}
+
+    def __init__(self, arena_bytes: int, max_active: int = 16, max_queued: int = 0, tick_cost: int = 0,
+                 launch=(0, 0), device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        cfg = sp_server_config(max_active, max_queued, tick_cost, sp_launch(int(launch[0]), int(launch[1])))
+        n = ctypes.c_size_t()
+        check(lib().sp_server_work_bytes(ctypes.byref(cfg), ctypes.byref(n)))
+        self.arena = torch.empty(arena_bytes + 256, dtype=torch.uint8, device=self.device)
+        self.work = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        a0, w0 = self.arena.data_ptr(), self.work.data_ptr()
+        self._arena_base = a0 + (-a0) % 256
+        w = w0 + (-w0) % 256
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().sp_server_create(ctypes.byref(cfg), ctypes.c_void_p(self._arena_base), arena_bytes,
+                                         ctypes.c_void_p(w), n.value, ctypes.byref(h)))
+        self._h = h
+        self._models = {}
+
+    def submit(self, model: DeviceModel, shots: int, seed: int = 0, first_shot: int = 0) -> int:
+        t = ctypes.c_uint64()
+        check(lib().sp_server_submit(self._h, model.handle, seed, first_shot, shots, ctypes.byref(t)))
+        self._models[t.value] = model
+        return t.value
+
+    def _status(self, st: sp_request_status) -> dict:
+        return {"state": self.STATES[st.state], "n_meas": st.n_meas, "d_out": st.d_out, "ld": st.ld_words,
+                "t_submit_ns": st.t_submit_ns, "t_admit_ns": st.t_admit_ns, "t_done_ns": st.t_done_ns}
+
+    def status(self, ticket: int) -> dict:
+        st = sp_request_status()
+        check(lib().sp_server_status(self._h, ticket, ctypes.byref(st)))
+        return self._status(st)
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> dict:
+        st = sp_request_status()
+        check(lib().sp_server_wait(self._h, ticket, timeout_ms, ctypes.byref(st)))
+        return self._status(st)
+
+    def output(self, status: dict) -> torch.Tensor:
+        """View of a finished request's output in the arena: (n_meas, ld) int64.
+        Valid until release."""
+        if status["d_out"] is None or status["n_meas"] == 0:
+            return torch.empty((0, status["ld"]), dtype=torch.int64, device=self.device)
+        off = status["d_out"] - self._arena_base
+        nbytes = status["n_meas"] * status["ld"] * 8
+        return self.arena[(self._arena_base - self.arena.data_ptr()) + off:][:nbytes].view(torch.int64).view(
+            status["n_meas"], status["ld"])
+
+    def release(self, ticket: int):
+        check(lib().sp_server_release(self._h, ticket))
+        self._models.pop(ticket, None)
+
+    def stats(self) -> dict:
+        c = sp_server_counters()
+        check(lib().sp_server_stats(self._h, ctypes.byref(c)))
+        return {k: getattr(c, k) for k, _ in sp_server_counters._fields_}
+
+    def close(self):
+        _release(self, "sp_server_destroy")
+
+    def __del__(self, _rel=_release):
+        _rel(self, "sp_server_destroy")
 
 
 def sample(dmodel: DeviceModel, shots: int, seed: int = 0, first_shot: int = 0, **kw) -> torch.Tensor:

@@ -14,6 +14,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsymphase
 
 SP_OK = 0
 SP_E_INVALID, SP_E_PARSE, SP_E_UNSUPPORTED, SP_E_NOMEM, SP_E_DEVICE, SP_E_LIMIT = -1, -2, -3, -4, -5, -6
+SP_E_BUDGET, SP_E_TIMEOUT = -7, -8
+SP_REQ_QUEUED, SP_REQ_ACTIVE, SP_REQ_DONE, SP_REQ_FAILED = 0, 1, 2, 3
 SP_PATH_AUTO, SP_PATH_SPARSE, SP_PATH_DENSE = 0, 1, 2
 SP_SCHED_PERSISTENT, SP_SCHED_FLAT = 0, 1
 
@@ -24,7 +26,9 @@ EXPORTS = (
     "sp_model_export_dense", "sp_model_export_csc", "sp_model_export_vars", "sp_model_device_bytes",
     "sp_model_upload", "sp_dmodel_free", "sp_dmodel_dims", "sp_dmodel_get_launch", "sp_dmodel_set_launch",
     "sp_sample", "sp_batch_work_bytes", "sp_batch_create", "sp_batch_info", "sp_batch_launch", "sp_batch_free",
-    "sp_graph_capture_batch", "sp_graph_capture_plain", "sp_graph_launch", "sp_graph_free", "sp_last_error",
+    "sp_graph_capture_batch", "sp_graph_capture_plain", "sp_graph_launch", "sp_graph_free",
+    "sp_server_work_bytes", "sp_server_create", "sp_server_submit", "sp_server_status", "sp_server_wait",
+    "sp_server_release", "sp_server_stats", "sp_server_destroy", "sp_last_error",
 )
 
 
@@ -41,6 +45,23 @@ class sp_launch(ctypes.Structure):
 class sp_batch_item(ctypes.Structure):
     _fields_ = [("model", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("first_shot", ctypes.c_uint64),
                 ("shots", ctypes.c_uint64), ("d_out", ctypes.c_void_p), ("ld_words", ctypes.c_size_t)]
+
+
+class sp_server_config(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_uint32), ("max_queued", ctypes.c_uint32), ("tick_cost", ctypes.c_uint64),
+                ("launch", sp_launch)]
+
+
+class sp_request_status(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("n_meas", ctypes.c_uint32), ("d_out", ctypes.c_void_p),
+                ("ld_words", ctypes.c_uint64), ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64)]
+
+
+class sp_server_counters(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_uint32), ("active", ctypes.c_uint32), ("arena_in_use", ctypes.c_uint64),
+                ("arena_capacity", ctypes.c_uint64), ("ticks", ctypes.c_uint64), ("groups_launched", ctypes.c_uint64),
+                ("words_launched", ctypes.c_uint64)]
 
 
 class SymphaseError(RuntimeError):
@@ -87,6 +108,14 @@ def lib():
         "sp_graph_capture_plain": ([vp, sz, P(vp)], ctypes.c_int),
         "sp_graph_launch": ([vp, vp], ctypes.c_int),
         "sp_graph_free": ([vp], None),
+        "sp_server_work_bytes": ([P(sp_server_config), P(sz)], ctypes.c_int),
+        "sp_server_create": ([P(sp_server_config), vp, sz, vp, sz, P(vp)], ctypes.c_int),
+        "sp_server_submit": ([vp, vp, u64, u64, u64, P(u64)], ctypes.c_int),
+        "sp_server_status": ([vp, u64, P(sp_request_status)], ctypes.c_int),
+        "sp_server_wait": ([vp, u64, ctypes.c_int64, P(sp_request_status)], ctypes.c_int),
+        "sp_server_release": ([vp, u64], ctypes.c_int),
+        "sp_server_stats": ([vp, P(sp_server_counters)], ctypes.c_int),
+        "sp_server_destroy": ([vp], None),
         "sp_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
