@@ -38,6 +38,7 @@ def parse_args():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -162,6 +163,10 @@ def main():
 
     if not args.no_extra:
         rec["extra"] = extra_workloads(sp, torch, surface_memory, repetition_memory)
+        rec["extra"]["batched_mix_64"] = batched_mix_leg(sp, torch)
+        rec["extra"]["batched_small_jobs_256"] = small_jobs_leg(sp, torch, surface_memory, repetition_memory)
+        if not args.no_serving:
+            rec["extra"]["serving_d15_pool16"] = serving_leg(sp, torch)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(text, n_meas)
     print(json.dumps(rec))
@@ -199,6 +204,110 @@ def extra_workloads(sp, torch, surface_memory, repetition_memory) -> dict:
         res[f"surface_d15_r15_p{p}_1e7_shots"] = {"bits_per_s": total * m.n_meas / dt, "seconds": dt,
                                                    "batches": len(starts), "launch": list(dm.launch)}
     return res
+
+
+def _event_ms(fn, reps, torch):
+    fn()
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        lat.append(a.elapsed_time(b))
+    return lat
+
+
+def _plain_vs_batched(sp, torch, jobs, reps=10) -> dict:
+    """Times the same jobs as one sp_sample launch each (plain), the plain
+    sequence replayed from a graph, the batched launch (autotuned shape and
+    schedule) and its graph replay."""
+    from paper_2311_03906_amd import autotune
+    bits = sum(j.shots * j.model.n_meas for j in jobs)
+    ops = sum(j.shots * (PHILOX_OPS * j.model.dims.n_draw_blocks + j.model.dims.n_drawn) for j in jobs)
+
+    def plain():
+        for j in jobs:
+            j.model.sample(j.shots, seed=j.seed, first_shot=j.first_shot, out=j.out)
+
+    res = {"jobs": len(jobs), "bits": bits}
+    lat = _event_ms(plain, reps, torch)
+    res["plain"] = {"ms_p50": pct(lat, 50), "ms_p99": pct(lat, 99)}
+    g = sp.Graph.capture_plain(jobs)
+    lat = _event_ms(g.launch, reps, torch)
+    res["plain_graph"] = {"ms_p50": pct(lat, 50), "ms_p99": pct(lat, 99)}
+    b, shape, sched, _ = autotune.tune_batch(jobs, reps=3)
+    lat = _event_ms(b.launch, reps, torch)
+    res["batched"] = {"ms_p50": pct(lat, 50), "ms_p99": pct(lat, 99), "launch": list(shape), "schedule": sched}
+    gb = sp.Graph.capture_batch(b)
+    lat = _event_ms(gb.launch, reps, torch)
+    res["batched_graph"] = {"ms_p50": pct(lat, 50), "ms_p99": pct(lat, 99)}
+    for k in ("plain", "plain_graph", "batched", "batched_graph"):
+        ms = res[k]["ms_p50"]
+        res[k]["bits_per_s"] = bits / (ms * 1e-3)
+        res[k]["valu_frac"] = ops / (ms * 1e-3) / PEAK_VALU
+    res["gain_batched_over_plain"] = res["plain"]["ms_p50"] / res["batched"]["ms_p50"]
+    res["gain_batched_graph_over_plain"] = res["plain"]["ms_p50"] / res["batched_graph"]["ms_p50"]
+    return res
+
+
+def batched_mix_leg(sp, torch) -> dict:
+    """64 circuits: repetition d 3..25 and rotated surface d 3..11 (odd),
+    rounds = d, p log-uniform in [1e-4, 1e-2], shots log-uniform in
+    [1e4, 1e6], sampling seed = circuit index (the mix is seeded, seed 0)."""
+    from workloads.circuits import batched_mix
+    jobs, models = [], {}
+    for m in batched_mix(0):
+        text = m["circuit"].text()
+        if text not in models:
+            mod = sp.Model(text)
+            models[text] = sp.DeviceModel(mod)
+        jobs.append(sp.Job(models[text], m["shots"], seed=m["seed"]))
+    return _plain_vs_batched(sp, torch, jobs)
+
+
+def small_jobs_leg(sp, torch, surface_memory, repetition_memory) -> dict:
+    """256 small jobs (repetition d 3/5/7/9 and surface d 3, d rounds,
+    p = 1e-3, 10^4 shots each): the plain path is launch-bound here."""
+    texts = [repetition_memory(d, d, "0.001").text() for d in (3, 5, 7, 9)] + [surface_memory(3, 3, "0.001").text()]
+    dms = [sp.DeviceModel(sp.Model(t)) for t in texts]
+    jobs = [sp.Job(dms[i % len(dms)], 10_000, seed=i) for i in range(256)]
+    return _plain_vs_batched(sp, torch, jobs)
+
+
+def serving_leg(sp, torch) -> dict:
+    """Serving over a resident pool of 16 rotated-surface d=15, 15-round
+    circuits (p log-uniform in [1e-3, 5e-3], the first two 1e-3 and 5e-3):
+    Poisson arrivals, circuit uniform over the pool, shots log-uniform in
+    [1e3, 1e6], seed = request id, outputs in a 16 GiB HBM arena.  The
+    saturation rate is measured with a burst; the open-loop sweep runs at
+    0.25 .. 1.2 of it."""
+    from paper_2311_03906_amd import loadgen
+    from workloads.circuits import serving_pool
+    pool = serving_pool(0)
+    models = [sp.DeviceModel(sp.Model(c["circuit"].text()), path="sparse") for c in pool]
+    srv = sp.Server(arena_bytes=16 << 30, max_active=16)
+    mean_shots = (1e6 - 1e3) / math.log(1e3)
+    mean_bits = mean_shots * models[0].n_meas
+    burst = loadgen.poisson_plan(128, 1e9, len(models), 1_000, 1_000_000, seed=1)
+    sat = loadgen.run(srv, models, burst, first_id=1_000_000)
+    mu = sat["bits_per_s"] / mean_bits
+    out = {"saturation": {"bits_per_s": sat["bits_per_s"], "requests_per_s": mu, "p50_ms": sat["p50_ms"],
+                          "p99_ms": sat["p99_ms"], "requests": sat["requests"]},
+           "arena_bytes": 16 << 30, "max_active": 16, "sweep": []}
+    blocks = [m.dims.n_draw_blocks for m in models]
+    for k, f in enumerate((0.25, 0.5, 0.75, 0.9, 1.0, 1.2)):
+        plan = loadgen.poisson_plan(240, f * mu, len(models), 1_000, 1_000_000, seed=10 + k)
+        r = loadgen.run(srv, models, plan, first_id=k * 10_000)
+        ops = sum(int(s) * (PHILOX_OPS * blocks[mi] + models[mi].dims.n_drawn) for mi, s in zip(plan[1], plan[2]))
+        r["valu_frac"] = ops / r["span_s"] / PEAK_VALU if r["span_s"] > 0 else None
+        r["rate_factor"] = f
+        r["offered_requests_per_s"] = f * mu
+        out["sweep"].append(r)
+    srv.close()
+    return out
 
 
 if __name__ == "__main__":

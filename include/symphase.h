@@ -267,7 +267,7 @@ int sp_server_work_bytes(const sp_server_config* cfg, size_t* bytes);
  * first out, when a slot is free and its output (n_meas * ceil(shots/64) *
  * 8 bytes) fits.  A scheduler thread launches ticks on a private stream:
  * each tick samples a fair share of every active request's remaining words
- * with one batched launch per evaluation path, two ticks in flight.  Both
+ * with one batched launch per evaluation path, three ticks in flight on three streams.  Both
  * buffers are owned by the server until sp_server_destroy.  Models submitted
  * must stay alive until their requests are released.  Errors: SP_E_INVALID,
  * SP_E_NOMEM, SP_E_DEVICE. */

@@ -40,6 +40,37 @@ using sp::BatchCounters;
 
 namespace {
 
+// Address-space views of model and output pointers.  The model is read-only
+// while kernels run: uniform reads through the constant space become scalar
+// loads, per-lane reads through the global space avoid flat instructions.
+// (Pointers that come from a job table in memory would otherwise be generic.)
+// The qualifiers mean something only to the device compiler.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SP_CONST_AS __attribute__((address_space(4)))
+#define SP_GLOBAL_AS __attribute__((address_space(1)))
+#else
+#define SP_CONST_AS
+#define SP_GLOBAL_AS
+#endif
+typedef const SP_CONST_AS uint32_t* cuint32_p;
+typedef const SP_CONST_AS uint64_t* cuint64_p;
+typedef const SP_GLOBAL_AS uint32_t* guint32_p;
+typedef const SP_GLOBAL_AS uint64_t* guint64_p;
+typedef SP_GLOBAL_AS uint64_t* gout_p;
+
+// A read-only object of 4-byte words loaded through the constant space
+// (wave-uniform address: scalar loads into SGPRs).
+template <class T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized objects only");
+  T v;
+  const cuint32_p src = (cuint32_p)p;
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(T) / 4; ++i) dst[i] = src[i];
+  return v;
+}
+
 constexpr uint32_t kM0 = 0xD2511F53u;   // Philox4x32 round multipliers
 constexpr uint32_t kM1 = 0xCD9E8D57u;
 constexpr uint32_t kW0 = 0x9E3779B9u;   // Philox key increments
@@ -104,7 +135,7 @@ struct Masks {
 };
 
 __device__ __forceinline__ Masks decode(const uint32_t* chans, uint32_t meta, uint32_t u, uint64_t fire) {
-  const uint32_t* T = chans + ((meta & 0xFFu) - 1u) * 16u;   // uniform address: scalar loads, no VALU
+  const cuint32_p T = (cuint32_p)chans + ((meta & 0xFFu) - 1u) * 16u;   // uniform: scalar loads, no VALU
   const uint32_t kind = T[0];
   Masks r{fire, 0ull, 0ull, 0ull, 1u};   // X/Y/Z errors and the random-measurement coin
   if (kind == sp::CH_DEP1) {
@@ -135,7 +166,7 @@ __device__ __forceinline__ Masks decode(const uint32_t* chans, uint32_t meta, ui
 // Evaluate a fired location: XOR its code-bit masks into the slab rows of
 // its variables' columns of M.
 __device__ __forceinline__ void xor_dense(const DevModel& m, uint64_t* slab, uint32_t var, uint64_t s, uint32_t lane) {
-  const uint64_t* col = m.dense + (size_t)var * m.dense_words;
+  const cuint64_p col = (cuint64_p)m.dense + (size_t)var * m.dense_words;
   for (uint32_t c = 0; c < m.dense_words; ++c) {
     const uint64_t bits = col[c];
     if ((bits >> lane) & 1ull) atomicXor((unsigned long long*)&slab[c * 64 + lane], (unsigned long long)s);
@@ -167,8 +198,9 @@ __device__ __forceinline__ void evaluate_sparse(const DevModel& m, uint64_t* sla
     const uint64_t s = select_mask<NB>(first, k);
     if (NB == 1 || s) atomicXor((unsigned long long*)&slab[first >> 2], (unsigned long long)s);
   }
+  const guint32_p entries = (guint32_p)m.entries;
   for (uint32_t i = lo + 64u + lane; i < hi; i += 64) {
-    const uint32_t e = m.entries[i];
+    const uint32_t e = entries[i];
     const uint64_t s = select_mask<NB>(e, k);
     if (NB == 1 || s) atomicXor((unsigned long long*)&slab[e >> 2], (unsigned long long)s);
   }
@@ -183,10 +215,18 @@ __device__ __forceinline__ void evaluate_dense(const DevModel& m, uint64_t* slab
   if (k.b3) xor_dense(m, slab, var0 + 3, k.b3, lane);
 }
 
+// One block descriptor (64 bytes, one scalar load).
+struct Desc {
+  uint4 q[4];
+};
+
 // The draw-select-evaluate loop of one wave over its share of the blocks.
 // UHI: the high word of every lane's shot index is the same (the usual case),
 // which lets the first Philox rounds run on the scalar unit.
-template <int R, int DENSE, bool UHI>
+// KARG: the job's pointers came straight from kernel arguments, which the
+// compiler already reads with scalar loads; jobs read from a table in memory
+// go through the constant address space explicitly instead.
+template <int R, int DENSE, bool UHI, bool KARG>
 __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, uint32_t g, uint32_t wave,
                                            uint32_t n_waves, uint32_t lane) {
   const DevModel& m = a.m;
@@ -206,15 +246,19 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
   uint32_t b = wave;
   if (b >= m.nb) return;
   const RoundKeys keys = round_keys(a.key0, a.key1);
-  uint4 d0 = m.blocks[4 * b], d1 = m.blocks[4 * b + 1], d2 = m.blocks[4 * b + 2], d3 = m.blocks[4 * b + 3];
+  const Desc* blocks = reinterpret_cast<const Desc*>(m.blocks);
+  const guint32_p entries = (guint32_p)m.entries;
+  Desc cur = KARG ? blocks[b] : load_uniform(blocks + b);
+  uint4 d0 = cur.q[0], d1 = cur.q[1], d2 = cur.q[2], d3 = cur.q[3];
   for (;;) {
     const uint32_t bn = b + n_waves;
     uint4 n0 = d0, n1 = d1, n2 = d2, n3 = d3;
     if (bn < m.nb) {   // next descriptor in flight while this block computes
-      n0 = m.blocks[4 * bn];
-      n1 = m.blocks[4 * bn + 1];
-      n2 = m.blocks[4 * bn + 2];
-      n3 = m.blocks[4 * bn + 3];
+      const Desc nx = KARG ? blocks[bn] : load_uniform(blocks + bn);
+      n0 = nx.q[0];
+      n1 = nx.q[1];
+      n2 = nx.q[2];
+      n3 = nx.q[3];
     }
     uint4 u[R];
 #pragma unroll
@@ -242,7 +286,7 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
 #pragma unroll
           for (int r = 0; r < R; ++r) fs |= f[r][s];
           const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
-          if (fs && lo + lane < hi) first[s] = m.entries[lo + lane];
+          if (fs && lo + lane < hi) first[s] = entries[lo + lane];
         }
       }
 #pragma unroll
@@ -283,12 +327,13 @@ __device__ __forceinline__ uint32_t xcd_group(uint32_t b, uint32_t n) {
 
 // One group = R consecutive 64-shot words of one job, each with its LDS
 // slab of n_meas rows: initialise from c, draw and evaluate, store.
-template <int R, int DENSE>
+template <int R, int DENSE, bool KARG>
 __device__ __forceinline__ void process_group(const LaunchArgs& a, uint64_t* slab, uint32_t g, uint32_t tid,
                                               uint32_t lane, uint32_t wave, uint32_t n_waves) {
   const DevModel& m = a.m;
+  const guint64_p c_mask = (guint64_p)m.c_mask;
   for (uint32_t k = tid; k < m.n_meas; k += blockDim.x) {
-    const uint64_t v = ((m.c_mask[k >> 6] >> (k & 63u)) & 1ull) ? ~0ull : 0ull;
+    const uint64_t v = ((c_mask[k >> 6] >> (k & 63u)) & 1ull) ? ~0ull : 0ull;
 #pragma unroll
     for (int r = 0; r < R; ++r) slab[(size_t)r * m.n_meas + k] = v;
   }
@@ -297,8 +342,8 @@ __device__ __forceinline__ void process_group(const LaunchArgs& a, uint64_t* sla
   // Do the R words' shot indices share one high word?
   const uint64_t first = a.first_shot + (uint64_t)g * R * 64u;
   const uint64_t last = first + (uint64_t)R * 64u - 1u;
-  if ((first >> 32) == (last >> 32)) run_blocks<R, DENSE, true>(a, slab, g, wave, n_waves, lane);
-  else run_blocks<R, DENSE, false>(a, slab, g, wave, n_waves, lane);
+  if ((first >> 32) == (last >> 32)) run_blocks<R, DENSE, true, KARG>(a, slab, g, wave, n_waves, lane);
+  else run_blocks<R, DENSE, false, KARG>(a, slab, g, wave, n_waves, lane);
   __syncthreads();
 
 #pragma unroll
@@ -307,7 +352,7 @@ __device__ __forceinline__ void process_group(const LaunchArgs& a, uint64_t* sla
     if (w >= a.n_words) break;
     const uint64_t rem = a.shots - (uint64_t)w * 64u;
     const uint64_t valid = rem >= 64u ? ~0ull : ((1ull << rem) - 1ull);
-    uint64_t* col = a.out + w;
+    const gout_p col = (gout_p)a.out + w;
     for (uint32_t k = tid; k < m.n_meas; k += blockDim.x) col[(size_t)k * a.ld] = slab[(size_t)r * m.n_meas + k] & valid;
   }
 }
@@ -318,7 +363,7 @@ __global__ void __launch_bounds__(1024) sample_kernel(LaunchArgs a) {
   extern __shared__ uint64_t slab[];
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
   const uint32_t wave = uniform(tid >> 6), n_waves = blockDim.x >> 6;
-  process_group<R, DENSE>(a, slab, xcd_group(blockIdx.x, a.n_groups), tid, lane, wave, n_waves);
+  process_group<R, DENSE, true>(a, slab, xcd_group(blockIdx.x, a.n_groups), tid, lane, wave, n_waves);
 }
 
 // Many jobs per launch, persistent schedule: workgroups take tasks (runs of
@@ -340,10 +385,10 @@ __global__ void __launch_bounds__(1024) batch_persistent_kernel(const BatchJob* 
   while (t < n_tasks) {
     uint32_t nxt = 0;
     if (tid == 0) nxt = atomicAdd(&ctr->next, 1u);   // next task, in flight during this one
-    const sp::BatchTask task = tasks[t];
-    const BatchJob& job = jobs[task.job];
+    const sp::BatchTask task = load_uniform(tasks + t);
+    const BatchJob job = load_uniform(jobs + task.job);
     for (uint32_t i = 0; i < task.count; ++i) {
-      process_group<R, DENSE>(job.a, slab, task.first + i, tid, lane, wave, n_waves);
+      process_group<R, DENSE, false>(job.a, slab, task.first + i, tid, lane, wave, n_waves);
       __syncthreads();
     }
     if (tid == 0) s_next = nxt;
@@ -360,18 +405,27 @@ __global__ void __launch_bounds__(1024) batch_persistent_kernel(const BatchJob* 
   }
 }
 
-// Many jobs per launch, flat schedule: workgroup b owns global group b (jobs
-// are ordered heaviest first, so the hardware dispatcher hands out the
+// blockIdx -> group within runs of 64: the dispatcher deals workgroups
+// round-robin over the 8 XCDs, so XCD x receives groups 8x .. 8x+7 of each
+// run (consecutive words of a job, adjacent in every output row); the runs
+// themselves keep their order.  The last partial run maps to itself.
+__device__ __forceinline__ uint32_t run_swizzle(uint32_t b, uint32_t n) {
+  if ((b | 63u) >= n) return b;
+  return (b & ~63u) | ((b & 7u) << 3) | ((b >> 3) & 7u);
+}
+
+// Many jobs per launch, flat schedule: one workgroup per group (jobs are
+// ordered heaviest first, so the hardware dispatcher hands out the
 // expensive groups first).
 template <int R, int DENSE>
 __global__ void __launch_bounds__(1024) batch_flat_kernel(const BatchJob* __restrict__ jobs,
-                                                          const uint32_t* __restrict__ group_job) {
+                                                          const uint32_t* __restrict__ group_job, uint32_t total) {
   extern __shared__ uint64_t slab[];
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
   const uint32_t wave = uniform(tid >> 6), n_waves = blockDim.x >> 6;
-  const uint32_t g = blockIdx.x;
-  const BatchJob& job = jobs[group_job[g]];
-  process_group<R, DENSE>(job.a, slab, g - job.group_base, tid, lane, wave, n_waves);
+  const uint32_t g = run_swizzle(blockIdx.x, total);
+  const BatchJob job = load_uniform(jobs + ((cuint32_p)group_job)[g]);
+  process_group<R, DENSE, false>(job.a, slab, g - job.group_base, tid, lane, wave, n_waves);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -458,7 +512,7 @@ Layout plan(const sp_model& m, int path, const HostBlocks& H) {
 
 using KernelFn = void (*)(LaunchArgs);
 using PersistentFn = void (*)(const BatchJob*, const sp::BatchTask*, uint32_t, BatchCounters*);
-using FlatFn = void (*)(const BatchJob*, const uint32_t*);
+using FlatFn = void (*)(const BatchJob*, const uint32_t*, uint32_t);
 
 KernelFn kernel_for(int path, uint32_t words_per_group) {
   const bool dense = path == SP_PATH_DENSE;
@@ -541,7 +595,7 @@ int launch_batch_flat(const BatchJob* jobs, const uint32_t* group_job, uint32_t 
   if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
   const size_t lds = lds_bytes(n_meas_max, nch_max, L.words_per_group);
   if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k, dim3(total_groups), dim3(64 * L.waves_per_group), lds, s, jobs, group_job);
+  hipLaunchKernelGGL(k, dim3(total_groups), dim3(64 * L.waves_per_group), lds, s, jobs, group_job, total_groups);
   HIP_TRY(hipGetLastError());
   return SP_OK;
 }

@@ -1,9 +1,10 @@
 // Sampling server: resident models, HBM-budget admission and continuous
-// batching.  A scheduler thread owns a private HIP stream.  Each tick it
+// batching.  A scheduler thread owns one HIP stream per tick in flight.  Each tick it
 // admits queued requests (FIFO) into free slots whose outputs fit in the
 // arena, gives every active request a fair share of the tick's work, and
-// samples all of it with one flat batched launch per evaluation path.  Two
-// ticks may be in flight; when a tick's event completes, the requests whose
+// samples all of it with one flat batched launch per evaluation path.  Three
+// ticks may be in flight on three streams, so one tick's last workgroups
+// overlap the next tick's first; when a tick's event completes, the requests whose
 // last words it held are done and their slots take new requests.  Every
 // output equals what sp_sample would write for the request alone, because
 // each draw is keyed by (seed, absolute shot, location).
@@ -34,13 +35,14 @@ uint64_t now_ns() {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-constexpr int kSlots = 2;                  // ticks in flight
+constexpr int kSlots = 3;                  // ticks in flight, one stream each
 constexpr uint64_t kDefaultTickCost = 16ull << 20;
 constexpr uint32_t kDefaultMaxGroups = 1u << 16;
 
 struct Slot {
   uint8_t* host = nullptr;      // pinned staging
   uint8_t* dev = nullptr;       // in the caller's work buffer
+  hipStream_t stream = nullptr; // ticks on different slots overlap on the device
   hipEvent_t ev = nullptr;
   std::vector<sp::serve::Chunk> tick;
   std::string error;
@@ -70,7 +72,6 @@ struct sp_server {
   std::thread thread;
   bool stop = false;
   int device = 0;
-  hipStream_t stream = nullptr;
   uint8_t* arena = nullptr;
   uint32_t max_groups = 0;
   Layout L{};
@@ -125,19 +126,19 @@ int stage_and_launch(sp_server* S, int si) {
   // jobs[] holds the sparse jobs then the dense ones; map[] the sparse
   // groups then the dense ones, each numbering jobs within its own path.
   hipError_t e = hipMemcpyAsync(sl.dev + S->L.jobs, sl.host + S->L.jobs, sizeof(sp::BatchJob) * j,
-                                hipMemcpyHostToDevice, S->stream);
+                                hipMemcpyHostToDevice, sl.stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(sl.dev + S->L.map, sl.host + S->L.map, sizeof(uint32_t) * g, hipMemcpyHostToDevice, S->stream);
+    e = hipMemcpyAsync(sl.dev + S->L.map, sl.host + S->L.map, sizeof(uint32_t) * g, hipMemcpyHostToDevice, sl.stream);
   if (e != hipSuccess) return set_error(SP_E_DEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
   const sp::BatchJob* d_jobs = (const sp::BatchJob*)(sl.dev + S->L.jobs);
   const uint32_t* d_map = (const uint32_t*)(sl.dev + S->L.map);
   for (int p = 0; p < 2; ++p) {
     if (!groups[p]) continue;
     int rc = sp::launch_batch_flat(d_jobs + (p ? n_jobs[0] : 0), d_map + (p ? groups[0] : 0), groups[p], n_meas_max[p],
-                                   nch_max[p], p ? SP_PATH_DENSE : SP_PATH_SPARSE, S->cfg.launch, S->stream);
+                                   nch_max[p], p ? SP_PATH_DENSE : SP_PATH_SPARSE, S->cfg.launch, sl.stream);
     if (rc) return rc;
   }
-  e = hipEventRecord(sl.ev, S->stream);
+  e = hipEventRecord(sl.ev, sl.stream);
   if (e != hipSuccess) return set_error(SP_E_DEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
   S->ticks++;
   S->groups_launched += groups[0] + groups[1];
@@ -160,7 +161,7 @@ void server_loop(sp_server* S) {
       sl.error.clear();
       if (stage_and_launch(S, si) != SP_OK) {
         sl.error = sp_last_error();   // reported when the tick is retired
-        (void)hipEventRecord(sl.ev, S->stream);
+        (void)hipEventRecord(sl.ev, sl.stream);
       }
       S->inflight.push_back(si);
     }
@@ -226,8 +227,9 @@ int sp_server_create(const sp_server_config* cfg_in, void* d_arena, size_t arena
   S->max_groups = kDefaultMaxGroups;
   S->arena = (uint8_t*)d_arena;
   hipError_t e = hipGetDevice(&S->device);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
   for (int i = 0; i < kSlots && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&S->slot[i].stream, hipStreamNonBlocking);   // default priority
+    if (e != hipSuccess) break;
     S->slot[i].dev = (uint8_t*)d_work + (size_t)i * L.slot_bytes;
     e = hipHostMalloc((void**)&S->slot[i].host, L.slot_bytes, hipHostMallocDefault);
     if (e == hipSuccess) std::memset(S->slot[i].host, 0, L.slot_bytes);
@@ -238,8 +240,8 @@ int sp_server_create(const sp_server_config* cfg_in, void* d_arena, size_t arena
     for (int i = 0; i < kSlots; ++i) {
       if (S->slot[i].host) (void)hipHostFree(S->slot[i].host);
       if (S->slot[i].ev) (void)hipEventDestroy(S->slot[i].ev);
+      if (S->slot[i].stream) (void)hipStreamDestroy(S->slot[i].stream);
     }
-    if (S->stream) (void)hipStreamDestroy(S->stream);
     delete S;
     return set_error(SP_E_DEVICE, msg);
   }
@@ -249,8 +251,8 @@ int sp_server_create(const sp_server_config* cfg_in, void* d_arena, size_t arena
     for (int i = 0; i < kSlots; ++i) {
       (void)hipHostFree(S->slot[i].host);
       (void)hipEventDestroy(S->slot[i].ev);
+      (void)hipStreamDestroy(S->slot[i].stream);
     }
-    (void)hipStreamDestroy(S->stream);
     delete S;
     return set_error(SP_E_NOMEM, "cannot start the scheduler thread");
   }
@@ -354,12 +356,12 @@ void sp_server_destroy(sp_server* S) {
   }
   S->cv_work.notify_all();
   if (S->thread.joinable()) S->thread.join();
-  (void)hipStreamSynchronize(S->stream);
   for (int i = 0; i < kSlots; ++i) {
+    (void)hipStreamSynchronize(S->slot[i].stream);
     (void)hipHostFree(S->slot[i].host);
     (void)hipEventDestroy(S->slot[i].ev);
+    (void)hipStreamDestroy(S->slot[i].stream);
   }
-  (void)hipStreamDestroy(S->stream);
   delete S;
 }
 
