@@ -39,6 +39,8 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--legs", default="rep,d15,mix,small,serving",
+                    help="comma list of the other workloads to run (rep, d15, mix, small, serving)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -97,7 +99,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the sampler shards by shot range with no exchange, "
-              "and only the one-GPU path is built and measured (see DESIGN.md).", file=sys.stderr)
+              "and only the one-GPU path is built and measured.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -161,28 +163,51 @@ def main():
                      "ops_per_launch": ops},
     }
 
-    if not args.no_extra:
-        rec["extra"] = extra_workloads(sp, torch, surface_memory, repetition_memory)
-        rec["extra"]["batched_mix_64"] = batched_mix_leg(sp, torch)
-        rec["extra"]["batched_small_jobs_256"] = small_jobs_leg(sp, torch, surface_memory, repetition_memory)
-        if not args.no_serving:
+    legs = set() if args.no_extra else {x.strip() for x in args.legs.split(",") if x.strip()}
+    if args.no_serving:
+        legs.discard("serving")
+    unknown = legs - {"rep", "d15", "mix", "small", "serving"}
+    if unknown:
+        print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
+        sys.exit(2)
+    if legs:
+        rec["extra"] = extra_workloads(sp, torch, surface_memory, repetition_memory, legs)
+        if "mix" in legs:
+            rec["extra"]["batched_mix_64"] = batched_mix_leg(sp, torch)
+        if "small" in legs:
+            rec["extra"]["batched_small_jobs_256"] = small_jobs_leg(sp, torch, surface_memory, repetition_memory)
+        if "serving" in legs:
             rec["extra"]["serving_d15_pool16"] = serving_leg(sp, torch)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(text, n_meas)
     print(json.dumps(rec))
 
 
-def extra_workloads(sp, torch, surface_memory, repetition_memory) -> dict:
+def extra_workloads(sp, torch, surface_memory, repetition_memory, legs) -> dict:
     """Other configurations, each timed over a few repetitions."""
     res = {}
-    # Distance-3 repetition code, 3 rounds, 10^4 shots (launch-latency bound).
+    if "rep" in legs:
+        res.update(_repetition_leg(sp, torch, repetition_memory))
+    if "d15" in legs:
+        res.update(_d15_leg(sp, torch, surface_memory))
+    return res
+
+
+def _repetition_leg(sp, torch, repetition_memory) -> dict:
+    """Distance-3 repetition code, 3 rounds, 10^4 shots (launch-latency bound)."""
+    res = {}
     m = sp.Model(repetition_memory(3, 3, "0.001").text())
     dm = sp.DeviceModel(m)
     out = torch.empty((m.n_meas, 157), dtype=torch.int64, device="cuda")
     wall, lat = time_steps(lambda i: dm.sample(10_000, seed=0, first_shot=i * 10_000, out=out), 200, 10, torch)
     res["repetition_d3_r3_1e4_shots"] = {"bits_per_s": 10_000 * m.n_meas * 200 / wall, "ms_per_call": wall / 200 * 1e3,
                                          "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99)}
-    # Distance-15 surface code, 15 rounds, 10^7 shots in 2^20-shot batches.
+    return res
+
+
+def _d15_leg(sp, torch, surface_memory) -> dict:
+    """Distance-15 surface code, 15 rounds, 10^7 shots in 2^20-shot batches."""
+    res = {}
     for p in ("0.001", "0.005"):
         m = sp.Model(surface_memory(15, 15, p).text())
         dm = sp.DeviceModel(m, path="sparse")
