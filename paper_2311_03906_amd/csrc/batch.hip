@@ -28,7 +28,7 @@ struct SubBatch {
   sp::BatchTask* tasks = nullptr;      // device, persistent schedule
   uint32_t* group_job = nullptr;       // device, flat schedule
   sp::BatchCounters* ctr = nullptr;    // device, persistent schedule
-  uint32_t n_jobs = 0, n_tasks = 0, total_groups = 0, n_meas_max = 0, nch_max = 0, grid = 0;
+  uint32_t n_jobs = 0, n_tasks = 0, total_groups = 0, n_meas_max = 0, grid = 0;
 };
 
 }  // namespace
@@ -57,7 +57,7 @@ struct SubPlan {
   std::vector<sp::BatchTask> tasks;
   std::vector<uint32_t> group_job;
   uint64_t total_groups = 0;
-  uint32_t n_meas_max = 0, nch_max = 0;
+  uint32_t n_meas_max = 0;
   size_t off_ctr = 0, off_jobs = 0, off_tasks = 0, off_map = 0;
 };
 
@@ -79,7 +79,7 @@ int make_plan(const sp_batch_item* items, size_t n, const sp_launch* launch, int
   int dev = -1;
   HIP_TRY(hipGetDevice(&dev));
   size_t lds_max = 0;
-  uint32_t n_meas_max = 0, nch_max = 0;
+  uint32_t n_meas_max = 0;
   std::vector<size_t> live;
   for (size_t i = 0; i < n; ++i) {
     const sp_batch_item& it = items[i];
@@ -94,20 +94,19 @@ int make_plan(const sp_batch_item* items, size_t n, const sp_launch* launch, int
     if (words > 0x7FFFFFFFull) return set_error(SP_E_LIMIT, at + "too many shots");
     if (it.first_shot + it.shots < it.first_shot) return set_error(SP_E_INVALID, at + "shot range overflows");
     n_meas_max = std::max(n_meas_max, it.model->m.n_meas);
-    nch_max = std::max(nch_max, it.model->m.nch);
     live.push_back(i);
   }
   if (launch) {
     P.launch = *launch;
   } else {
     P.launch.waves_per_group = 8;
-    P.launch.words_per_group = (sp::lds_bytes(n_meas_max, nch_max, 2) * 3 <= lds_max || lds_max == 0) ? 2 : 1;
+    P.launch.words_per_group = 1;
   }
   const sp_launch& L = P.launch;
   if (L.waves_per_group < 1 || L.waves_per_group > 16) return set_error(SP_E_INVALID, "waves_per_group must be 1..16");
   if (L.words_per_group != 1 && L.words_per_group != 2 && L.words_per_group != 4)
     return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
-  if (lds_max && sp::lds_bytes(n_meas_max, nch_max, L.words_per_group) > lds_max)
+  if (lds_max && sp::lds_bytes(n_meas_max, L.words_per_group, L.waves_per_group, SP_PATH_SPARSE) > lds_max)
     return set_error(SP_E_LIMIT, "the largest model's slabs exceed the LDS of one workgroup");
   // Heavier groups first: with either schedule the light ones fill the tail.
   std::stable_sort(live.begin(), live.end(), [&](size_t x, size_t y) {
@@ -134,7 +133,6 @@ int make_plan(const sp_batch_item* items, size_t n, const sp_launch* launch, int
       S.total_groups += J.a.n_groups;
       if (S.total_groups >= 0x7FFFFFFFull) return set_error(SP_E_LIMIT, "more than 2^31 groups in one batch");
       S.n_meas_max = std::max(S.n_meas_max, it.model->m.n_meas);
-      S.nch_max = std::max(S.nch_max, it.model->m.nch);
       const uint32_t j = (uint32_t)S.jobs.size();
       if (schedule == SP_SCHED_PERSISTENT) {
         const uint32_t k = task_groups(it.model->m.nb);
@@ -201,7 +199,7 @@ int sp_batch_create(const sp_batch_item* items, size_t n, const sp_launch* launc
   uint32_t grids[2] = {0, 0};
   if (schedule == SP_SCHED_PERSISTENT)
     for (int i = 0; i < P.n_sub; ++i) {
-      int rc = sp::batch_grid(P.launch, P.sub[i].n_meas_max, P.sub[i].nch_max, P.sub[i].path, &grids[i]);
+      int rc = sp::batch_grid(P.launch, P.sub[i].n_meas_max, P.sub[i].path, &grids[i]);
       if (rc) return rc;
     }
   hipStream_t s = (hipStream_t)stream;
@@ -223,7 +221,6 @@ int sp_batch_create(const sp_batch_item* items, size_t n, const sp_launch* launc
     B.n_tasks = (uint32_t)S.tasks.size();
     B.total_groups = (uint32_t)S.total_groups;
     B.n_meas_max = S.n_meas_max;
-    B.nch_max = S.nch_max;
     B.grid = std::min<uint32_t>(grids[i], std::max<uint32_t>(B.n_tasks, 1));
   }
   b->schedule = schedule;
@@ -257,10 +254,10 @@ int sp_batch_launch(const sp_batch* b, void* stream) {
   for (int i = 0; i < b->n_sub; ++i) {
     const SubBatch& B = b->sub[i];
     int rc = b->schedule == SP_SCHED_PERSISTENT
-                 ? sp::launch_batch_persistent(B.jobs, B.tasks, B.n_tasks, B.ctr, B.n_meas_max, B.nch_max, B.path,
-                                               b->launch, B.grid, (hipStream_t)stream)
-                 : sp::launch_batch_flat(B.jobs, B.group_job, B.total_groups, B.n_meas_max, B.nch_max, B.path,
-                                         b->launch, (hipStream_t)stream);
+                 ? sp::launch_batch_persistent(B.jobs, B.tasks, B.n_tasks, B.ctr, B.n_meas_max, B.path, b->launch,
+                                               B.grid, (hipStream_t)stream)
+                 : sp::launch_batch_flat(B.jobs, B.group_job, B.total_groups, B.n_meas_max, B.path, b->launch,
+                                         (hipStream_t)stream);
     if (rc) return rc;
   }
   return SP_OK;

@@ -14,12 +14,14 @@ namespace sp {
 
 // Device model: every section lives in the caller's buffer.
 struct DevModel {
-  const uint4* blocks;       // [nb][4]: tm1[4] | meta[4] | lst[0..3] | (lst[4], blk, 0, 0)
-  const uint32_t* entries;   // merged (row << 2 | bit) lists, one per drawn location
-  const uint32_t* chans;     // [nch][16]: kind, T_1..T_15
+  const uint4* hot;          // [nb][2]: tm1[4] | (blk, 0, 0, 0), read for every block
+  const uint4* cold;         // [nb][4]: meta[4] | lst[0..3] | (lst[4], 0, 0, 0) | 0, read when a block fires
+  const uint32_t* entries;   // merged (row << 5 | bit) lists, one per drawn location
+  const uint32_t* chans;     // [nch][16]: kind | m << 8, T_1..T_{m-1}, then 0xFFFFFFFF
   const uint64_t* c_mask;    // [ceil(n_meas/64)]
   const uint64_t* dense;     // [n_vars][dense_words] (dense path only)
   uint32_t nb, n_meas, dense_words, nch;
+  uint32_t defer_max;        // fired lanes up to which a location is queued rather than evaluated at once
 };
 
 // One sampling job: a model, an output and a shot range.
@@ -33,8 +35,9 @@ struct LaunchArgs {
   uint32_t n_words, n_groups;
 };
 
-// A job inside a batched launch (device memory).
-struct BatchJob {
+// A job inside a batched launch (device memory; 16-byte multiple so that
+// kernels read it with 16-byte scalar loads).
+struct alignas(16) BatchJob {
   LaunchArgs a;
   uint32_t group_base;   // global index of the job's first group
   uint32_t pad[3];
@@ -56,20 +59,23 @@ struct BatchCounters {
 
 int set_error(int code, const std::string& msg);
 
-// LDS bytes of one workgroup (its slabs).
-size_t lds_bytes(uint32_t n_meas, uint32_t nch, uint32_t words_per_group);
+// Events a wave queues before it evaluates them (sparse path).
+constexpr uint32_t kQueueCap = 64;
+
+// LDS bytes of one workgroup: its slabs, then (sparse path) one event
+// queue of kQueueCap 16-byte records per wave.
+size_t lds_bytes(uint32_t n_meas, uint32_t words_per_group, uint32_t waves_per_group, int path);
 
 // Kernel launchers (sample.hip).
 int launch_sample(const LaunchArgs& a, int path, const sp_launch& L, hipStream_t s);
 // Persistent schedule: `grid` workgroups take tasks from ctr until none is left.
 int launch_batch_persistent(const BatchJob* jobs, const BatchTask* tasks, uint32_t n_tasks, BatchCounters* ctr,
-                            uint32_t n_meas_max, uint32_t nch_max, int path, const sp_launch& L, uint32_t grid,
-                            hipStream_t s);
+                            uint32_t n_meas_max, int path, const sp_launch& L, uint32_t grid, hipStream_t s);
 // Flat schedule: one workgroup per group, group_job[g] names its job.
 int launch_batch_flat(const BatchJob* jobs, const uint32_t* group_job, uint32_t total_groups, uint32_t n_meas_max,
-                      uint32_t nch_max, int path, const sp_launch& L, hipStream_t s);
+                      int path, const sp_launch& L, hipStream_t s);
 // Workgroups of the persistent kernel that fit on the device at once.
-int batch_grid(const sp_launch& L, uint32_t n_meas_max, uint32_t nch_max, int path, uint32_t* grid);
+int batch_grid(const sp_launch& L, uint32_t n_meas_max, int path, uint32_t* grid);
 
 }  // namespace sp
 

@@ -56,18 +56,21 @@ typedef const SP_CONST_AS uint32_t* cuint32_p;
 typedef const SP_CONST_AS uint64_t* cuint64_p;
 typedef const SP_GLOBAL_AS uint32_t* guint32_p;
 typedef const SP_GLOBAL_AS uint64_t* guint64_p;
+typedef const SP_GLOBAL_AS uint4* guint4_p;
 typedef SP_GLOBAL_AS uint64_t* gout_p;
 
-// A read-only object of 4-byte words loaded through the constant space
-// (wave-uniform address: scalar loads into SGPRs).
+// A read-only object loaded through the constant space, 16 bytes at a time
+// (wave-uniform address: scalar loads into SGPRs, merged by the compiler).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 template <class T>
 __device__ __forceinline__ T load_uniform(const T* p) {
-  static_assert(sizeof(T) % 4 == 0, "word-sized objects only");
+  static_assert(sizeof(T) % 16 == 0, "16-byte multiples only");
   T v;
-  const cuint32_p src = (cuint32_p)p;
-  uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+  const SP_CONST_AS u32x4* src = (const SP_CONST_AS u32x4*)p;
+  u32x4* dst = reinterpret_cast<u32x4*>(&v);
 #pragma unroll
-  for (unsigned i = 0; i < sizeof(T) / 4; ++i) dst[i] = src[i];
+  for (unsigned i = 0; i < sizeof(T) / 16; ++i) dst[i] = src[i];
   return v;
 }
 
@@ -77,8 +80,8 @@ constexpr uint32_t kW0 = 0x9E3779B9u;   // Philox key increments
 constexpr uint32_t kW1 = 0xBB67AE85u;
 
 // Round keys of Philox4x32-10 for one seed: round r uses (key0 + r*W0,
-// key1 + r*W1).  They are wave-uniform and stay in SGPRs: each round's
-// three-input XOR then reads two VGPRs and one SGPR.
+// key1 + r*W1).  They are wave-uniform SGPR operands of each round's
+// three-input XOR.
 struct RoundKeys {
   uint32_t k0[10], k1[10];
 };
@@ -124,41 +127,40 @@ __device__ __forceinline__ uint32_t pick(const uint4& v, int s) {
   return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
 }
 
-// Code-bit masks of a fired location.  fire = lanes with u < T_m.  For a
-// channel with m codes, m_k = ballot(u < T_k) are nested (m_1 <= ... <= m_m),
-// so a lane with code k lies in exactly the m_j with j >= k; the XOR of the
-// m_j over the j where bit i of the code flips between j and j+1 (j = m
-// included, code m+1 read as 0) is therefore bit i of the lane's code.
+// Pauli code of a fired draw u under channel ch1 - 1: the k with
+// T_{k-1} <= u < T_k (T_0 = 0).  The channel row holds kind | m << 8, then
+// T_1..T_{m-1}, then 0xFFFFFFFF; T_1..T_15 is thus nondecreasing and a
+// binary search counts j = #{k : T_k <= u}, so code = j + 1.  A draw of
+// u = 2^32 - 1 fires only when T_m = 2^32 (p = 1), and its code is m.
+__device__ __forceinline__ uint32_t lane_code(const uint32_t* chans, uint32_t ch1, uint32_t u) {
+  const guint32_p T = (guint32_p)chans + (ch1 - 1u) * 16u;
+  uint32_t j = 0;
+  j += (T[j + 8] <= u) ? 8u : 0u;
+  j += (T[j + 4] <= u) ? 4u : 0u;
+  j += (T[j + 2] <= u) ? 2u : 0u;
+  j += (T[j + 1] <= u) ? 1u : 0u;
+  return min(j + 1u, T[0] >> 8);
+}
+
+// Code-bit masks of a fired location (fire = lanes with u < T_m): mask i
+// holds the fired lanes whose code has bit i set.
 struct Masks {
   uint64_t b0, b1, b2, b3;   // 64-lane masks of code bits 0..3
   uint32_t nbits;            // code bits of the channel: 1, 2 or 4
 };
 
-__device__ __forceinline__ Masks decode(const uint32_t* chans, uint32_t meta, uint32_t u, uint64_t fire) {
-  const cuint32_p T = (cuint32_p)chans + ((meta & 0xFFu) - 1u) * 16u;   // uniform: scalar loads, no VALU
-  const uint32_t kind = T[0];
-  Masks r{fire, 0ull, 0ull, 0ull, 1u};   // X/Y/Z errors and the random-measurement coin
-  if (kind == sp::CH_DEP1) {
-    r.nbits = 2;
-    const uint64_t m1 = ballot(u < T[1]), m2 = ballot(u < T[2]);
-    r.b0 = m1 ^ m2 ^ fire;   // X part: codes 1 (X) and 3 (Y)
-    r.b1 = m1 ^ fire;        // Z part: codes 2 (Z) and 3 (Y)
-  } else if (kind == sp::CH_DEP2) {
-    r.nbits = 4;
-    uint64_t mk[16];
-#pragma unroll
-    for (int k = 1; k < 15; ++k) mk[k] = ballot(u < T[k]);
-    mk[15] = fire;
-    uint64_t b0 = 0, b1 = 0;
-#pragma unroll
-    for (int k = 1; k <= 15; ++k) {
-      b0 ^= mk[k];
-      if (k & 1) b1 ^= mk[k];
-    }
-    r.b0 = b0;
-    r.b1 = b1;
-    r.b2 = mk[3] ^ mk[7] ^ mk[11] ^ mk[15];
-    r.b3 = mk[7] ^ mk[15];
+__device__ __forceinline__ Masks decode(const uint32_t* chans, uint32_t meta, uint32_t u, uint64_t fire,
+                                        uint32_t lane) {
+  const uint32_t m = ((const cuint32_p)chans)[((meta & 0xFFu) - 1u) * 16u] >> 8;   // uniform
+  Masks r{fire, 0ull, 0ull, 0ull, 1u};   // one code: X/Y/Z errors and the random-measurement coin
+  if (m > 1) {
+    const bool f = (fire >> lane) & 1ull;
+    const uint32_t code = lane_code(chans, meta & 0xFFu, u);
+    r.nbits = m == 3 ? 2u : 4u;
+    r.b0 = ballot(f && (code & 1u));
+    r.b1 = ballot(f && (code & 2u));
+    r.b2 = ballot(f && (code & 4u));
+    r.b3 = ballot(f && (code & 8u));
   }
   return r;
 }
@@ -174,6 +176,11 @@ __device__ __forceinline__ void xor_dense(const DevModel& m, uint64_t* slab, uin
 }
 
 constexpr uint32_t kNoEntry = 0xFFFFFFFFu;
+
+// The slab row named by entry e = row << 5 | bit: e >> 2 is its byte offset.
+__device__ __forceinline__ uint64_t& row_of(uint64_t* slab, uint32_t e) {
+  return *reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(slab) + (e >> 2));
+}
 
 // Mask of the code bit named by entry e (low two bits) among the first NB.
 // Written as masked XORs rather than selects: the uniform masks stay scalar
@@ -196,13 +203,13 @@ __device__ __forceinline__ void evaluate_sparse(const DevModel& m, uint64_t* sla
                                                 uint32_t first, const Masks& k, uint32_t lane) {
   if (first != kNoEntry) {
     const uint64_t s = select_mask<NB>(first, k);
-    if (NB == 1 || s) atomicXor((unsigned long long*)&slab[first >> 2], (unsigned long long)s);
+    if (NB == 1 || s) atomicXor((unsigned long long*)&row_of(slab, first), (unsigned long long)s);
   }
   const guint32_p entries = (guint32_p)m.entries;
   for (uint32_t i = lo + 64u + lane; i < hi; i += 64) {
     const uint32_t e = entries[i];
     const uint64_t s = select_mask<NB>(e, k);
-    if (NB == 1 || s) atomicXor((unsigned long long*)&slab[e >> 2], (unsigned long long)s);
+    if (NB == 1 || s) atomicXor((unsigned long long*)&row_of(slab, e), (unsigned long long)s);
   }
 }
 
@@ -215,20 +222,67 @@ __device__ __forceinline__ void evaluate_dense(const DevModel& m, uint64_t* slab
   if (k.b3) xor_dense(m, slab, var0 + 3, k.b3, lane);
 }
 
-// One block descriptor (64 bytes, one scalar load).
-struct Desc {
-  uint4 q[4];
+// Orders the LDS accesses of one wave's lanes around an exchange through
+// LDS (no instruction: the wave's LDS operations already run in order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A fired location with few fired lanes is not evaluated at once: each of
+// its fired lanes queues one event {list start, list end, u, channel + 1 |
+// lane << 8 | word << 14} in the wave's LDS queue.  The queue is evaluated
+// with one event per lane: the lane finds its code from u, then walks its
+// location's list and flips its shot's bit in the rows of the code's set
+// bits.  One pass then serves up to 64 fired lanes instead of one location.
+__device__ __forceinline__ void flush_events(const DevModel& m, uint64_t* slab, const uint4* q, uint32_t qn,
+                                             uint32_t lane) {
+  wave_sync();
+  if (lane < qn) {
+    const uint4 ev = q[lane];
+    const uint32_t u = ev.z, info = ev.w;
+    const uint32_t code = lane_code(m.chans, info & 0xFFu, u);
+    const uint64_t bit = 1ull << ((info >> 8) & 63u);
+    uint64_t* sl = slab + (size_t)(info >> 14) * m.n_meas;
+    const guint32_p p0 = (guint32_p)m.entries + ev.x;
+    const guint32_p p1 = (guint32_p)m.entries + ev.y;
+    guint32_p p = p0;
+    for (; p + 4 <= p1; p += 4) {   // four loads in flight
+      const uint32_t e0 = p[0], e1 = p[1], e2 = p[2], e3 = p[3];
+      if (__builtin_amdgcn_ubfe(code, e0, 1)) atomicXor((unsigned long long*)&row_of(sl, e0), (unsigned long long)bit);
+      if (__builtin_amdgcn_ubfe(code, e1, 1)) atomicXor((unsigned long long*)&row_of(sl, e1), (unsigned long long)bit);
+      if (__builtin_amdgcn_ubfe(code, e2, 1)) atomicXor((unsigned long long*)&row_of(sl, e2), (unsigned long long)bit);
+      if (__builtin_amdgcn_ubfe(code, e3, 1)) atomicXor((unsigned long long*)&row_of(sl, e3), (unsigned long long)bit);
+    }
+    for (; p < p1; ++p) {
+      const uint32_t e = *p;
+      if (__builtin_amdgcn_ubfe(code, e, 1)) atomicXor((unsigned long long*)&row_of(sl, e), (unsigned long long)bit);
+    }
+  }
+  wave_sync();
+}
+
+// A block's descriptor: the part every block needs (thresholds and the
+// Philox block index, 32 bytes) and the part only fired blocks need
+// (channels, variables and list bounds, 64 bytes).
+struct Hot {
+  uint4 tm1;    // T_m - 1 per slot; 0 for a slot without a drawn location
+  uint4 blk;    // .x = l / 4
+};
+struct Cold {
+  uint4 meta;   // var0 << 8 | channel + 1 per slot; 0 = no drawn location
+  uint4 lst;    // start of each slot's entry list
+  uint4 end;    // .x = end of slot 3's list
+  uint4 pad;
 };
 
 // The draw-select-evaluate loop of one wave over its share of the blocks.
 // UHI: the high word of every lane's shot index is the same (the usual case),
 // which lets the first Philox rounds run on the scalar unit.
-// KARG: the job's pointers came straight from kernel arguments, which the
-// compiler already reads with scalar loads; jobs read from a table in memory
-// go through the constant address space explicitly instead.
-template <int R, int DENSE, bool UHI, bool KARG>
-__device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, uint32_t g, uint32_t wave,
-                                           uint32_t n_waves, uint32_t lane) {
+template <int R, int DENSE, bool UHI>
+__device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, uint4* queue, uint32_t g,
+                                           uint32_t wave, uint32_t n_waves, uint32_t lane) {
   const DevModel& m = a.m;
   uint32_t s_lo[R], s_hi[R];
 #pragma unroll
@@ -246,47 +300,64 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
   uint32_t b = wave;
   if (b >= m.nb) return;
   const RoundKeys keys = round_keys(a.key0, a.key1);
-  const Desc* blocks = reinterpret_cast<const Desc*>(m.blocks);
+  const Hot* hot = reinterpret_cast<const Hot*>(m.hot);
+  const Cold* cold = reinterpret_cast<const Cold*>(m.cold);
   const guint32_p entries = (guint32_p)m.entries;
-  Desc cur = KARG ? blocks[b] : load_uniform(blocks + b);
-  uint4 d0 = cur.q[0], d1 = cur.q[1], d2 = cur.q[2], d3 = cur.q[3];
+  Hot cur = load_uniform(hot + b);
+  uint32_t qn = 0;   // queued events (wave-uniform)
   for (;;) {
     const uint32_t bn = b + n_waves;
-    uint4 n0 = d0, n1 = d1, n2 = d2, n3 = d3;
-    if (bn < m.nb) {   // next descriptor in flight while this block computes
-      const Desc nx = KARG ? blocks[bn] : load_uniform(blocks + bn);
-      n0 = nx.q[0];
-      n1 = nx.q[1];
-      n2 = nx.q[2];
-      n3 = nx.q[3];
-    }
+    Hot nx = cur;
+    if (bn < m.nb) nx = load_uniform(hot + bn);   // in flight while this block computes
     uint4 u[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) u[r] = philox4x32_10(d3.y, s_lo[r], s_hi[r], 0u, keys);
+    for (int r = 0; r < R; ++r) u[r] = philox4x32_10(cur.blk.x, s_lo[r], s_hi[r], 0u, keys);
+    // A slot without a drawn location has threshold 0: it "fires" only at
+    // u = 0, and the fired path drops it by its zero meta.
     uint64_t f[R][4];
     uint64_t any = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      f[r][0] = d1.x ? ballot(u[r].x <= d0.x) : 0ull;
-      f[r][1] = d1.y ? ballot(u[r].y <= d0.y) : 0ull;
-      f[r][2] = d1.z ? ballot(u[r].z <= d0.z) : 0ull;
-      f[r][3] = d1.w ? ballot(u[r].w <= d0.w) : 0ull;
+      f[r][0] = ballot(u[r].x <= cur.tm1.x);
+      f[r][1] = ballot(u[r].y <= cur.tm1.y);
+      f[r][2] = ballot(u[r].z <= cur.tm1.z);
+      f[r][3] = ballot(u[r].w <= cur.tm1.w);
       any |= f[r][0] | f[r][1] | f[r][2] | f[r][3];
     }
     if (any) {
-      // Issue the entry loads of every fired location of the block first, so
-      // their latencies overlap, then decode and XOR.  (Measured: the fired
-      // path is bound by its VALU work -- decode compares and one list pass
-      // per fired location -- not by these latencies.)
-      uint32_t first[4] = {kNoEntry, kNoEntry, kNoEntry, kNoEntry};
-      if (!DENSE) {
+      const Cold c = load_uniform(cold + b);
+      const uint4 d1 = c.meta, d2 = c.lst, d3 = c.end;
+      // Locations fired in more than defer_max lanes are evaluated now (one
+      // pass over the location's list, lane = entry); the others queue
+      // their fired lanes.  At most kQueueCap / (4R) lanes per deferred
+      // location, so that one block's events always fit in an emptied queue.
+      const uint32_t dmax = min(m.defer_max, sp::kQueueCap / (4u * R));
+      uint32_t need = 0;   // events this block queues
+      bool big = false;    // some location is evaluated now
+#pragma unroll
+      for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          uint64_t fs = 0;
+          if (!pick(d1, s)) f[r][s] = 0;
+          const uint32_t n = (uint32_t)__builtin_popcountll(f[r][s]);
+          need += n;
+          big |= DENSE || n > dmax;
+        }
+      if (!DENSE && qn + need > sp::kQueueCap) {
+        flush_events(m, slab, queue, qn, lane);
+        qn = 0;
+      }
+      // Issue the entry loads of every location evaluated now first, so
+      // their latencies overlap, then decode and XOR.
+      uint32_t first[4] = {kNoEntry, kNoEntry, kNoEntry, kNoEntry};
+      if (!DENSE && big) {
 #pragma unroll
-          for (int r = 0; r < R; ++r) fs |= f[r][s];
+        for (int s = 0; s < 4; ++s) {
+          bool now_s = false;
+#pragma unroll
+          for (int r = 0; r < R; ++r) now_s |= (uint32_t)__builtin_popcountll(f[r][s]) > dmax;
           const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
-          if (fs && lo + lane < hi) first[s] = entries[lo + lane];
+          if (now_s && lo + lane < hi) first[s] = entries[lo + lane];
         }
       }
 #pragma unroll
@@ -295,12 +366,22 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
         for (int s = 0; s < 4; ++s) {
           if (!f[r][s]) continue;
           const uint32_t meta = pick(d1, s);
-          const Masks k = decode(m.chans, meta, pick(u[r], s), f[r][s]);
+          const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
+          const uint32_t n = (uint32_t)__builtin_popcountll(f[r][s]);
+          if (!DENSE && n <= dmax) {
+            if ((f[r][s] >> lane) & 1ull) {
+              const uint32_t pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(f[r][s] >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)f[r][s], 0u));
+              queue[pos] = make_uint4(lo, hi, pick(u[r], s), (meta & 0xFFu) | (lane << 8) | ((uint32_t)r << 14));
+            }
+            qn += n;
+            continue;
+          }
+          const Masks k = decode(m.chans, meta, pick(u[r], s), f[r][s], lane);
           uint64_t* sl = slab + (size_t)r * m.n_meas;
           if (DENSE) {
             evaluate_dense(m, sl, meta, k, lane);
           } else {
-            const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
             if (k.nbits == 1) evaluate_sparse<1>(m, sl, lo, hi, first[s], k, lane);
             else if (k.nbits == 2) evaluate_sparse<2>(m, sl, lo, hi, first[s], k, lane);
             else evaluate_sparse<4>(m, sl, lo, hi, first[s], k, lane);
@@ -310,11 +391,9 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
     }
     if (bn >= m.nb) break;
     b = bn;
-    d0 = n0;
-    d1 = n1;
-    d2 = n2;
-    d3 = n3;
+    cur = nx;
   }
+  if (!DENSE && qn) flush_events(m, slab, queue, qn, lane);
 }
 
 // blockIdx -> group, keeping consecutive groups on one XCD (workgroups are
@@ -327,7 +406,7 @@ __device__ __forceinline__ uint32_t xcd_group(uint32_t b, uint32_t n) {
 
 // One group = R consecutive 64-shot words of one job, each with its LDS
 // slab of n_meas rows: initialise from c, draw and evaluate, store.
-template <int R, int DENSE, bool KARG>
+template <int R, int DENSE>
 __device__ __forceinline__ void process_group(const LaunchArgs& a, uint64_t* slab, uint32_t g, uint32_t tid,
                                               uint32_t lane, uint32_t wave, uint32_t n_waves) {
   const DevModel& m = a.m;
@@ -342,8 +421,10 @@ __device__ __forceinline__ void process_group(const LaunchArgs& a, uint64_t* sla
   // Do the R words' shot indices share one high word?
   const uint64_t first = a.first_shot + (uint64_t)g * R * 64u;
   const uint64_t last = first + (uint64_t)R * 64u - 1u;
-  if ((first >> 32) == (last >> 32)) run_blocks<R, DENSE, true, KARG>(a, slab, g, wave, n_waves, lane);
-  else run_blocks<R, DENSE, false, KARG>(a, slab, g, wave, n_waves, lane);
+  // The wave's event queue follows the slabs (16-byte aligned).
+  uint4* queue = reinterpret_cast<uint4*>(slab + (((size_t)R * m.n_meas + 1u) & ~(size_t)1)) + wave * sp::kQueueCap;
+  if ((first >> 32) == (last >> 32)) run_blocks<R, DENSE, true>(a, slab, queue, g, wave, n_waves, lane);
+  else run_blocks<R, DENSE, false>(a, slab, queue, g, wave, n_waves, lane);
   __syncthreads();
 
 #pragma unroll
@@ -363,7 +444,7 @@ __global__ void __launch_bounds__(1024) sample_kernel(LaunchArgs a) {
   extern __shared__ uint64_t slab[];
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
   const uint32_t wave = uniform(tid >> 6), n_waves = blockDim.x >> 6;
-  process_group<R, DENSE, true>(a, slab, xcd_group(blockIdx.x, a.n_groups), tid, lane, wave, n_waves);
+  process_group<R, DENSE>(a, slab, xcd_group(blockIdx.x, a.n_groups), tid, lane, wave, n_waves);
 }
 
 // Many jobs per launch, persistent schedule: workgroups take tasks (runs of
@@ -388,7 +469,7 @@ __global__ void __launch_bounds__(1024) batch_persistent_kernel(const BatchJob* 
     const sp::BatchTask task = load_uniform(tasks + t);
     const BatchJob job = load_uniform(jobs + task.job);
     for (uint32_t i = 0; i < task.count; ++i) {
-      process_group<R, DENSE, false>(job.a, slab, task.first + i, tid, lane, wave, n_waves);
+      process_group<R, DENSE>(job.a, slab, task.first + i, tid, lane, wave, n_waves);
       __syncthreads();
     }
     if (tid == 0) s_next = nxt;
@@ -425,26 +506,33 @@ __global__ void __launch_bounds__(1024) batch_flat_kernel(const BatchJob* __rest
   const uint32_t wave = uniform(tid >> 6), n_waves = blockDim.x >> 6;
   const uint32_t g = run_swizzle(blockIdx.x, total);
   const BatchJob job = load_uniform(jobs + ((cuint32_p)group_job)[g]);
-  process_group<R, DENSE, false>(job.a, slab, g - job.group_base, tid, lane, wave, n_waves);
+  process_group<R, DENSE>(job.a, slab, g - job.group_base, tid, lane, wave, n_waves);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Fired lanes up to which a location's lanes are queued (sparse path).
+constexpr uint32_t kDeferMax = 8;
+
 // Drawn locations grouped by Philox block (l/4); blocks without a drawn
-// location are left out.  16 words per block:
-//   [0..3]  T_m - 1 per slot (fire when u <= T_m - 1, i.e. u < T_m)
-//   [4..7]  meta per slot: var0 << 8 | (channel + 1); 0 = no drawn location
-//   [8..11] start of the slot's entry list; [12] end of slot 3's list
-//   [13]    the Philox block index l/4
+// location are left out.  Per block, a hot record of 8 words:
+//   [0..3]  T_m - 1 per slot (fire when u <= T_m - 1, i.e. u < T_m); 0 for
+//           a slot without a drawn location
+//   [4]     the Philox block index l/4
+// and a cold record of 16 words:
+//   [0..3]  meta per slot: var0 << 8 | (channel + 1); 0 = no drawn location
+//   [4..7]  start of the slot's entry list; [8] end of slot 3's list
 // Entry lists: for every variable of the location (bit b), for every row k
-// of its column of M, the word k << 2 | b.
+// of its column of M, the word k << 5 | b (so that e >> 2 is the row's LDS
+// byte offset and bits 0..4 of e are the bit index).
 struct HostBlocks {
-  std::vector<uint32_t> words;
+  std::vector<uint32_t> hot, cold;
   std::vector<uint32_t> entries;
 };
 
 HostBlocks build_blocks(const sp_model& m) {
   HostBlocks H;
+  if (m.n_meas >= (1u << 27)) throw sp::Error(SP_E_LIMIT, "more than 2^27 measurements");
   int64_t cur = -1;
   for (uint32_t l = 0; l < m.n_locs; ++l) {
     const int32_t ch = m.loc_chan[l];
@@ -454,22 +542,24 @@ HostBlocks build_blocks(const sp_model& m) {
     if (Tm == 0) continue;  // never fires
     const int64_t blk = l >> 2;
     if (blk != cur) {
-      H.words.insert(H.words.end(), 16, 0u);
-      uint32_t* w = &H.words[H.words.size() - 16];
-      for (int i = 8; i <= 12; ++i) w[i] = (uint32_t)H.entries.size();
-      w[13] = (uint32_t)blk;
+      H.hot.insert(H.hot.end(), 8, 0u);
+      H.cold.insert(H.cold.end(), 16, 0u);
+      uint32_t* w = &H.cold[H.cold.size() - 16];
+      for (int i = 4; i <= 8; ++i) w[i] = (uint32_t)H.entries.size();
+      H.hot[H.hot.size() - 8 + 4] = (uint32_t)blk;
       cur = blk;
     }
-    uint32_t* w = &H.words[H.words.size() - 16];
+    uint32_t* h = &H.hot[H.hot.size() - 8];
+    uint32_t* w = &H.cold[H.cold.size() - 16];
     const uint32_t s = l & 3u, var0 = (uint32_t)m.loc_var0[l];
-    w[s] = (uint32_t)(Tm - 1);
-    w[4 + s] = (var0 << 8) | (uint32_t)(ch + 1);
-    w[8 + s] = (uint32_t)H.entries.size();
+    h[s] = (uint32_t)(Tm - 1);
+    w[s] = (var0 << 8) | (uint32_t)(ch + 1);
+    w[4 + s] = (uint32_t)H.entries.size();
     for (uint32_t b = 0; b < sp::loc_bits(m.loc_kind[l]); ++b)
       for (uint32_t i = m.col_ptr[var0 + b]; i < m.col_ptr[var0 + b + 1]; ++i)
-        H.entries.push_back((m.row_idx[i] << 2) | b);
+        H.entries.push_back((m.row_idx[i] << 5) | b);
     if (H.entries.size() >= (1ull << 32)) throw sp::Error(SP_E_LIMIT, "more than 2^32 entries in M");
-    for (uint32_t t = s + 1; t <= 4; ++t) w[8 + t] = (uint32_t)H.entries.size();
+    for (uint32_t t = s + 1; t <= 4; ++t) w[4 + t] = (uint32_t)H.entries.size();
   }
   return H;
 }
@@ -484,17 +574,18 @@ int choose_path(const sp_model& m, int path) {
 }
 
 struct Layout {
-  size_t blocks, entries, chans, c_mask, dense, total;
+  size_t hot, cold, entries, chans, c_mask, dense, total;
   uint32_t nb, nch, dense_words;
 };
 
 Layout plan(const sp_model& m, int path, const HostBlocks& H) {
   Layout L{};
-  L.nb = (uint32_t)(H.words.size() / 16);
+  L.nb = (uint32_t)(H.hot.size() / 8);
   L.nch = (uint32_t)m.channels.size();
   L.dense_words = (m.n_meas + 63) / 64;
   size_t off = 0;
-  L.blocks = off;  off = align256(off + 64 * std::max<size_t>(L.nb, 1));
+  L.hot = off;     off = align256(off + 32 * std::max<size_t>(L.nb, 1));
+  L.cold = off;    off = align256(off + 64 * std::max<size_t>(L.nb, 1));
   L.entries = off; off = align256(off + 4 * std::max<size_t>(H.entries.size(), 1));
   L.chans = off;   off = align256(off + 64 * (size_t)L.nch);
   L.c_mask = off;  off = align256(off + 8 * std::max<size_t>(L.dense_words, 1));
@@ -548,13 +639,13 @@ FlatFn flat_for(int path, uint32_t words_per_group) {
 
 namespace sp {
 
-size_t lds_bytes(uint32_t n_meas, uint32_t nch, uint32_t words_per_group) {
-  (void)nch;   // the channel table is read through the scalar cache
-  return (size_t)n_meas * 8 * words_per_group;
+size_t lds_bytes(uint32_t n_meas, uint32_t words_per_group, uint32_t waves_per_group, int path) {
+  const size_t slabs = ((size_t)n_meas * words_per_group + 1u) / 2u * 16u;
+  return path == SP_PATH_DENSE ? slabs : slabs + (size_t)waves_per_group * kQueueCap * 16u;
 }
 
 int launch_sample(const LaunchArgs& a, int path, const sp_launch& L, hipStream_t s) {
-  const size_t lds = lds_bytes(a.m.n_meas, a.m.nch, L.words_per_group);
+  const size_t lds = lds_bytes(a.m.n_meas, L.words_per_group, L.waves_per_group, path);
   KernelFn k = kernel_for(path, L.words_per_group);
   if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
   if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -563,10 +654,10 @@ int launch_sample(const LaunchArgs& a, int path, const sp_launch& L, hipStream_t
   return SP_OK;
 }
 
-int batch_grid(const sp_launch& L, uint32_t n_meas_max, uint32_t nch_max, int path, uint32_t* grid) {
+int batch_grid(const sp_launch& L, uint32_t n_meas_max, int path, uint32_t* grid) {
   PersistentFn k = persistent_for(path, L.words_per_group);
   if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
-  const size_t lds = lds_bytes(n_meas_max, nch_max, L.words_per_group);
+  const size_t lds = lds_bytes(n_meas_max, L.words_per_group, L.waves_per_group, path);
   if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   int dev = 0, cus = 0, per_cu = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -578,11 +669,10 @@ int batch_grid(const sp_launch& L, uint32_t n_meas_max, uint32_t nch_max, int pa
 }
 
 int launch_batch_persistent(const BatchJob* jobs, const BatchTask* tasks, uint32_t n_tasks, BatchCounters* ctr,
-                            uint32_t n_meas_max, uint32_t nch_max, int path, const sp_launch& L, uint32_t grid,
-                            hipStream_t s) {
+                            uint32_t n_meas_max, int path, const sp_launch& L, uint32_t grid, hipStream_t s) {
   PersistentFn k = persistent_for(path, L.words_per_group);
   if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
-  const size_t lds = lds_bytes(n_meas_max, nch_max, L.words_per_group);
+  const size_t lds = lds_bytes(n_meas_max, L.words_per_group, L.waves_per_group, path);
   if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k, dim3(grid), dim3(64 * L.waves_per_group), lds, s, jobs, tasks, n_tasks, ctr);
   HIP_TRY(hipGetLastError());
@@ -590,10 +680,10 @@ int launch_batch_persistent(const BatchJob* jobs, const BatchTask* tasks, uint32
 }
 
 int launch_batch_flat(const BatchJob* jobs, const uint32_t* group_job, uint32_t total_groups, uint32_t n_meas_max,
-                      uint32_t nch_max, int path, const sp_launch& L, hipStream_t s) {
+                      int path, const sp_launch& L, hipStream_t s) {
   FlatFn k = flat_for(path, L.words_per_group);
   if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
-  const size_t lds = lds_bytes(n_meas_max, nch_max, L.words_per_group);
+  const size_t lds = lds_bytes(n_meas_max, L.words_per_group, L.waves_per_group, path);
   if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k, dim3(total_groups), dim3(64 * L.waves_per_group), lds, s, jobs, group_job, total_groups);
   HIP_TRY(hipGetLastError());
@@ -604,19 +694,20 @@ int launch_batch_flat(const BatchJob* jobs, const uint32_t* group_job, uint32_t 
 
 namespace {
 
-// Default launch: 8 waves per group; two words per group when two slabs fit
-// in a third of the LDS (more shots per descriptor fetch), else one.
+// Default launch: 8 waves per group, one word per group (the shape that
+// keeps the draw loop free of register spills).
 sp_launch default_launch(const sp_dmodel& dm) {
+  (void)dm;
   sp_launch L;
   L.waves_per_group = 8;
-  L.words_per_group = (sp::lds_bytes(dm.m.n_meas, dm.m.nch, 2) * 3 <= dm.lds_max) ? 2 : 1;
+  L.words_per_group = 1;
   return L;
 }
 
 int validate_launch(const sp_dmodel& dm, const sp_launch& L) {
   if (L.waves_per_group < 1 || L.waves_per_group > 16) return set_error(SP_E_INVALID, "waves_per_group must be 1..16");
   if (!kernel_for(dm.path, L.words_per_group)) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
-  if (sp::lds_bytes(dm.m.n_meas, dm.m.nch, L.words_per_group) > dm.lds_max)
+  if (sp::lds_bytes(dm.m.n_meas, L.words_per_group, L.waves_per_group, dm.path) > dm.lds_max)
     return set_error(SP_E_LIMIT, "words_per_group slabs exceed the LDS of one workgroup");
   return SP_OK;
 }
@@ -649,11 +740,11 @@ int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_byt
   HIP_TRY(hipGetDevice(&dev));
   int lds_max = 0;
   HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  if (sp::lds_bytes(model->n_meas, (uint32_t)model->channels.size(), 1) > (size_t)lds_max)
-    return set_error(SP_E_LIMIT, "n_meas " + std::to_string(model->n_meas) + " needs " +
-                                     std::to_string(sp::lds_bytes(model->n_meas, (uint32_t)model->channels.size(), 1)) +
-                                     " bytes of LDS; the device allows " + std::to_string(lds_max));
   const int p = choose_path(*model, path);
+  if (sp::lds_bytes(model->n_meas, 1, 1, p) > (size_t)lds_max)
+    return set_error(SP_E_LIMIT, "n_meas " + std::to_string(model->n_meas) + " needs " +
+                                     std::to_string(sp::lds_bytes(model->n_meas, 1, 1, p)) +
+                                     " bytes of LDS; the device allows " + std::to_string(lds_max));
   std::vector<uint8_t> host;
   Layout L;
   try {
@@ -663,13 +754,14 @@ int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_byt
       return set_error(SP_E_INVALID, "device buffer of " + std::to_string(buf_bytes) + " bytes, need " +
                                          std::to_string(L.total));
     host.assign(L.total, 0);
-    if (!H.words.empty()) std::memcpy(&host[L.blocks], H.words.data(), 4 * H.words.size());
+    if (!H.hot.empty()) std::memcpy(&host[L.hot], H.hot.data(), 4 * H.hot.size());
+    if (!H.cold.empty()) std::memcpy(&host[L.cold], H.cold.data(), 4 * H.cold.size());
     if (!H.entries.empty()) std::memcpy(&host[L.entries], H.entries.data(), 4 * H.entries.size());
     for (uint32_t c = 0; c < L.nch; ++c) {
       uint32_t* t = reinterpret_cast<uint32_t*>(&host[L.chans + 64 * (size_t)c]);
       const sp::Channel& ch = model->channels[c];
-      t[0] = ch.kind;
-      for (uint32_t k = 1; k < 16; ++k) t[k] = (uint32_t)std::min<uint64_t>(ch.T[k], 0xFFFFFFFFull);
+      t[0] = ch.kind | (ch.m << 8);
+      for (uint32_t k = 1; k < 16; ++k) t[k] = k < ch.m ? (uint32_t)ch.T[k] : 0xFFFFFFFFu;
     }
     std::memcpy(&host[L.c_mask], model->c_bits.data(), 8 * L.dense_words);
     if (p == SP_PATH_DENSE) {
@@ -692,13 +784,15 @@ int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_byt
   auto* dm = new (std::nothrow) sp_dmodel();
   if (!dm) return set_error(SP_E_NOMEM, "out of host memory");
   const uint8_t* base = (const uint8_t*)d_buf;
-  dm->m.blocks = (const uint4*)(base + L.blocks);
+  dm->m.hot = (const uint4*)(base + L.hot);
+  dm->m.cold = (const uint4*)(base + L.cold);
   dm->m.entries = (const uint32_t*)(base + L.entries);
   dm->m.chans = (const uint32_t*)(base + L.chans);
   dm->m.c_mask = (const uint64_t*)(base + L.c_mask);
   dm->m.dense = p == SP_PATH_DENSE ? (const uint64_t*)(base + L.dense) : nullptr;
   dm->m.nb = L.nb;
   dm->m.nch = L.nch;
+  dm->m.defer_max = kDeferMax;
   dm->m.n_meas = model->n_meas;
   dm->m.dense_words = L.dense_words;
   dm->path = p;

@@ -91,7 +91,7 @@ int stage_and_launch(sp_server* S, int si) {
   const uint32_t R = S->cfg.launch.words_per_group;
   sp::BatchJob* jobs = (sp::BatchJob*)(sl.host + S->L.jobs);
   uint32_t* map = (uint32_t*)(sl.host + S->L.map);
-  uint32_t n_jobs[2] = {0, 0}, groups[2] = {0, 0}, n_meas_max[2] = {0, 0}, nch_max[2] = {0, 0};
+  uint32_t n_jobs[2] = {0, 0}, groups[2] = {0, 0}, n_meas_max[2] = {0, 0};
   std::vector<uint32_t> order[2];
   for (uint32_t i = 0; i < sl.tick.size(); ++i) {
     const sp::serve::Request* r = S->sched.find(sl.tick[i].ticket);
@@ -118,7 +118,6 @@ int stage_and_launch(sp_server* S, int si) {
       g += J.a.n_groups;
       groups[p] += J.a.n_groups;
       n_meas_max[p] = std::max(n_meas_max[p], dm->m.n_meas);
-      nch_max[p] = std::max(nch_max[p], dm->m.nch);
       jobs[j++] = J;
       ++n_jobs[p];
     }
@@ -135,7 +134,7 @@ int stage_and_launch(sp_server* S, int si) {
   for (int p = 0; p < 2; ++p) {
     if (!groups[p]) continue;
     int rc = sp::launch_batch_flat(d_jobs + (p ? n_jobs[0] : 0), d_map + (p ? groups[0] : 0), groups[p], n_meas_max[p],
-                                   nch_max[p], p ? SP_PATH_DENSE : SP_PATH_SPARSE, S->cfg.launch, sl.stream);
+                                   p ? SP_PATH_DENSE : SP_PATH_SPARSE, S->cfg.launch, sl.stream);
     if (rc) return rc;
   }
   e = hipEventRecord(sl.ev, sl.stream);
@@ -266,7 +265,8 @@ int sp_server_submit(sp_server* S, const sp_dmodel* model, uint64_t seed, uint64
   if (model->device != S->device) return set_error(SP_E_INVALID, "model on another device");
   if (first_shot + shots < first_shot) return set_error(SP_E_INVALID, "shot range overflows 64 bits");
   if ((shots + 63) / 64 > 0x7FFFFFFFull) return set_error(SP_E_LIMIT, "too many shots for one request");
-  if (sp::lds_bytes(model->m.n_meas, model->m.nch, S->cfg.launch.words_per_group) > model->lds_max)
+  if (sp::lds_bytes(model->m.n_meas, S->cfg.launch.words_per_group, S->cfg.launch.waves_per_group, model->path) >
+      model->lds_max)
     return set_error(SP_E_LIMIT, "the model's slabs exceed the LDS of one workgroup with this launch shape");
   sp::serve::Request r;
   r.model = model;
