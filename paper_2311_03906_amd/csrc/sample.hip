@@ -271,7 +271,7 @@ struct Hot {
   uint4 blk;    // .x = l / 4
 };
 struct Cold {
-  uint4 meta;   // var0 << 8 | channel + 1 per slot; 0 = no drawn location
+  uint4 meta;   // var0 << 8 | channel + 1 per slot (1 and an empty list: no drawn location)
   uint4 lst;    // start of each slot's entry list
   uint4 end;    // .x = end of slot 3's list
   uint4 pad;
@@ -313,7 +313,7 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = philox4x32_10(cur.blk.x, s_lo[r], s_hi[r], 0u, keys);
     // A slot without a drawn location has threshold 0: it "fires" only at
-    // u = 0, and the fired path drops it by its zero meta.
+    // u = 0, and its empty list makes that a no-op.
     uint64_t f[R][4];
     uint64_t any = 0;
 #pragma unroll
@@ -327,64 +327,98 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
     if (any) {
       const Cold c = load_uniform(cold + b);
       const uint4 d1 = c.meta, d2 = c.lst, d3 = c.end;
-      // Locations fired in more than defer_max lanes are evaluated now (one
-      // pass over the location's list, lane = entry); the others queue
-      // their fired lanes.  At most kQueueCap / (4R) lanes per deferred
-      // location, so that one block's events always fit in an emptied queue.
+      // Locations fired in more than dmax lanes are evaluated now (one pass
+      // over the location's list, lane = entry); the others queue their
+      // fired lanes.  dmax <= kQueueCap / (4R), so that one block's events
+      // always fit in an emptied queue.  A slot without a drawn location
+      // has an empty list (and the coin channel), so its spurious fires at
+      // u = 0 change nothing.
       const uint32_t dmax = min(m.defer_max, sp::kQueueCap / (4u * R));
-      uint32_t need = 0;   // events this block queues
-      bool big = false;    // some location is evaluated now
+      uint32_t need = 0;   // fired lanes of the block
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          if (!pick(d1, s)) f[r][s] = 0;
-          const uint32_t n = (uint32_t)__builtin_popcountll(f[r][s]);
-          need += n;
-          big |= DENSE || n > dmax;
-        }
-      if (!DENSE && qn + need > sp::kQueueCap) {
-        flush_events(m, slab, queue, qn, lane);
-        qn = 0;
+        for (int s = 0; s < 4; ++s) need += (uint32_t)__builtin_popcountll(f[r][s]);
+      bool big = DENSE;    // some location is evaluated now
+      if (!DENSE && need > dmax) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) big |= (uint32_t)__builtin_popcountll(f[r][s]) > dmax;
       }
-      // Issue the entry loads of every location evaluated now first, so
-      // their latencies overlap, then decode and XOR.
-      uint32_t first[4] = {kNoEntry, kNoEntry, kNoEntry, kNoEntry};
-      if (!DENSE && big) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          bool now_s = false;
-#pragma unroll
-          for (int r = 0; r < R; ++r) now_s |= (uint32_t)__builtin_popcountll(f[r][s]) > dmax;
-          const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
-          if (now_s && lo + lane < hi) first[s] = entries[lo + lane];
+      if (!big) {
+        // The usual case: every fired location of the block is queued.
+        if (qn + need > sp::kQueueCap) {
+          flush_events(m, slab, queue, qn, lane);
+          qn = 0;
         }
-      }
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          if (!f[r][s]) continue;
-          const uint32_t meta = pick(d1, s);
-          const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
-          const uint32_t n = (uint32_t)__builtin_popcountll(f[r][s]);
-          if (!DENSE && n <= dmax) {
+          for (int s = 0; s < 4; ++s) {
+            if (!f[r][s]) continue;
             if ((f[r][s] >> lane) & 1ull) {
               const uint32_t pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(f[r][s] >> 32),
                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)f[r][s], 0u));
-              queue[pos] = make_uint4(lo, hi, pick(u[r], s), (meta & 0xFFu) | (lane << 8) | ((uint32_t)r << 14));
+              const uint32_t hi = s < 3 ? pick(d2, s + 1) : d3.x;
+              queue[pos] = make_uint4(pick(d2, s), hi, pick(u[r], s),
+                                      (pick(d1, s) & 0xFFu) | (lane << 8) | ((uint32_t)r << 14));
             }
-            qn += n;
-            continue;
+            qn += (uint32_t)__builtin_popcountll(f[r][s]);
           }
-          const Masks k = decode(m.chans, meta, pick(u[r], s), f[r][s], lane);
-          uint64_t* sl = slab + (size_t)r * m.n_meas;
-          if (DENSE) {
-            evaluate_dense(m, sl, meta, k, lane);
-          } else {
-            if (k.nbits == 1) evaluate_sparse<1>(m, sl, lo, hi, first[s], k, lane);
-            else if (k.nbits == 2) evaluate_sparse<2>(m, sl, lo, hi, first[s], k, lane);
-            else evaluate_sparse<4>(m, sl, lo, hi, first[s], k, lane);
+      } else {
+        uint32_t defer = 0;   // events this block queues
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const uint32_t n = (uint32_t)__builtin_popcountll(f[r][s]);
+            if (!DENSE && n <= dmax) defer += n;
+          }
+        if (!DENSE && qn + defer > sp::kQueueCap) {
+          flush_events(m, slab, queue, qn, lane);
+          qn = 0;
+        }
+        // Issue the entry loads of every location evaluated now first, so
+        // their latencies overlap, then decode and XOR.
+        uint32_t first[4] = {kNoEntry, kNoEntry, kNoEntry, kNoEntry};
+        if (!DENSE) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            bool now_s = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r) now_s |= (uint32_t)__builtin_popcountll(f[r][s]) > dmax;
+            const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
+            if (now_s && lo + lane < hi) first[s] = entries[lo + lane];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            if (!f[r][s]) continue;
+            const uint32_t meta = pick(d1, s);
+            const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
+            if (lo == hi) continue;   // no measurement depends on it (or no drawn location)
+            const uint32_t n = (uint32_t)__builtin_popcountll(f[r][s]);
+            if (!DENSE && n <= dmax) {
+              if ((f[r][s] >> lane) & 1ull) {
+                const uint32_t pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(f[r][s] >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)f[r][s], 0u));
+                queue[pos] = make_uint4(lo, hi, pick(u[r], s), (meta & 0xFFu) | (lane << 8) | ((uint32_t)r << 14));
+              }
+              qn += n;
+              continue;
+            }
+            const Masks k = decode(m.chans, meta, pick(u[r], s), f[r][s], lane);
+            uint64_t* sl = slab + (size_t)r * m.n_meas;
+            if (DENSE) {
+              evaluate_dense(m, sl, meta, k, lane);
+            } else {
+              if (k.nbits == 1) evaluate_sparse<1>(m, sl, lo, hi, first[s], k, lane);
+              else if (k.nbits == 2) evaluate_sparse<2>(m, sl, lo, hi, first[s], k, lane);
+              else evaluate_sparse<4>(m, sl, lo, hi, first[s], k, lane);
+            }
           }
         }
       }
@@ -520,7 +554,8 @@ constexpr uint32_t kDeferMax = 8;
 //           a slot without a drawn location
 //   [4]     the Philox block index l/4
 // and a cold record of 16 words:
-//   [0..3]  meta per slot: var0 << 8 | (channel + 1); 0 = no drawn location
+//   [0..3]  meta per slot: var0 << 8 | (channel + 1); 1 (channel 0, with an
+//           empty list) for a slot without a drawn location
 //   [4..7]  start of the slot's entry list; [8] end of slot 3's list
 // Entry lists: for every variable of the location (bit b), for every row k
 // of its column of M, the word k << 5 | b (so that e >> 2 is the row's LDS
@@ -545,6 +580,7 @@ HostBlocks build_blocks(const sp_model& m) {
       H.hot.insert(H.hot.end(), 8, 0u);
       H.cold.insert(H.cold.end(), 16, 0u);
       uint32_t* w = &H.cold[H.cold.size() - 16];
+      for (int i = 0; i < 4; ++i) w[i] = 1u;   // empty slot: the coin channel, empty list
       for (int i = 4; i <= 8; ++i) w[i] = (uint32_t)H.entries.size();
       H.hot[H.hot.size() - 8 + 4] = (uint32_t)blk;
       cur = blk;
