@@ -163,7 +163,7 @@ int sp_sample(const sp_dmodel* dmodel, uint64_t seed, uint64_t first_shot, uint6
 /* Launch shape of the sampling kernel: a workgroup of waves_per_group
  * wave64s (1..16) owns words_per_group (1, 2 or 4) consecutive 64-shot words,
  * each with its own LDS slab of n_meas uint64 rows (sparse path: plus a
- * 1 KiB event queue per wave).  The output does not depend on the launch
+ * 512-byte event queue per wave).  The output does not depend on the launch
  * shape. */
 typedef struct {
   uint32_t waves_per_group;

@@ -100,7 +100,8 @@ int make_plan(const sp_batch_item* items, size_t n, const sp_launch* launch, int
     P.launch = *launch;
   } else {
     P.launch.waves_per_group = 8;
-    P.launch.words_per_group = 1;
+    P.launch.words_per_group =
+        (lds_max == 0 || sp::lds_bytes(n_meas_max, 2, 8, SP_PATH_SPARSE) * 3 <= lds_max) ? 2 : 1;
   }
   const sp_launch& L = P.launch;
   if (L.waves_per_group < 1 || L.waves_per_group > 16) return set_error(SP_E_INVALID, "waves_per_group must be 1..16");

@@ -63,7 +63,7 @@ int set_error(int code, const std::string& msg);
 constexpr uint32_t kQueueCap = 64;
 
 // LDS bytes of one workgroup: its slabs, then (sparse path) one event
-// queue of kQueueCap 16-byte records per wave.
+// queue of kQueueCap 8-byte records per wave.
 size_t lds_bytes(uint32_t n_meas, uint32_t words_per_group, uint32_t waves_per_group, int path);
 
 // Kernel launchers (sample.hip).

@@ -231,23 +231,27 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // A fired location with few fired lanes is not evaluated at once: each of
-// its fired lanes queues one event {list start, list end, u, channel + 1 |
-// lane << 8 | word << 14} in the wave's LDS queue.  The queue is evaluated
-// with one event per lane: the lane finds its code from u, then walks its
-// location's list and flips its shot's bit in the rows of the code's set
-// bits.  One pass then serves up to 64 fired lanes instead of one location.
-__device__ __forceinline__ void flush_events(const DevModel& m, uint64_t* slab, const uint4* q, uint32_t qn,
+// its fired lanes queues one 8-byte event {u, block << 10 | slot << 8 |
+// lane << 2 | word} in the wave's LDS queue.  The queue is evaluated with
+// one event per lane: the lane reads its location's channel and list from
+// the block's cold record, finds its code from u, then walks the list and
+// flips its shot's bit in the rows of the code's set bits.  Queueing costs a
+// few instructions per fired location; everything else is shared by up to
+// 64 events.
+__device__ __forceinline__ void flush_events(const DevModel& m, uint64_t* slab, const uint2* q, uint32_t qn,
                                              uint32_t lane) {
   wave_sync();
   if (lane < qn) {
-    const uint4 ev = q[lane];
-    const uint32_t u = ev.z, info = ev.w;
-    const uint32_t code = lane_code(m.chans, info & 0xFFu, u);
-    const uint64_t bit = 1ull << ((info >> 8) & 63u);
-    uint64_t* sl = slab + (size_t)(info >> 14) * m.n_meas;
-    const guint32_p p0 = (guint32_p)m.entries + ev.x;
-    const guint32_p p1 = (guint32_p)m.entries + ev.y;
-    guint32_p p = p0;
+    const uint2 ev = q[lane];
+    const uint32_t u = ev.x, info = ev.y;
+    const guint32_p cw = (guint32_p)m.cold + (size_t)(info >> 10) * 16u;   // meta[4] | lst[4] | end
+    const uint32_t s = (info >> 8) & 3u;
+    const uint32_t meta = cw[s], lo = cw[4 + s], hi = cw[5 + s];
+    const uint32_t code = lane_code(m.chans, meta & 0xFFu, u);
+    const uint64_t bit = 1ull << ((info >> 2) & 63u);
+    uint64_t* sl = slab + (size_t)(info & 3u) * m.n_meas;
+    const guint32_p p1 = (guint32_p)m.entries + hi;
+    guint32_p p = (guint32_p)m.entries + lo;
     for (; p + 4 <= p1; p += 4) {   // four loads in flight
       const uint32_t e0 = p[0], e1 = p[1], e2 = p[2], e3 = p[3];
       if (__builtin_amdgcn_ubfe(code, e0, 1)) atomicXor((unsigned long long*)&row_of(sl, e0), (unsigned long long)bit);
@@ -261,6 +265,16 @@ __device__ __forceinline__ void flush_events(const DevModel& m, uint64_t* slab, 
     }
   }
   wave_sync();
+}
+
+// Queues the fired lanes of slot s of word r of block b (fired: this lane
+// drew u <= T_m - 1 there; f: the slot's 64-lane fire mask).
+__device__ __forceinline__ void enqueue(uint2* q, uint32_t qn, uint64_t f, bool fired, uint32_t u, uint32_t tag,
+                                        uint32_t lane4) {
+  if (fired) {
+    const uint32_t pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(f >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)f, 0u));
+    q[pos] = make_uint2(u, tag | lane4);
+  }
 }
 
 // A block's descriptor: the part every block needs (thresholds and the
@@ -281,7 +295,7 @@ struct Cold {
 // UHI: the high word of every lane's shot index is the same (the usual case),
 // which lets the first Philox rounds run on the scalar unit.
 template <int R, int DENSE, bool UHI>
-__device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, uint4* queue, uint32_t g,
+__device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, uint2* queue, uint32_t g,
                                            uint32_t wave, uint32_t n_waves, uint32_t lane) {
   const DevModel& m = a.m;
   uint32_t s_lo[R], s_hi[R];
@@ -325,8 +339,6 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
       any |= f[r][0] | f[r][1] | f[r][2] | f[r][3];
     }
     if (any) {
-      const Cold c = load_uniform(cold + b);
-      const uint4 d1 = c.meta, d2 = c.lst, d3 = c.end;
       // Locations fired in more than dmax lanes are evaluated now (one pass
       // over the location's list, lane = entry); the others queue their
       // fired lanes.  dmax <= kQueueCap / (4R), so that one block's events
@@ -357,16 +369,13 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
             if (!f[r][s]) continue;
-            if ((f[r][s] >> lane) & 1ull) {
-              const uint32_t pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(f[r][s] >> 32),
-                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)f[r][s], 0u));
-              const uint32_t hi = s < 3 ? pick(d2, s + 1) : d3.x;
-              queue[pos] = make_uint4(pick(d2, s), hi, pick(u[r], s),
-                                      (pick(d1, s) & 0xFFu) | (lane << 8) | ((uint32_t)r << 14));
-            }
+            enqueue(queue, qn, f[r][s], pick(u[r], s) <= pick(cur.tm1, s), pick(u[r], s),
+                    (b << 10) | ((uint32_t)s << 8) | (uint32_t)r, lane << 2);
             qn += (uint32_t)__builtin_popcountll(f[r][s]);
           }
       } else {
+        const Cold c = load_uniform(cold + b);
+        const uint4 d1 = c.meta, d2 = c.lst, d3 = c.end;
         uint32_t defer = 0;   // events this block queues
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -402,11 +411,8 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
             if (lo == hi) continue;   // no measurement depends on it (or no drawn location)
             const uint32_t n = (uint32_t)__builtin_popcountll(f[r][s]);
             if (!DENSE && n <= dmax) {
-              if ((f[r][s] >> lane) & 1ull) {
-                const uint32_t pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(f[r][s] >> 32),
-                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)f[r][s], 0u));
-                queue[pos] = make_uint4(lo, hi, pick(u[r], s), (meta & 0xFFu) | (lane << 8) | ((uint32_t)r << 14));
-              }
+              enqueue(queue, qn, f[r][s], pick(u[r], s) <= pick(cur.tm1, s), pick(u[r], s),
+                      (b << 10) | ((uint32_t)s << 8) | (uint32_t)r, lane << 2);
               qn += n;
               continue;
             }
@@ -456,7 +462,7 @@ __device__ __forceinline__ void process_group(const LaunchArgs& a, uint64_t* sla
   const uint64_t first = a.first_shot + (uint64_t)g * R * 64u;
   const uint64_t last = first + (uint64_t)R * 64u - 1u;
   // The wave's event queue follows the slabs (16-byte aligned).
-  uint4* queue = reinterpret_cast<uint4*>(slab + (((size_t)R * m.n_meas + 1u) & ~(size_t)1)) + wave * sp::kQueueCap;
+  uint2* queue = reinterpret_cast<uint2*>(slab + (((size_t)R * m.n_meas + 1u) & ~(size_t)1)) + wave * sp::kQueueCap;
   if ((first >> 32) == (last >> 32)) run_blocks<R, DENSE, true>(a, slab, queue, g, wave, n_waves, lane);
   else run_blocks<R, DENSE, false>(a, slab, queue, g, wave, n_waves, lane);
   __syncthreads();
@@ -568,6 +574,7 @@ struct HostBlocks {
 HostBlocks build_blocks(const sp_model& m) {
   HostBlocks H;
   if (m.n_meas >= (1u << 27)) throw sp::Error(SP_E_LIMIT, "more than 2^27 measurements");
+  if (m.n_locs >= (1u << 24)) throw sp::Error(SP_E_LIMIT, "more than 2^24 locations");
   int64_t cur = -1;
   for (uint32_t l = 0; l < m.n_locs; ++l) {
     const int32_t ch = m.loc_chan[l];
@@ -677,7 +684,7 @@ namespace sp {
 
 size_t lds_bytes(uint32_t n_meas, uint32_t words_per_group, uint32_t waves_per_group, int path) {
   const size_t slabs = ((size_t)n_meas * words_per_group + 1u) / 2u * 16u;
-  return path == SP_PATH_DENSE ? slabs : slabs + (size_t)waves_per_group * kQueueCap * 16u;
+  return path == SP_PATH_DENSE ? slabs : slabs + (size_t)waves_per_group * kQueueCap * 8u;
 }
 
 int launch_sample(const LaunchArgs& a, int path, const sp_launch& L, hipStream_t s) {
@@ -730,13 +737,12 @@ int launch_batch_flat(const BatchJob* jobs, const uint32_t* group_job, uint32_t 
 
 namespace {
 
-// Default launch: 8 waves per group, one word per group (the shape that
-// keeps the draw loop free of register spills).
+// Default launch: 8 waves per group; two words per group when three such
+// groups fit in the LDS of a CU (more shots per descriptor fetch), else one.
 sp_launch default_launch(const sp_dmodel& dm) {
-  (void)dm;
   sp_launch L;
   L.waves_per_group = 8;
-  L.words_per_group = 1;
+  L.words_per_group = (sp::lds_bytes(dm.m.n_meas, 2, 8, dm.path) * 3 <= dm.lds_max) ? 2 : 1;
   return L;
 }
 
