@@ -32,8 +32,19 @@
  *   X_ERROR(p) Y_ERROR(p) Z_ERROR(p) <q...>   Pauli fault with probability p
  *   DEPOLARIZE1(p) <q...>       X, Y, Z each with probability p/3
  *   DEPOLARIZE2(p) <a b ...>    each of the 15 non-identity two-qubit Paulis with p/15
+ *   CX rec[-k] <q>  CY rec[-k] <q>  CZ rec[-k] <q>
+ *                               X / Y / Z on q when the k-th most recent recorded
+ *                               measurement was 1 (the conditional Paulis X^e, Y^e,
+ *                               Z^e of the paper's conclusion; e is that
+ *                               measurement's expression); several (rec, q)
+ *                               pairs may follow, and CX may mix them with
+ *                               CNOT pairs
+ *   DETECTOR[(args)] rec[-k] ...          a detector: the XOR of the named records
+ *                                         (args, e.g. coordinates, are ignored)
+ *   OBSERVABLE_INCLUDE(i) rec[-k] ...     XORs the named records into observable i
  *   TICK
- * p is an exact decimal literal in [0, 1].
+ * p is an exact decimal literal in [0, 1].  rec[-k] (k >= 1) names the k-th
+ * most recent measurement recorded before the instruction.
  *
  * Locations, variables and draws (the sampling contract)
  *   - A location l is, in program order, each target of a one-qubit channel,
@@ -54,9 +65,12 @@
  *     measurement owns one, a determined measurement none.
  *
  * Output layout (M_samples of Eq. 4, packed 64 shots per word)
- *   out[k * ld_words + w], bit b (LSB = 0) = outcome of recorded measurement k
- *   (program order) in shot first_shot + 64 w + b.  Bits for shots >= `shots`
- *   are written as 0; words w >= ceil(shots/64) are not written.
+ *   out[k * ld_words + w], bit b (LSB = 0) = output row k in shot
+ *   first_shot + 64 w + b.  Bits for shots >= `shots` are written as 0; words
+ *   w >= ceil(shots/64) are not written.  Rows are the recorded measurements
+ *   in program order (SP_OUT_MEASUREMENTS), or the detectors in program order
+ *   followed by observables 0, 1, ... (SP_OUT_DETECTORS): each such row is the
+ *   XOR of its records, so its expression is the XOR of their rows of (M, c).
  */
 #ifndef SYMPHASE_H
 #define SYMPHASE_H
@@ -84,7 +98,7 @@ typedef struct sp_dmodel sp_dmodel;   /* device-resident model */
 
 typedef struct {
   uint32_t n_qubits;
-  uint32_t n_meas;        /* recorded measurements = rows of M */
+  uint32_t n_meas;        /* output rows = rows of M (see SP_OUT_*) */
   uint32_t n_locs;        /* locations */
   uint32_t n_vars;        /* variables = columns of M (the constant excluded) */
   uint32_t n_random_meas; /* M/R/MR locations whose outcome is random */
@@ -101,10 +115,21 @@ enum {
   SP_PATH_DENSE = 2   /* per fired variable, XOR into the rows set in its n_m-bit mask */
 };
 
+/* Output rows of a model. */
+enum {
+  SP_OUT_MEASUREMENTS = 0, /* every recorded measurement */
+  SP_OUT_DETECTORS = 1     /* every detector, then every observable */
+};
+
 /* Parses circuit text (len bytes, need not be NUL-terminated).
  * Errors: SP_E_INVALID (null), SP_E_PARSE, SP_E_UNSUPPORTED. */
 int sp_circuit_parse(const char* text, size_t len, sp_circuit** out);
 void sp_circuit_free(sp_circuit* circuit);
+
+/* Counts of a parsed circuit (any pointer may be NULL): qubits, recorded
+ * measurements, detectors, observables (1 + the largest index used). */
+int sp_circuit_counts(const sp_circuit* circuit, uint32_t* n_qubits, uint32_t* n_meas, uint32_t* n_detectors,
+                      uint32_t* n_observables);
 
 /* Algorithm 1, Initialization: one forward pass of the tableau with symbolic
  * phases (Section 3.2.2; Init-C for H/S/CNOT, Init-P for each fault variable,
@@ -113,6 +138,11 @@ void sp_circuit_free(sp_circuit* circuit);
  * of channel instructions in the circuit.  Errors: SP_E_INVALID, SP_E_NOMEM,
  * SP_E_LIMIT. */
 int sp_symbolize(const sp_circuit* circuit, sp_model** out);
+/* The same pass with a choice of output rows (SP_OUT_*): with
+ * SP_OUT_DETECTORS the rows of (M, c) are the detectors' and observables'
+ * expressions, sums of measurement expressions.  Errors as sp_symbolize,
+ * and SP_E_INVALID for an unknown `outputs`. */
+int sp_symbolize_outputs(const sp_circuit* circuit, int outputs, sp_model** out);
 void sp_model_free(sp_model* model);
 
 int sp_model_dims(const sp_model* model, sp_dims* out);

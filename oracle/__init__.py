@@ -64,6 +64,12 @@ def lib():
         L.oracle_sample.argtypes = [P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, U64P,
                                     ctypes.c_size_t, ctypes.c_int]
         L.oracle_sample_shots.argtypes = [P, ctypes.c_uint64, U64P, ctypes.c_size_t, U8P, ctypes.c_int]
+        L.oracle_output_dims.argtypes = [P, IP, IP]
+        L.oracle_rows_from_outcomes.argtypes = [P, ctypes.c_int, U8P, U8P]
+        L.oracle_sample_outputs.argtypes = [P, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                            U64P, ctypes.c_size_t, ctypes.c_int]
+        L.oracle_sample_shots_outputs.argtypes = [P, ctypes.c_int, ctypes.c_uint64, U64P, ctypes.c_size_t, U8P,
+                                                  ctypes.c_int]
         L.oracle_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -82,10 +88,15 @@ def _ptr(a: np.ndarray, ct):
     return a.ctypes.data_as(ctypes.POINTER(ct))
 
 
-class Circuit:
-    """A parsed circuit held by the oracle library."""
+OUTPUTS = {"measurements": 0, "detectors": 1}
 
-    def __init__(self, text: str):
+
+class Circuit:
+    """A parsed circuit held by the oracle library.  `outputs` picks the rows
+    that sample/sample_shots return: "measurements" (every recorded outcome)
+    or "detectors" (every detector, then every observable)."""
+
+    def __init__(self, text: str, outputs: str = "measurements"):
         h = ctypes.c_void_p()
         b = text.encode()
         _check(lib().oracle_parse(b, len(b), ctypes.byref(h)))
@@ -93,6 +104,21 @@ class Circuit:
         nq, nl, nm = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(lib().oracle_dims(h, ctypes.byref(nq), ctypes.byref(nl), ctypes.byref(nm)))
         self.n_qubits, self.n_locs, self.n_meas = nq.value, nl.value, nm.value
+        nd, no = ctypes.c_int(), ctypes.c_int()
+        _check(lib().oracle_output_dims(h, ctypes.byref(nd), ctypes.byref(no)))
+        self.n_detectors, self.n_observables = nd.value, no.value
+        self._out = OUTPUTS[outputs]
+        self.n_rows = self.n_meas if self._out == 0 else self.n_detectors + self.n_observables
+
+    def rows_from_outcomes(self, outcomes) -> np.ndarray:
+        """Output rows (per `outputs`) of one shot from its recorded outcomes."""
+        oc = np.ascontiguousarray(outcomes, dtype=np.uint8)
+        if oc.size == 0:
+            oc = np.zeros(1, dtype=np.uint8)
+        rows = np.zeros(max(self.n_rows, 1), dtype=np.uint8)
+        _check(lib().oracle_rows_from_outcomes(self._h, self._out, _ptr(oc, ctypes.c_uint8),
+                                               _ptr(rows, ctypes.c_uint8)))
+        return rows[: self.n_rows]
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -123,21 +149,21 @@ class Circuit:
 
     def sample(self, seed: int, first_shot: int, shots: int, ld: int | None = None,
                n_threads: int = 0) -> np.ndarray:
-        """Packed outcomes, shape (n_meas, ld) uint64."""
+        """Packed output rows, shape (n_rows, ld) uint64."""
         words = (shots + 63) // 64
         ld = words if ld is None else ld
-        out = np.zeros((max(self.n_meas, 1), max(ld, 1)), dtype=np.uint64)
-        _check(lib().oracle_sample(self._h, seed, first_shot, shots, _ptr(out, ctypes.c_uint64),
-                                   max(ld, 1), n_threads))
-        return out[: self.n_meas, :ld]
+        out = np.zeros((max(self.n_rows, 1), max(ld, 1)), dtype=np.uint64)
+        _check(lib().oracle_sample_outputs(self._h, self._out, seed, first_shot, shots,
+                                           _ptr(out, ctypes.c_uint64), max(ld, 1), n_threads))
+        return out[: self.n_rows, :ld]
 
     def sample_shots(self, seed: int, shot_ids, n_threads: int = 0) -> np.ndarray:
-        """Outcomes of the listed absolute shots, shape (len(shot_ids), n_meas) uint8."""
+        """Output rows of the listed absolute shots, shape (len(shot_ids), n_rows) uint8."""
         ids = np.ascontiguousarray(shot_ids, dtype=np.uint64)
-        out = np.zeros((max(len(ids), 1), max(self.n_meas, 1)), dtype=np.uint8)
-        _check(lib().oracle_sample_shots(self._h, seed, _ptr(ids, ctypes.c_uint64), len(ids),
-                                         _ptr(out, ctypes.c_uint8), n_threads))
-        return out[: len(ids), : self.n_meas]
+        out = np.zeros((max(len(ids), 1), max(self.n_rows, 1)), dtype=np.uint8)
+        _check(lib().oracle_sample_shots_outputs(self._h, self._out, seed, _ptr(ids, ctypes.c_uint64), len(ids),
+                                                 _ptr(out, ctypes.c_uint8), n_threads))
+        return out[: len(ids), : self.n_rows]
 
 
 def philox4x32_10(ctr, key) -> tuple:

@@ -18,6 +18,9 @@
  *
  * Reset R is read as: measure (outcome random or determined, as above), then
  * apply X when the outcome is 1.  MR is M followed by that conditional X.
+ * "CX/CY/CZ rec[-k] q" applies X/Y/Z to q when the k-th most recent recorded
+ * outcome of this shot is 1 (the conditional Paulis of the conclusion).
+ * Detector and observable outputs are XORs of this shot's recorded outcomes.
  *
  * Nothing here is blocked, fused or reordered: one shot is one pass of the
  * textbook algorithm.  Threads only split independent shots.
@@ -54,7 +57,10 @@ const char* oracle_last_error(void) { return g_err; }
 
 enum {
   OP_H, OP_S, OP_X, OP_Y, OP_Z, OP_CX, OP_M, OP_R, OP_MR,
-  OP_XERR, OP_YERR, OP_ZERR, OP_DEP1, OP_DEP2, OP_TICK
+  OP_XERR, OP_YERR, OP_ZERR, OP_DEP1, OP_DEP2, OP_TICK,
+  OP_CY, OP_CZ,       /* parsed names; only record-controlled pairs are kept */
+  OP_FX, OP_FY, OP_FZ, /* Pauli on a qubit if a recorded outcome is 1: (record, qubit) pairs */
+  OP_DET, OP_OBS       /* detector: records; observable: index, then records */
 };
 
 typedef struct {
@@ -73,6 +79,7 @@ struct oracle_circuit {
   op_t* ops;
   int nlocs;
   int nmeas;
+  int ndet, nobs;  /* detectors, observables (1 + largest index) */
   int* loc_kind;   /* ORACLE_LOC_* per location */
 };
 
@@ -160,6 +167,8 @@ static const struct { const char* name; int kind; int has_p; int m; } k_names[] 
   {"MR", OP_MR, 0, 0},      {"X_ERROR", OP_XERR, 1, 1}, {"Y_ERROR", OP_YERR, 1, 1},
   {"Z_ERROR", OP_ZERR, 1, 1}, {"DEPOLARIZE1", OP_DEP1, 1, 3},
   {"DEPOLARIZE2", OP_DEP2, 1, 15}, {"TICK", OP_TICK, 0, 0},
+  {"CY", OP_CY, 0, 0},      {"CZ", OP_CZ, 0, 0},
+  {"DETECTOR", OP_DET, 2, 0}, {"OBSERVABLE_INCLUDE", OP_OBS, 3, 0},
 };
 
 void oracle_free(oracle_circuit* c) {
@@ -180,39 +189,43 @@ int oracle_parse(const char* text, size_t len, oracle_circuit** out) {
   memcpy(buf, text, len);
   buf[len] = 0;
   int rc = 0, lineno = 0;
+  long nmeas_so_far = 0;
   char* save = NULL;
   for (char* line = strtok_r(buf, "\n", &save); line; line = strtok_r(NULL, "\n", &save)) {
     lineno++;
     char* hash = strchr(line, '#');
     if (hash) *hash = 0;
-    char* tokp = NULL;
-    char* tok = strtok_r(line, " \t\r", &tokp);
-    if (!tok) continue;
+    /* head: NAME or NAME(argument); the argument may contain spaces */
+    char* p = line;
+    while (*p == ' ' || *p == '\t' || *p == '\r') p++;
+    if (!*p) continue;
     char name[64], ptext[64];
     ptext[0] = 0;
-    char* paren = strchr(tok, '(');
-    if (paren) {
-      size_t nl = (size_t)(paren - tok);
-      char* close = strchr(paren, ')');
-      if (!close || close[1] != 0 || nl >= sizeof name || (size_t)(close - paren - 1) >= sizeof ptext) {
-        rc = fail(-2, "line %d: malformed '%s'", lineno, tok);
-        break;
-      }
-      memcpy(name, tok, nl);
-      name[nl] = 0;
-      memcpy(ptext, paren + 1, (size_t)(close - paren - 1));
-      ptext[close - paren - 1] = 0;
-    } else {
-      if (strlen(tok) >= sizeof name) { rc = fail(-2, "line %d: name too long", lineno); break; }
-      strcpy(name, tok);
+    int has_arg = 0;
+    size_t nl = 0;
+    while (p[nl] && (isalnum((unsigned char)p[nl]) || p[nl] == '_')) nl++;
+    if (nl == 0 || nl >= sizeof name) { rc = fail(-2, "line %d: malformed instruction", lineno); break; }
+    memcpy(name, p, nl);
+    name[nl] = 0;
+    p += nl;
+    if (*p == '(') {
+      char* close = strchr(p, ')');
+      if (!close || (size_t)(close - p - 1) >= sizeof ptext) { rc = fail(-2, "line %d: malformed '%s('", lineno, name); break; }
+      memcpy(ptext, p + 1, (size_t)(close - p - 1));
+      ptext[close - p - 1] = 0;
+      has_arg = 1;
+      p = close + 1;
     }
-    int kind = -1, has_p = 0, m = 0;
+    if (*p && *p != ' ' && *p != '\t' && *p != '\r') { rc = fail(-2, "line %d: malformed instruction", lineno); break; }
+    int kind = -1, argk = 0, m = 0;
     for (size_t i = 0; i < sizeof k_names / sizeof k_names[0]; i++)
       if (strcmp(name, k_names[i].name) == 0) {
-        kind = k_names[i].kind; has_p = k_names[i].has_p; m = k_names[i].m;
+        kind = k_names[i].kind; argk = k_names[i].has_p; m = k_names[i].m;
       }
     if (kind < 0) { rc = fail(-3, "line %d: unsupported instruction '%s'", lineno, name); break; }
-    if (has_p != (ptext[0] != 0)) { rc = fail(-2, "line %d: probability %s for '%s'", lineno, has_p ? "missing" : "not allowed", name); break; }
+    /* argk: 0 none, 1 probability, 2 optional and ignored, 3 required index */
+    if ((argk == 1 || argk == 3) && !has_arg) { rc = fail(-2, "line %d: missing argument for '%s'", lineno, name); break; }
+    if (argk == 0 && has_arg) { rc = fail(-2, "line %d: argument not allowed for '%s'", lineno, name); break; }
     if (c->nops == cap) {
       cap *= 2;
       c->ops = realloc(c->ops, cap * sizeof(op_t));
@@ -221,7 +234,7 @@ int oracle_parse(const char* text, size_t len, oracle_circuit** out) {
     memset(op, 0, sizeof *op);
     op->kind = kind;
     op->m = m;
-    if (has_p) {
+    if (argk == 1) {
       strcpy(op->ptext, ptext);
       if ((rc = compute_thresholds(ptext, m, op->T)) != 0) {
         char msg[256];
@@ -233,24 +246,93 @@ int oracle_parse(const char* text, size_t len, oracle_circuit** out) {
     }
     int tcap = 8;
     op->targets = malloc(tcap * sizeof(int));
-    for (char* t = strtok_r(NULL, " \t\r", &tokp); t; t = strtok_r(NULL, " \t\r", &tokp)) {
+    int* isrec = malloc(tcap * sizeof(int));
+    if (argk == 3) {
       char* end = NULL;
-      long v = strtol(t, &end, 10);
-      if (!isdigit((unsigned char)t[0]) || *end != 0 || v < 0 || v > 1000000) {
-        rc = fail(-2, "line %d: bad target '%s'", lineno, t);
+      long v = strtol(ptext, &end, 10);
+      if (!isdigit((unsigned char)ptext[0]) || *end != 0 || v < 0 || v > 1000000) {
+        rc = fail(-2, "line %d: bad observable index '%s'", lineno, ptext);
+        c->nops++;
+        free(isrec);
         break;
+      }
+      op->targets[op->ntargets] = (int)v;
+      isrec[op->ntargets++] = 0;
+      if ((int)v + 1 > c->nobs) c->nobs = (int)v + 1;
+    }
+    char* tokp = NULL;
+    for (char* t = strtok_r(p, " \t\r", &tokp); t; t = strtok_r(NULL, " \t\r", &tokp)) {
+      long v;
+      int rec = 0;
+      char* end = NULL;
+      if (strncmp(t, "rec[-", 5) == 0) {
+        v = strtol(t + 5, &end, 10);
+        if (!isdigit((unsigned char)t[5]) || strcmp(end, "]") != 0 || v < 1 || v > nmeas_so_far) {
+          rc = fail(-2, "line %d: bad record target '%s'", lineno, t);
+          break;
+        }
+        v = nmeas_so_far - v;   /* absolute index of the recorded outcome */
+        rec = 1;
+      } else {
+        v = strtol(t, &end, 10);
+        if (!isdigit((unsigned char)t[0]) || *end != 0 || v < 0 || v > 1000000) {
+          rc = fail(-2, "line %d: bad target '%s'", lineno, t);
+          break;
+        }
       }
       if (op->ntargets == tcap) {
         tcap *= 2;
         op->targets = realloc(op->targets, tcap * sizeof(int));
+        isrec = realloc(isrec, tcap * sizeof(int));
       }
+      isrec[op->ntargets] = rec;
       op->targets[op->ntargets++] = (int)v;
-      if ((int)v + 1 > c->nq) c->nq = (int)v + 1;
+      if (!rec && (int)v + 1 > c->nq) c->nq = (int)v + 1;
     }
     c->nops++;
+    if (rc) { free(isrec); break; }
+    /* target kinds per instruction */
+    if (kind == OP_DET || kind == OP_OBS) {
+      for (int i = (kind == OP_OBS); i < op->ntargets; i++)
+        if (!isrec[i]) { rc = fail(-2, "line %d: '%s' takes record targets", lineno, name); break; }
+      if (kind == OP_DET) c->ndet++;
+    } else if (kind == OP_CX || kind == OP_CY || kind == OP_CZ) {
+      if (op->ntargets % 2) rc = fail(-2, "line %d: odd number of targets", lineno);
+      for (int i = 0; !rc && i < op->ntargets; i += 2) {
+        if (isrec[i + 1]) rc = fail(-2, "line %d: record as the target of a pair", lineno);
+        else if (!isrec[i] && kind != OP_CX) rc = fail(-3, "line %d: quantum '%s' not supported", lineno, name);
+        else if (!isrec[i] && op->targets[i] == op->targets[i + 1]) rc = fail(-2, "line %d: pair on one qubit", lineno);
+      }
+      /* one op per pair, in order: CNOT or the controlled Pauli */
+      if (!rc) {
+        int np = op->ntargets / 2;
+        int* tg = op->targets;
+        int* rc_of = isrec;
+        c->nops--;   /* the parsed op is replaced by one op per pair */
+        for (int i = 0; i < np; i++) {
+          if (c->nops == cap) {
+            cap *= 2;
+            c->ops = realloc(c->ops, cap * sizeof(op_t));
+          }
+          op_t* po = &c->ops[c->nops++];
+          memset(po, 0, sizeof *po);
+          po->kind = rc_of[2 * i] ? (kind == OP_CX ? OP_FX : kind == OP_CY ? OP_FY : OP_FZ) : OP_CX;
+          po->ntargets = 2;
+          po->targets = malloc(2 * sizeof(int));
+          po->targets[0] = tg[2 * i];
+          po->targets[1] = tg[2 * i + 1];
+        }
+        free(tg);
+      }
+    } else {
+      for (int i = 0; i < op->ntargets; i++)
+        if (isrec[i]) { rc = fail(-2, "line %d: '%s' takes qubit targets", lineno, name); break; }
+    }
+    free(isrec);
     if (rc) break;
+    if (kind == OP_M || kind == OP_MR) nmeas_so_far += op->ntargets;
     if (kind == OP_TICK && op->ntargets) { rc = fail(-2, "line %d: TICK takes no targets", lineno); break; }
-    if (kind == OP_CX || kind == OP_DEP2) {
+    if (kind == OP_DEP2) {
       if (op->ntargets % 2) { rc = fail(-2, "line %d: odd number of targets", lineno); break; }
       for (int i = 0; i < op->ntargets; i += 2)
         if (op->targets[i] == op->targets[i + 1]) { rc = fail(-2, "line %d: pair on one qubit", lineno); break; }
@@ -591,7 +673,11 @@ static int run_shot(const oracle_circuit* c, tab_t* t, const codesrc_t* src, uin
           if (op->kind != OP_M && m) gate_pauli(t, q[j], 1, 0);
         }
         break;
-      case OP_TICK: break;
+      case OP_FX: case OP_FY: case OP_FZ:
+        for (int j = 0; j < op->ntargets; j += 2)
+          if (outcomes[q[j]]) gate_pauli(t, q[j + 1], op->kind != OP_FZ, op->kind != OP_FX);
+        break;
+      case OP_TICK: case OP_DET: case OP_OBS: case OP_CY: case OP_CZ: break;
     }
     if (check && check_relations(t) != 0)
       return fail(-5, "tableau relations violated after instruction %d", oi);
@@ -611,12 +697,49 @@ int oracle_run_codes(const oracle_circuit* c, const uint8_t* codes, uint8_t* out
   return rc;
 }
 
+/* Output rows of one shot from its recorded outcomes: the outcomes
+ * themselves (outputs 0), or each detector's XOR of its records followed by
+ * each observable's (outputs 1). */
+static int n_rows(const oracle_circuit* c, int outputs) { return outputs ? c->ndet + c->nobs : c->nmeas; }
+
+static void shot_rows(const oracle_circuit* c, int outputs, const uint8_t* oc, uint8_t* rows) {
+  if (!outputs) {
+    memcpy(rows, oc, (size_t)c->nmeas);
+    return;
+  }
+  memset(rows, 0, (size_t)(c->ndet + c->nobs));
+  int d = 0;
+  for (int i = 0; i < c->nops; i++) {
+    const op_t* op = &c->ops[i];
+    if (op->kind == OP_DET) {
+      for (int j = 0; j < op->ntargets; j++) rows[d] ^= oc[op->targets[j]];
+      d++;
+    } else if (op->kind == OP_OBS) {
+      for (int j = 1; j < op->ntargets; j++) rows[c->ndet + op->targets[0]] ^= oc[op->targets[j]];
+    }
+  }
+}
+
+int oracle_output_dims(const oracle_circuit* c, int* n_detectors, int* n_observables) {
+  if (!c) return fail(-1, "null argument");
+  if (n_detectors) *n_detectors = c->ndet;
+  if (n_observables) *n_observables = c->nobs;
+  return 0;
+}
+
+int oracle_rows_from_outcomes(const oracle_circuit* c, int outputs, const uint8_t* outcomes, uint8_t* rows) {
+  if (!c || !outcomes || !rows) return fail(-1, "null argument");
+  shot_rows(c, outputs, outcomes, rows);
+  return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* many shots                                                          */
 /* ------------------------------------------------------------------ */
 
 typedef struct {
   const oracle_circuit* c;
+  int outputs;
   uint64_t seed, first_shot, shots;
   uint64_t* out;
   size_t ld;
@@ -631,17 +754,21 @@ static void* sample_words(void* arg) {
   const oracle_circuit* c = j->c;
   tab_t t;
   tab_alloc(&t, c->nq);
+  const int nr = n_rows(c, j->outputs);
   uint8_t* oc = malloc((size_t)(c->nmeas ? c->nmeas : 1));
+  uint8_t* rows = malloc((size_t)(nr ? nr : 1));
   for (uint64_t w = j->lo; w < j->hi && j->rc == 0; w++) {
     for (int b = 0; b < 64; b++) {
       uint64_t i = w * 64 + (uint64_t)b;
       if (i >= j->shots) break;
       codesrc_t src = {NULL, j->seed, j->first_shot + i};
       if ((j->rc = run_shot(c, &t, &src, oc, NULL, 0)) != 0) break;
-      for (int k = 0; k < c->nmeas; k++)
-        if (oc[k]) j->out[(size_t)k * j->ld + w] |= (uint64_t)1 << b;
+      shot_rows(c, j->outputs, oc, rows);
+      for (int k = 0; k < nr; k++)
+        if (rows[k]) j->out[(size_t)k * j->ld + w] |= (uint64_t)1 << b;
     }
   }
+  free(rows);
   free(oc);
   tab_free(&t);
   return NULL;
@@ -652,10 +779,14 @@ static void* sample_list(void* arg) {
   const oracle_circuit* c = j->c;
   tab_t t;
   tab_alloc(&t, c->nq);
+  const int nr = n_rows(c, j->outputs);
+  uint8_t* oc = malloc((size_t)(c->nmeas ? c->nmeas : 1));
   for (uint64_t i = j->lo; i < j->hi && j->rc == 0; i++) {
     codesrc_t src = {NULL, j->seed, j->shot_ids[i]};
-    j->rc = run_shot(c, &t, &src, j->outcomes + i * (size_t)c->nmeas, NULL, 0);
+    if ((j->rc = run_shot(c, &t, &src, oc, NULL, 0)) != 0) break;
+    shot_rows(c, j->outputs, oc, j->outcomes + i * (size_t)nr);
   }
+  free(oc);
   tab_free(&t);
   return NULL;
 }
@@ -690,21 +821,33 @@ static int run_jobs(job_t* proto, uint64_t work, int n_threads, void* (*fn)(void
   return rc;
 }
 
-int oracle_sample(const oracle_circuit* c, uint64_t seed, uint64_t first_shot, uint64_t shots,
-                  uint64_t* out, size_t ld, int n_threads) {
+int oracle_sample_outputs(const oracle_circuit* c, int outputs, uint64_t seed, uint64_t first_shot, uint64_t shots,
+                          uint64_t* out, size_t ld, int n_threads) {
   if (!c || (!out && shots)) return fail(-1, "null argument");
+  if (outputs != 0 && outputs != 1) return fail(-1, "unknown outputs %d", outputs);
   uint64_t words = (shots + 63) / 64;
   if (ld < words) return fail(-1, "ld %zu < %llu words", ld, (unsigned long long)words);
-  memset(out, 0, (size_t)c->nmeas * ld * 8);
+  memset(out, 0, (size_t)n_rows(c, outputs) * ld * 8);
   if (!shots) return 0;
-  job_t proto = {c, seed, first_shot, shots, out, ld, NULL, NULL, 0, 0, 0};
+  job_t proto = {c, outputs, seed, first_shot, shots, out, ld, NULL, NULL, 0, 0, 0};
   return run_jobs(&proto, words, n_threads, sample_words);
+}
+
+int oracle_sample(const oracle_circuit* c, uint64_t seed, uint64_t first_shot, uint64_t shots,
+                  uint64_t* out, size_t ld, int n_threads) {
+  return oracle_sample_outputs(c, 0, seed, first_shot, shots, out, ld, n_threads);
+}
+
+int oracle_sample_shots_outputs(const oracle_circuit* c, int outputs, uint64_t seed, const uint64_t* shot_ids,
+                                size_t n, uint8_t* rows, int n_threads) {
+  if (!c || (n && (!shot_ids || !rows))) return fail(-1, "null argument");
+  if (outputs != 0 && outputs != 1) return fail(-1, "unknown outputs %d", outputs);
+  if (!n) return 0;
+  job_t proto = {c, outputs, seed, 0, 0, NULL, 0, shot_ids, rows, 0, 0, 0};
+  return run_jobs(&proto, n, n_threads, sample_list);
 }
 
 int oracle_sample_shots(const oracle_circuit* c, uint64_t seed, const uint64_t* shot_ids,
                         size_t n, uint8_t* outcomes, int n_threads) {
-  if (!c || (n && (!shot_ids || !outcomes))) return fail(-1, "null argument");
-  if (!n) return 0;
-  job_t proto = {c, seed, 0, 0, NULL, 0, shot_ids, outcomes, 0, 0, 0};
-  return run_jobs(&proto, n, n_threads, sample_list);
+  return oracle_sample_shots_outputs(c, 0, seed, shot_ids, n, outcomes, n_threads);
 }

@@ -80,6 +80,16 @@ int oracle_sample(const oracle_circuit* c, uint64_t seed, uint64_t first_shot, u
 int oracle_sample_shots(const oracle_circuit* c, uint64_t seed, const uint64_t* shot_ids,
                         size_t n, uint8_t* outcomes, int n_threads);
 
+/* Detector outputs.  outputs = 0: rows are the recorded measurements (as
+ * above); outputs = 1: rows are the detectors in program order, then
+ * observables 0, 1, ...; each is the XOR of the shot's outcomes it names. */
+int oracle_output_dims(const oracle_circuit* c, int* n_detectors, int* n_observables);
+int oracle_rows_from_outcomes(const oracle_circuit* c, int outputs, const uint8_t* outcomes, uint8_t* rows);
+int oracle_sample_outputs(const oracle_circuit* c, int outputs, uint64_t seed, uint64_t first_shot, uint64_t shots,
+                          uint64_t* out, size_t ld, int n_threads);
+int oracle_sample_shots_outputs(const oracle_circuit* c, int outputs, uint64_t seed, const uint64_t* shot_ids,
+                                size_t n, uint8_t* rows, int n_threads);
+
 const char* oracle_last_error(void);
 
 #ifdef __cplusplus

@@ -65,6 +65,9 @@ class Circuit:
         h = ctypes.c_void_p()
         check(lib().sp_circuit_parse(b, len(b), ctypes.byref(h)))
         self._h = h
+        v = [ctypes.c_uint32() for _ in range(4)]
+        check(lib().sp_circuit_counts(h, *[ctypes.byref(x) for x in v]))
+        self.n_qubits, self.n_meas, self.n_detectors, self.n_observables = (x.value for x in v)
 
     @property
     def handle(self):
@@ -74,14 +77,23 @@ class Circuit:
         _rel(self, "sp_circuit_free")
 
 
-class Model:
-    """(M, c) and the location table (sp_symbolize): Algorithm 1, Initialization."""
+_OUTPUTS = {"measurements": _capi.SP_OUT_MEASUREMENTS, "detectors": _capi.SP_OUT_DETECTORS}
 
-    def __init__(self, circuit: Circuit | str):
+
+class Model:
+    """(M, c) and the location table (sp_symbolize_outputs): Algorithm 1,
+    Initialization.  outputs="measurements" gives one row per recorded
+    measurement; outputs="detectors" one row per detector, then one per
+    observable."""
+
+    def __init__(self, circuit: Circuit | str, outputs: str = "measurements"):
         if isinstance(circuit, str):
             circuit = Circuit(circuit)
+        if outputs not in _OUTPUTS:
+            raise ValueError(f"outputs must be one of {sorted(_OUTPUTS)}")
+        self.outputs = outputs
         h = ctypes.c_void_p()
-        check(lib().sp_symbolize(circuit.handle, ctypes.byref(h)))
+        check(lib().sp_symbolize_outputs(circuit.handle, _OUTPUTS[outputs], ctypes.byref(h)))
         self._h = h
         d = sp_dims()
         check(lib().sp_model_dims(h, ctypes.byref(d)))

@@ -18,10 +18,12 @@ SP_E_BUDGET, SP_E_TIMEOUT = -7, -8
 SP_REQ_QUEUED, SP_REQ_ACTIVE, SP_REQ_DONE, SP_REQ_FAILED = 0, 1, 2, 3
 SP_PATH_AUTO, SP_PATH_SPARSE, SP_PATH_DENSE = 0, 1, 2
 SP_SCHED_PERSISTENT, SP_SCHED_FLAT = 0, 1
+SP_OUT_MEASUREMENTS, SP_OUT_DETECTORS = 0, 1
 
 #: every function the header declares (checked by the tests)
 EXPORTS = (
-    "sp_circuit_parse", "sp_circuit_free", "sp_symbolize", "sp_model_free", "sp_model_dims",
+    "sp_circuit_parse", "sp_circuit_free", "sp_circuit_counts", "sp_symbolize", "sp_symbolize_outputs",
+    "sp_model_free", "sp_model_dims",
     "sp_model_expected_work",
     "sp_model_export_dense", "sp_model_export_csc", "sp_model_export_vars", "sp_model_device_bytes",
     "sp_model_upload", "sp_dmodel_free", "sp_dmodel_dims", "sp_dmodel_get_launch", "sp_dmodel_set_launch",
@@ -86,6 +88,9 @@ def lib():
         "sp_circuit_parse": ([ctypes.c_char_p, sz, P(vp)], ctypes.c_int),
         "sp_circuit_free": ([vp], None),
         "sp_symbolize": ([vp, P(vp)], ctypes.c_int),
+        "sp_symbolize_outputs": ([vp, ctypes.c_int, P(vp)], ctypes.c_int),
+        "sp_circuit_counts": ([vp, P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32)],
+                              ctypes.c_int),
         "sp_model_free": ([vp], None),
         "sp_model_dims": ([vp, P(sp_dims)], ctypes.c_int),
         "sp_model_expected_work": ([vp, P(ctypes.c_double), P(ctypes.c_double)], ctypes.c_int),

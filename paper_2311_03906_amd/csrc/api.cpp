@@ -41,14 +41,28 @@ int sp_circuit_parse(const char* text, size_t len, sp_circuit** out) {
 
 void sp_circuit_free(sp_circuit* c) { delete c; }
 
-int sp_symbolize(const sp_circuit* c, sp_model** out) {
+int sp_circuit_counts(const sp_circuit* c, uint32_t* n_qubits, uint32_t* n_meas, uint32_t* n_detectors,
+                      uint32_t* n_observables) {
+  if (!c) return set_error(SP_E_INVALID, "null circuit");
+  if (n_qubits) *n_qubits = c->n_qubits;
+  if (n_meas) *n_meas = c->n_meas;
+  if (n_detectors) *n_detectors = c->n_detectors;
+  if (n_observables) *n_observables = c->n_observables;
+  return SP_OK;
+}
+
+int sp_symbolize_outputs(const sp_circuit* c, int outputs, sp_model** out) {
   SP_GUARD_BEGIN
   if (!c || !out) return set_error(SP_E_INVALID, "null argument");
   *out = nullptr;
-  *out = sp::symbolize(*c);
+  if (outputs != SP_OUT_MEASUREMENTS && outputs != SP_OUT_DETECTORS)
+    return set_error(SP_E_INVALID, "unknown outputs " + std::to_string(outputs));
+  *out = sp::symbolize(*c, outputs);
   return SP_OK;
   SP_GUARD_END
 }
+
+int sp_symbolize(const sp_circuit* c, sp_model** out) { return sp_symbolize_outputs(c, SP_OUT_MEASUREMENTS, out); }
 
 void sp_model_free(sp_model* m) { delete m; }
 

@@ -5,6 +5,7 @@
 // Pauli, two-qubit depolarizing with p/15 per non-identity Pauli.  Each is
 // sampled from one 32-bit draw u by integer thresholds
 // T_k = floor(k * p * 2^32 / m), computed exactly from the decimal literal.
+#include <algorithm>
 #include <cctype>
 #include <cstring>
 #include <map>
@@ -79,33 +80,68 @@ Channel make_channel(uint32_t kind, uint32_t m, const std::string& ptext) {
   return ch;
 }
 
+// How an instruction takes its parenthesized argument.
+enum ArgKind : uint8_t { ARG_NONE, ARG_PROB, ARG_IGNORED, ARG_INDEX };
+
 struct NameInfo {
   OpKind kind;
-  bool noise;
+  ArgKind arg;
   uint32_t chan_kind;
   uint32_t m;
 };
 
 const std::map<std::string, NameInfo>& names() {
   static const std::map<std::string, NameInfo> tbl = {
-      {"H", {OpKind::H, false, 0, 0}},
-      {"S", {OpKind::S, false, 0, 0}},
-      {"X", {OpKind::X, false, 0, 0}},
-      {"Y", {OpKind::Y, false, 0, 0}},
-      {"Z", {OpKind::Z, false, 0, 0}},
-      {"CX", {OpKind::CX, false, 0, 0}},
-      {"CNOT", {OpKind::CX, false, 0, 0}},
-      {"M", {OpKind::M, false, 0, 0}},
-      {"R", {OpKind::R, false, 0, 0}},
-      {"MR", {OpKind::MR, false, 0, 0}},
-      {"TICK", {OpKind::TICK, false, 0, 0}},
-      {"X_ERROR", {OpKind::XERR, true, CH_XERR, 1}},
-      {"Y_ERROR", {OpKind::YERR, true, CH_YERR, 1}},
-      {"Z_ERROR", {OpKind::ZERR, true, CH_ZERR, 1}},
-      {"DEPOLARIZE1", {OpKind::DEP1, true, CH_DEP1, 3}},
-      {"DEPOLARIZE2", {OpKind::DEP2, true, CH_DEP2, 15}},
+      {"H", {OpKind::H, ARG_NONE, 0, 0}},
+      {"S", {OpKind::S, ARG_NONE, 0, 0}},
+      {"X", {OpKind::X, ARG_NONE, 0, 0}},
+      {"Y", {OpKind::Y, ARG_NONE, 0, 0}},
+      {"Z", {OpKind::Z, ARG_NONE, 0, 0}},
+      {"CX", {OpKind::CX, ARG_NONE, 0, 0}},
+      {"CNOT", {OpKind::CX, ARG_NONE, 0, 0}},
+      {"CY", {OpKind::FY, ARG_NONE, 0, 0}},
+      {"CZ", {OpKind::FZ, ARG_NONE, 0, 0}},
+      {"M", {OpKind::M, ARG_NONE, 0, 0}},
+      {"R", {OpKind::R, ARG_NONE, 0, 0}},
+      {"MR", {OpKind::MR, ARG_NONE, 0, 0}},
+      {"TICK", {OpKind::TICK, ARG_NONE, 0, 0}},
+      {"DETECTOR", {OpKind::DET, ARG_IGNORED, 0, 0}},
+      {"OBSERVABLE_INCLUDE", {OpKind::OBS, ARG_INDEX, 0, 0}},
+      {"X_ERROR", {OpKind::XERR, ARG_PROB, CH_XERR, 1}},
+      {"Y_ERROR", {OpKind::YERR, ARG_PROB, CH_YERR, 1}},
+      {"Z_ERROR", {OpKind::ZERR, ARG_PROB, CH_ZERR, 1}},
+      {"DEPOLARIZE1", {OpKind::DEP1, ARG_PROB, CH_DEP1, 3}},
+      {"DEPOLARIZE2", {OpKind::DEP2, ARG_PROB, CH_DEP2, 15}},
   };
   return tbl;
+}
+
+// A target: a qubit index, or a measurement record rec[-k] (k >= 1).
+struct Target {
+  bool rec;
+  uint32_t v;   // qubit, or k
+};
+
+bool parse_uint(const std::string& t, uint32_t limit, uint32_t* v) {
+  if (t.empty() || t.size() > 9) return false;
+  for (char ch : t)
+    if (!std::isdigit((unsigned char)ch)) return false;
+  const unsigned long x = std::stoul(t);
+  if (x > limit) return false;
+  *v = (uint32_t)x;
+  return true;
+}
+
+Target parse_target(const std::string& t, const std::string& where) {
+  Target r{false, 0};
+  if (t.compare(0, 5, "rec[-") == 0 && t.size() > 6 && t.back() == ']') {
+    r.rec = true;
+    if (!parse_uint(t.substr(5, t.size() - 6), 1u << 30, &r.v) || r.v == 0)
+      throw Error(SP_E_PARSE, where + "bad record target '" + t + "'");
+    return r;
+  }
+  if (!parse_uint(t, 1000000, &r.v)) throw Error(SP_E_PARSE, where + "bad target '" + t + "'");
+  return r;
 }
 
 }  // namespace
@@ -119,39 +155,112 @@ sp_circuit* parse_circuit(const char* text, size_t len) {
     std::istringstream lines(all);
     std::string line;
     int lineno = 0;
-    uint64_t n_locs = 0, n_meas = 0;
+    uint64_t n_locs = 0, n_meas = 0, n_det = 0, n_obs = 0;
     uint32_t max_q = 0;
     bool any_q = false;
+    auto use_qubit = [&](uint32_t q) {
+      if (!any_q || q > max_q) max_q = q;
+      any_q = true;
+    };
     while (std::getline(lines, line)) {
       ++lineno;
       auto hash = line.find('#');
       if (hash != std::string::npos) line.resize(hash);
-      std::istringstream toks(line);
-      std::string head;
-      if (!(toks >> head)) continue;
       const std::string where = "line " + std::to_string(lineno) + ": ";
-      std::string name = head, ptext;
-      auto lp = head.find('(');
-      if (lp != std::string::npos) {
-        if (head.back() != ')' || head.size() < lp + 3)
-          throw Error(SP_E_PARSE, where + "malformed '" + head + "'");
-        name = head.substr(0, lp);
-        ptext = head.substr(lp + 1, head.size() - lp - 2);
+      // Head: a name, optionally followed by "(argument)".
+      size_t i = 0;
+      while (i < line.size() && std::isspace((unsigned char)line[i])) ++i;
+      if (i == line.size()) continue;
+      size_t j = i;
+      while (j < line.size() && (std::isalnum((unsigned char)line[j]) || line[j] == '_')) ++j;
+      const std::string name = line.substr(i, j - i);
+      std::string arg;
+      bool has_arg = false;
+      if (j < line.size() && line[j] == '(') {
+        const size_t close = line.find(')', j);
+        if (close == std::string::npos) throw Error(SP_E_PARSE, where + "unclosed '(' after '" + name + "'");
+        arg = line.substr(j + 1, close - j - 1);
+        has_arg = true;
+        j = close + 1;
       }
+      if (name.empty() || (j < line.size() && !std::isspace((unsigned char)line[j])))
+        throw Error(SP_E_PARSE, where + "malformed instruction");
       auto it = names().find(name);
       if (it == names().end()) throw Error(SP_E_UNSUPPORTED, where + "unsupported instruction '" + name + "'");
       const NameInfo& ni = it->second;
-      if (ni.noise != (lp != std::string::npos))
-        throw Error(SP_E_PARSE, where + (ni.noise ? "missing probability for '" : "unexpected argument for '") + name + "'");
+      if (ni.arg == ARG_PROB && !has_arg) throw Error(SP_E_PARSE, where + "missing probability for '" + name + "'");
+      if ((ni.arg == ARG_NONE) && has_arg) throw Error(SP_E_PARSE, where + "unexpected argument for '" + name + "'");
+      if (ni.arg == ARG_INDEX && !has_arg) throw Error(SP_E_PARSE, where + "missing index for '" + name + "'");
+      std::vector<Target> tg;
+      {
+        std::istringstream toks(line.substr(j));
+        std::string t;
+        while (toks >> t) tg.push_back(parse_target(t, where));
+      }
+      // Record targets -> absolute measurement indices.
+      auto record = [&](const Target& t) -> uint32_t {
+        if (!t.rec) throw Error(SP_E_PARSE, where + "'" + name + "' takes record targets rec[-k]");
+        if (t.v > n_meas) throw Error(SP_E_PARSE, where + "rec[-" + std::to_string(t.v) + "] precedes the first measurement");
+        return (uint32_t)(n_meas - t.v);
+      };
+      auto qubit = [&](const Target& t) -> uint32_t {
+        if (t.rec) throw Error(SP_E_PARSE, where + "'" + name + "' takes qubit targets here");
+        use_qubit(t.v);
+        return t.v;
+      };
+      auto push = [&](Op&& op) { c->ops.push_back(std::move(op)); };
+
+      if (ni.kind == OpKind::CX || ni.kind == OpKind::FY || ni.kind == OpKind::FZ) {
+        // (control, target) pairs: qubit pairs are CNOTs (CX only), record
+        // pairs are Paulis controlled by a measurement.
+        if (tg.size() % 2) throw Error(SP_E_PARSE, where + "targets must come in pairs");
+        const OpKind fk = ni.kind == OpKind::CX ? OpKind::FX : ni.kind;
+        Op cur;
+        cur.kind = OpKind::TICK;
+        for (size_t k = 0; k < tg.size(); k += 2) {
+          const bool fb = tg[k].rec;
+          if (!fb && ni.kind != OpKind::CX)
+            throw Error(SP_E_UNSUPPORTED, where + "quantum '" + name + "' is outside the gate set (H, S, CNOT)");
+          const OpKind kind = fb ? fk : OpKind::CX;
+          if (cur.kind != kind && !cur.targets.empty()) push(std::move(cur));
+          if (cur.kind != kind || cur.targets.empty()) { cur = Op(); cur.kind = kind; }
+          if (fb) {
+            cur.targets.push_back(record(tg[k]));
+            cur.targets.push_back(qubit(tg[k + 1]));
+          } else {
+            const uint32_t a = qubit(tg[k]), b = qubit(tg[k + 1]);
+            if (a == b) throw Error(SP_E_PARSE, where + "pair acts twice on one qubit");
+            cur.targets.push_back(a);
+            cur.targets.push_back(b);
+          }
+        }
+        if (!cur.targets.empty()) push(std::move(cur));
+        continue;
+      }
       Op op;
       op.kind = ni.kind;
-      if (ni.noise) {
-        auto key = std::make_pair(ni.chan_kind, ptext);
+      if (ni.kind == OpKind::DET) {
+        for (const Target& t : tg) op.targets.push_back(record(t));
+        ++n_det;
+        push(std::move(op));
+        continue;
+      }
+      if (ni.kind == OpKind::OBS) {
+        uint32_t idx = 0;
+        if (!parse_uint(arg, 1000000, &idx)) throw Error(SP_E_PARSE, where + "bad observable index '" + arg + "'");
+        op.targets.push_back(idx);
+        for (const Target& t : tg) op.targets.push_back(record(t));
+        n_obs = std::max<uint64_t>(n_obs, (uint64_t)idx + 1);
+        push(std::move(op));
+        continue;
+      }
+      if (ni.arg == ARG_PROB) {
+        auto key = std::make_pair(ni.chan_kind, arg);
         auto ci = chan_index.find(key);
         if (ci == chan_index.end()) {
           Channel ch;
           try {
-            ch = make_channel(ni.chan_kind, ni.m, ptext);
+            ch = make_channel(ni.chan_kind, ni.m, arg);
           } catch (const Error& e) {
             throw Error(e.code, where + e.what());
           }
@@ -160,22 +269,12 @@ sp_circuit* parse_circuit(const char* text, size_t len) {
         }
         op.chan = ci->second;
       }
-      std::string t;
-      while (toks >> t) {
-        if (t.empty() || t.size() > 9) throw Error(SP_E_PARSE, where + "bad target '" + t + "'");
-        for (char ch : t)
-          if (!std::isdigit((unsigned char)ch)) throw Error(SP_E_PARSE, where + "bad target '" + t + "'");
-        uint32_t q = (uint32_t)std::stoul(t);
-        if (q > 1000000) throw Error(SP_E_PARSE, where + "qubit index too large");
-        op.targets.push_back(q);
-        if (!any_q || q > max_q) max_q = q;
-        any_q = true;
-      }
+      for (const Target& t : tg) op.targets.push_back(qubit(t));
       if (op.kind == OpKind::TICK && !op.targets.empty()) throw Error(SP_E_PARSE, where + "TICK takes no targets");
-      if (op.kind == OpKind::CX || op.kind == OpKind::DEP2) {
+      if (op.kind == OpKind::DEP2) {
         if (op.targets.size() % 2) throw Error(SP_E_PARSE, where + "targets must come in pairs");
-        for (size_t i = 0; i < op.targets.size(); i += 2)
-          if (op.targets[i] == op.targets[i + 1]) throw Error(SP_E_PARSE, where + "pair acts twice on one qubit");
+        for (size_t k = 0; k < op.targets.size(); k += 2)
+          if (op.targets[k] == op.targets[k + 1]) throw Error(SP_E_PARSE, where + "pair acts twice on one qubit");
       }
       switch (op.kind) {
         case OpKind::XERR: case OpKind::YERR: case OpKind::ZERR: case OpKind::DEP1: case OpKind::R:
@@ -187,12 +286,15 @@ sp_circuit* parse_circuit(const char* text, size_t len) {
           break;
         default: break;
       }
-      if (n_locs >= (1ull << 32)) throw Error(SP_E_LIMIT, "more than 2^32 locations");
-      c->ops.push_back(std::move(op));
+      if (n_locs >= (1ull << 32) || n_meas >= (1ull << 31)) throw Error(SP_E_LIMIT, "more than 2^32 locations");
+      push(std::move(op));
     }
+    if (n_det >= (1ull << 31) || n_det + n_obs >= (1ull << 31)) throw Error(SP_E_LIMIT, "too many detectors");
     c->n_qubits = any_q ? max_q + 1 : 0;
     c->n_locs = (uint32_t)n_locs;
     c->n_meas = (uint32_t)n_meas;
+    c->n_detectors = (uint32_t)n_det;
+    c->n_observables = (uint32_t)n_obs;
     return c;
   } catch (...) {
     delete c;

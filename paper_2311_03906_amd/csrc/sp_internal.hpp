@@ -16,7 +16,11 @@ struct Error : std::runtime_error {
   Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
-enum class OpKind : uint8_t { H, S, X, Y, Z, CX, M, R, MR, XERR, YERR, ZERR, DEP1, DEP2, TICK };
+// FX/FY/FZ: a Pauli on a qubit controlled by a recorded measurement (targets:
+// pairs of absolute measurement index, qubit).  DET: a detector (targets:
+// absolute measurement indices).  OBS: a contribution to an observable
+// (targets: the observable index, then absolute measurement indices).
+enum class OpKind : uint8_t { H, S, X, Y, Z, CX, M, R, MR, XERR, YERR, ZERR, DEP1, DEP2, TICK, FX, FY, FZ, DET, OBS };
 
 // Channel kinds as seen by the sampling kernel.  RANDBIT is the fair coin of
 // a random measurement (threshold 2^31).
@@ -52,12 +56,17 @@ struct sp_circuit {
   uint32_t n_qubits = 0;
   uint32_t n_locs = 0;
   uint32_t n_meas = 0;
+  uint32_t n_detectors = 0;
+  uint32_t n_observables = 0;
   std::vector<sp::Op> ops;
   std::vector<sp::Channel> channels;  // channels[0] is the random-measurement coin
 };
 
 struct sp_model {
+  // n_meas counts the output rows: recorded measurements, or detectors then
+  // observables (outputs == SP_OUT_DETECTORS).
   uint32_t n_qubits = 0, n_meas = 0, n_locs = 0, n_vars = 0, n_random = 0;
+  int outputs = 0;
   std::vector<sp::Channel> channels;
   // per location
   std::vector<uint8_t> loc_kind;
@@ -74,5 +83,5 @@ struct sp_model {
 
 namespace sp {
 sp_circuit* parse_circuit(const char* text, size_t len);
-sp_model* symbolize(const sp_circuit& c);
+sp_model* symbolize(const sp_circuit& c, int outputs);
 }  // namespace sp

@@ -25,7 +25,11 @@
 // z_a = 1 and contradicts the printed example, so it is not followed.
 //
 // Reset R = measure without recording, then X^e with e the outcome's vector
-// (the conditional-Pauli idea of the conclusion).  MR = M, then X^e.
+// (the conditional-Pauli idea of the conclusion).  MR = M, then X^e.  A
+// Pauli controlled by a recorded measurement k is P^{e_k} the same way.
+//
+// Outputs.  The rows of (M, c) are the recorded measurements' vectors, or
+// (detector outputs) each detector's and observable's sum of them.
 #include <algorithm>
 #include <cstring>
 
@@ -106,10 +110,13 @@ class SymTableau {
     for (uint32_t i = n_; i < 2 * n_; ++i)
       if ((px & bit(zr(i), a)) ^ (pz & bit(xr(i), a))) ph_[i - n_].v.push_back(var);
   }
-  // X^e with a vector exponent (reset after a measurement with outcome e).
-  void x_expr(uint32_t a, const Phase& e) {
+  // X^(px e) Z^(pz e) with a vector exponent e: a reset after a
+  // measurement with outcome e (X^e), or a Pauli controlled by a recorded
+  // measurement (the conditional Paulis of the conclusion).  Like a fault,
+  // it adds e to the rows it anticommutes with.
+  void pauli_expr(uint32_t a, int px, int pz, const Phase& e) {
     for (uint32_t i = n_; i < 2 * n_; ++i)
-      if (bit(zr(i), a)) phase_add(ph_[i - n_], e, tmp_);
+      if ((px & bit(zr(i), a)) ^ (pz & bit(xr(i), a))) phase_add(ph_[i - n_], e, tmp_);
   }
 
   // --- Init-M ---------------------------------------------------------
@@ -188,11 +195,11 @@ class SymTableau {
 
 }  // namespace
 
-sp_model* symbolize(const sp_circuit& c) {
+sp_model* symbolize(const sp_circuit& c, int outputs) {
   auto* mdl = new sp_model();
   try {
     mdl->n_qubits = c.n_qubits;
-    mdl->n_meas = c.n_meas;
+    mdl->outputs = outputs;
     mdl->n_locs = c.n_locs;
     mdl->channels = c.channels;
     mdl->loc_kind.reserve(c.n_locs);
@@ -200,7 +207,8 @@ sp_model* symbolize(const sp_circuit& c) {
     mdl->loc_var0.reserve(c.n_locs);
 
     SymTableau tab(c.n_qubits);
-    std::vector<Phase> outcomes;
+    std::vector<Phase> outcomes, dets, obs(c.n_observables);
+    std::vector<uint32_t> tmp;
     outcomes.reserve(c.n_meas);
     uint64_t n_vars = 0;
 
@@ -232,6 +240,23 @@ sp_model* symbolize(const sp_circuit& c) {
         case OpKind::Z: for (uint32_t q : t) tab.pauli_const(q, 0, 1); break;
         case OpKind::CX: for (size_t i = 0; i < t.size(); i += 2) tab.cx(t[i], t[i + 1]); break;
         case OpKind::TICK: break;
+        case OpKind::FX: case OpKind::FY: case OpKind::FZ: {
+          const int px = op.kind != OpKind::FZ, pz = op.kind != OpKind::FX;
+          for (size_t i = 0; i < t.size(); i += 2) {
+            const Phase e = outcomes[t[i]];   // a copy: the tableau update may not alias it
+            tab.pauli_expr(t[i + 1], px, pz, e);
+          }
+          break;
+        }
+        case OpKind::DET: {
+          Phase d;
+          for (uint32_t k : t) phase_add(d, outcomes[k], tmp);
+          dets.push_back(std::move(d));
+          break;
+        }
+        case OpKind::OBS:
+          for (size_t i = 1; i < t.size(); ++i) phase_add(obs[t[0]], outcomes[t[i]], tmp);
+          break;
         case OpKind::XERR: case OpKind::YERR: case OpKind::ZERR: {
           const int px = op.kind != OpKind::ZERR, pz = op.kind != OpKind::XERR;
           const uint8_t lk = op.kind == OpKind::XERR ? L_XERR : op.kind == OpKind::YERR ? L_YERR : L_ZERR;
@@ -273,7 +298,7 @@ sp_model* symbolize(const sp_circuit& c) {
               new_loc(lk, -1, -1);
             }
             if (op.kind != OpKind::R) outcomes.push_back(e);
-            if (op.kind != OpKind::M) tab.x_expr(q, e);
+            if (op.kind != OpKind::M) tab.pauli_expr(q, 1, 0, e);
           }
           break;
         }
@@ -281,17 +306,25 @@ sp_model* symbolize(const sp_circuit& c) {
     }
     mdl->n_vars = (uint32_t)n_vars;
 
+    // The output rows: recorded measurements, or detectors then observables.
+    std::vector<Phase>* rows = &outcomes;
+    if (outputs == SP_OUT_DETECTORS) {
+      for (Phase& o : obs) dets.push_back(std::move(o));
+      rows = &dets;
+    }
+    mdl->n_meas = (uint32_t)rows->size();
+
     // M as column lists, rows ascending; c as bits.
     mdl->col_ptr.assign(n_vars + 1, 0);
-    mdl->c_bits.assign((c.n_meas + 63) / 64 + 1, 0);
-    for (const Phase& p : outcomes)
+    mdl->c_bits.assign((rows->size() + 63) / 64 + 1, 0);
+    for (const Phase& p : *rows)
       for (uint32_t v : p.v) mdl->col_ptr[v + 1]++;
     for (uint64_t j = 0; j < n_vars; ++j) mdl->col_ptr[j + 1] += mdl->col_ptr[j];
     mdl->row_idx.resize(mdl->col_ptr[n_vars]);
     std::vector<uint32_t> fill(mdl->col_ptr.begin(), mdl->col_ptr.end() - 1);
-    for (uint32_t k = 0; k < outcomes.size(); ++k) {
-      for (uint32_t v : outcomes[k].v) mdl->row_idx[fill[v]++] = k;
-      if (outcomes[k].c) mdl->c_bits[k >> 6] |= 1ull << (k & 63);
+    for (uint32_t k = 0; k < rows->size(); ++k) {
+      for (uint32_t v : (*rows)[k].v) mdl->row_idx[fill[v]++] = k;
+      if ((*rows)[k].c) mdl->c_bits[k >> 6] |= 1ull << (k & 63);
     }
     return mdl;
   } catch (const std::bad_alloc&) {

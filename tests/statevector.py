@@ -2,7 +2,8 @@
 
 Dense 2^n complex amplitudes, qubit q = bit q of the basis index.  Gates
 are the textbook matrices of the paper's background section (H, S, CNOT,
-the Paulis); a Z measurement computes P(1) from the amplitudes and projects.
+the Paulis); a Z measurement computes P(1) from the amplitudes and projects;
+"CX/CY/CZ rec[-k] q" applies the Pauli matrix when that recorded outcome was 1.
 It has its own reader of the circuit text and its own location numbering
 (program order: each 1-qubit channel target, each DEPOLARIZE2 pair, each
 M/R/MR target).  It never draws random numbers: per-location codes are
@@ -24,15 +25,27 @@ MATS = {
 
 
 def parse(text: str):
+    """(name, targets) per instruction; a record target rec[-k] becomes the
+    string 'rec', k; detector and observable lines are skipped (they do not
+    act on the state)."""
     ops = []
     for line in text.splitlines():
         line = line.split("#")[0].strip()
         if not line:
             continue
-        parts = line.split()
-        head = parts[0]
-        name = head.split("(")[0]
-        ops.append((name, [int(t) for t in parts[1:]]))
+        name = line.split("(")[0].split()[0]
+        if name in ("DETECTOR", "OBSERVABLE_INCLUDE"):
+            continue
+        rest = line[len(name):]
+        if rest.startswith("("):
+            rest = rest[rest.index(")") + 1:]
+        tg = []
+        for t in rest.split():
+            if t.startswith("rec[-"):
+                tg.append(("rec", int(t[5:-1])))
+            else:
+                tg.append(int(t))
+        ops.append((name, tg))
     return ops
 
 
@@ -83,9 +96,13 @@ def run(text: str, n: int, codes, tol: float = 1e-9):
         if name in MATS:
             for q in tg:
                 st.apply1(MATS[name], q)
-        elif name in ("CX", "CNOT"):
+        elif name in ("CX", "CNOT", "CY", "CZ"):
             for i in range(0, len(tg), 2):
-                st.cx(tg[i], tg[i + 1])
+                if isinstance(tg[i], tuple):   # Pauli on tg[i+1] if record rec[-k] was 1
+                    if outcomes[len(outcomes) - tg[i][1]]:
+                        st.apply1(MATS[name[1]], tg[i + 1])
+                else:
+                    st.cx(tg[i], tg[i + 1])
         elif name in ("X_ERROR", "Y_ERROR", "Z_ERROR"):
             P = MATS[name[0]]
             for q in tg:

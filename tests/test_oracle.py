@@ -135,6 +135,78 @@ def test_oracle_matches_statevector(seed, n, n_ops):
         assert np.array_equal(got_rnd, want_rnd)
 
 
+@settings(max_examples=200, deadline=None)
+@given(seed=st.integers(0, 2 ** 31), n=st.integers(1, 6), n_ops=st.integers(1, 45))
+def test_oracle_matches_statevector_with_feedback(seed, n, n_ops):
+    """The same with Paulis controlled by earlier records (CX/CY/CZ
+    rec[-k] q): the statevector applies the Pauli matrix when the recorded
+    outcome it reached was 1."""
+    text = random_clifford_circuit(seed, n, n_ops, feedback=True, detectors=True).text()
+    c = oracle.Circuit(text)
+    rng = np.random.default_rng(seed + 2)
+    kinds = c.location_kinds()
+    for _ in range(3):
+        codes = np.array([rng.integers(0, 2 ** oracle.CODE_BITS[int(k)]) for k in kinds], dtype=np.uint8)
+        got, got_rnd = c.run_codes(codes, check_invariants=True)
+        want, want_rnd = statevector.run(text, c.n_qubits, codes)
+        assert np.array_equal(got, want)
+        assert np.array_equal(got_rnd, want_rnd)
+
+
+@pytest.mark.parametrize("pauli,prep,unprep", [("X", "", ""), ("Y", "", ""), ("Z", "H 1\n", "H 1\n"),
+                                               ("Y", "H 1\n", "H 1\n")])
+def test_feedback_copies_a_random_outcome(pauli, prep, unprep):
+    """A random outcome m0 (H then M), then P on a fresh qubit controlled by
+    it: with the qubit prepared so that P flips its measured value, the
+    second outcome equals m0 in every shot, and m0 is fair."""
+    text = f"H 0\nM 0\n{prep}C{pauli} rec[-1] 1\n{unprep}M 1\n"
+    c = oracle.Circuit(text)
+    out = c.sample(seed=5, first_shot=0, shots=4096)
+    assert np.array_equal(out[0], out[1])
+    ones = sum(bin(int(w)).count("1") for w in out[0])
+    assert abs(ones - 2048) < 5 * math.sqrt(1024)
+
+
+@pytest.mark.parametrize("d,rounds", [(3, 3), (5, 4)])
+def test_repetition_detectors_closed_form(d, rounds):
+    """Repetition memory with detectors: with no fault every detector and
+    the observable are 0; a single X fault on data qubit j before round t
+    fires exactly the detectors of the ancillas next to j in round t (an
+    ancilla compares consecutive rounds, and the final parity check cancels
+    the flip), and flips the observable iff j = 0."""
+    circ = repetition_memory(d, rounds, "0.01", detectors=True)
+    c = oracle.Circuit(circ.text(), outputs="detectors")
+    na = d - 1
+    assert (c.n_detectors, c.n_observables) == ((rounds + 1) * na, 1)
+    per_round = d + na + 2 * na
+    zero = np.zeros(c.n_locs, dtype=np.uint8)
+    out, _ = c.run_codes(zero)
+    assert not c.rows_from_outcomes(out).any()
+    for t in range(rounds):
+        for j in range(d):
+            codes = zero.copy()
+            codes[t * per_round + j] = 1
+            rows = c.rows_from_outcomes(c.run_codes(codes)[0])
+            want = np.zeros(c.n_rows, dtype=np.uint8)
+            for i in (j - 1, j):
+                if 0 <= i < na:
+                    want[t * na + i] = 1
+            want[-1] = int(j == 0)
+            assert np.array_equal(rows, want), (t, j)
+
+
+@pytest.mark.parametrize("d,rounds", [(3, 3), (5, 3)])
+def test_surface_noiseless_detectors_are_zero(d, rounds):
+    """p = 0 memory-Z with detectors: every detector and the observable is
+    0 in every shot, although the first round's X checks are random."""
+    circ = surface_memory(d, rounds, "0", detectors=True)
+    det = oracle.Circuit(circ.text(), outputs="detectors")
+    meas = oracle.Circuit(circ.text())
+    assert det.n_detectors == circ.n_detectors and det.n_observables == 1
+    assert not det.sample(seed=1, first_shot=0, shots=1024).any()
+    assert meas.sample(seed=1, first_shot=0, shots=1024).any()
+
+
 def test_statevector_catches_planted_phase_error():
     """The brute-force check is sharp enough to see a single wrong phase:
     flipping one outcome bit of the oracle's result must be detected."""
@@ -277,7 +349,10 @@ def test_sample_is_shot_addressable():
 
 @pytest.mark.parametrize("text", ["T 0\n", "CX 0\n", "CX 1 1\n", "X_ERROR 0\n", "H(0.1) 0\n",
                                   "X_ERROR(1.2) 0\n", "M a\n", "DEPOLARIZE2(0.1) 0 1 2\n",
-                                  "TICK 3\n"])
+                                  "TICK 3\n", "CX rec[-1] 0\n", "M 0\nCX rec[-2] 1\n", "M 0\nCX 1 rec[-1]\n",
+                                  "CZ 0 1\n", "M 0\nDETECTOR 0\n", "M 0\nOBSERVABLE_INCLUDE rec[-1]\n",
+                                  "M 0\nOBSERVABLE_INCLUDE(a) rec[-1]\n", "M 0\nH rec[-1]\n",
+                                  "M 0\nDETECTOR rec[0]\n"])
 def test_parse_rejects(text):
     with pytest.raises(oracle.OracleError):
         oracle.Circuit(text)

@@ -16,7 +16,7 @@ import torch
 
 import oracle
 import paper_2311_03906_amd as sp
-from workloads import repetition_memory, surface_memory, random_layered_circuit
+from workloads import random_clifford_circuit, random_layered_circuit, repetition_memory, surface_memory
 
 pytestmark = pytest.mark.gpu
 
@@ -28,11 +28,11 @@ def _say(msg):
 _cache = {}
 
 
-def _models(text, path="auto"):
-    key = (text, path)
+def _models(text, path="auto", outputs="measurements"):
+    key = (text, path, outputs)
     if key not in _cache:
-        m = sp.Model(text)
-        _cache[key] = (m, sp.DeviceModel(m, path=path), oracle.Circuit(text))
+        m = sp.Model(text, outputs=outputs)
+        _cache[key] = (m, sp.DeviceModel(m, path=path), oracle.Circuit(text, outputs=outputs))
     return _cache[key]
 
 
@@ -77,6 +77,48 @@ def test_layered_random_circuit_full():
     m, dm, oc = _models(text)
     got = _gpu(dm, 3000, seed=8)
     assert np.array_equal(got, oc.sample(seed=8, first_shot=0, shots=3000))
+
+
+@pytest.mark.parametrize("path", ["sparse", "dense"])
+@pytest.mark.parametrize("name,circ", [("rep5", repetition_memory(5, 5, "0.01", detectors=True)),
+                                       ("surf5", surface_memory(5, 5, "0.005", detectors=True)),
+                                       ("surf3", surface_memory(3, 3, "0.02", detectors=True))])
+def test_detector_outputs_full(name, circ, path):
+    """Detector and observable rows (XORs of records) sampled on the GPU
+    equal the oracle's detector rows, word for word."""
+    text = circ.text()
+    _say(f"detectors {name} 20000 shots path={path}")
+    m, dm, oc = _models(text, path, "detectors")
+    assert m.n_meas == oc.n_rows == circ.n_detectors + circ.n_observables
+    got = _gpu(dm, 20_000, seed=11, first_shot=640)
+    assert np.array_equal(got, oc.sample(seed=11, first_shot=640, shots=20_000))
+
+
+@pytest.mark.parametrize("outputs", ["measurements", "detectors"])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_feedback_circuits_full(seed, outputs):
+    """Random noisy circuits with Paulis controlled by earlier records
+    (CX/CY/CZ rec[-k] q), detectors and observables: every word equals the
+    oracle's."""
+    text = random_clifford_circuit(seed, 8, 120, feedback=True, detectors=True).text()
+    _say(f"feedback circuit seed={seed} outputs={outputs} 5000 shots")
+    m, dm, oc = _models(text, "auto", outputs)
+    got = _gpu(dm, 5000, seed=seed)
+    assert np.array_equal(got, oc.sample(seed=seed, first_shot=0, shots=5000))
+
+
+def test_surface_d15_detectors_sampled():
+    """Surface d=15, 15 rounds, p = 5e-3, detector outputs, one 2^20-shot
+    launch at first_shot = 2^20: 1024 shots equal the oracle's rows."""
+    text = surface_memory(15, 15, "0.005", detectors=True).text()
+    _say("surface d15 detectors 2^20 shots sampled")
+    m, dm, oc = _models(text, "sparse", "detectors")
+    shots = 1 << 20
+    got = _gpu(dm, shots, seed=4, first_shot=shots)
+    ids = np.random.default_rng(4).choice(shots, 1024, replace=False)
+    want = oc.sample_shots(4, ids + shots)
+    for i, s in enumerate(ids):
+        assert np.array_equal(_column(got, int(s)), want[i]), int(s)
 
 
 # ------------------------------------------------------ full-size, sampled --

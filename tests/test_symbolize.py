@@ -41,21 +41,21 @@ def test_paper_examples_M_and_c(name):
     assert not c.any()
 
 
-def _probe(text):
-    """(M, c) read off the oracle: c = outcomes with every code 0; column j =
-    outcomes with only variable j's code bit set, plus c."""
-    oc = oracle.Circuit(text)
-    m = sp.Model(text)
+def _probe(text, outputs="measurements"):
+    """(M, c) read off the oracle: c = output rows with every code 0;
+    column j = rows with only variable j's code bit set, plus c."""
+    oc = oracle.Circuit(text, outputs=outputs)
+    m = sp.Model(text, outputs=outputs)
     var_loc, var_bit = m.export_vars()
     zero = np.zeros(oc.n_locs, dtype=np.uint8)
-    c0, _ = oc.run_codes(zero)
+    c0 = oc.rows_from_outcomes(oc.run_codes(zero)[0])
     cols = []
     for l, b in zip(var_loc, var_bit):
         codes = zero.copy()
         codes[l] = 1 << b
-        o, _ = oc.run_codes(codes)
+        o = oc.rows_from_outcomes(oc.run_codes(codes)[0])
         cols.append(o ^ c0)
-    M = np.array(cols, dtype=np.uint8).T if cols else np.zeros((oc.n_meas, 0), dtype=np.uint8)
+    M = np.array(cols, dtype=np.uint8).T if cols else np.zeros((oc.n_rows, 0), dtype=np.uint8)
     return m, M, c0
 
 
@@ -69,6 +69,52 @@ def test_model_equals_oracle_probing(circ):
     M, c = m.export_dense()
     assert np.array_equal(M, M_or)
     assert np.array_equal(c, c_or)
+
+
+@pytest.mark.parametrize("circ", [repetition_memory(3, 3, 1e-3, detectors=True),
+                                  repetition_memory(5, 4, "0.01", detectors=True),
+                                  surface_memory(3, 3, 1e-3, detectors=True),
+                                  surface_memory(5, 2, "0.002", detectors=True),
+                                  random_clifford_circuit(11, 4, 40, feedback=True, detectors=True)],
+                         ids=["rep3", "rep5", "surf3", "surf5r2", "random_feedback"])
+def test_detector_model_equals_oracle_probing(circ):
+    """Detector outputs: the rows of (M, c) are the detectors' and
+    observables' expressions, read off the oracle's detector rows."""
+    text = circ.text()
+    m, M_or, c_or = _probe(text, outputs="detectors")
+    M, c = m.export_dense()
+    assert m.n_meas == circ.n_detectors + circ.n_observables
+    assert np.array_equal(M, M_or)
+    assert np.array_equal(c, c_or)
+
+
+def test_detector_model_is_sparser_than_measurements():
+    """Detector rows of a memory experiment have a few symbols each, where
+    raw measurement rows accumulate every earlier fault on their qubits."""
+    text = surface_memory(5, 5, 1e-3, detectors=True).text()
+    meas, det = sp.Model(text), sp.Model(text, outputs="detectors")
+    assert det.n_vars == meas.n_vars
+    assert det.dims.nnz * 2 < meas.dims.nnz
+
+
+@settings(max_examples=200, deadline=None)
+@given(seed=st.integers(0, 2 ** 31), n=st.integers(1, 7), n_ops=st.integers(1, 60))
+def test_feedback_model_matches_oracle_on_random_circuits(seed, n, n_ops):
+    """M b + c equals the oracle for random circuits with Paulis controlled
+    by records, for both measurement and detector outputs."""
+    text = random_clifford_circuit(seed, n, n_ops, feedback=True, detectors=True).text()
+    rng = np.random.default_rng(seed)
+    for outputs in ("measurements", "detectors"):
+        oc = oracle.Circuit(text, outputs=outputs)
+        m = sp.Model(text, outputs=outputs)
+        M, c = m.export_dense()
+        mv = m.export_vars()
+        kinds = oc.location_kinds()
+        for _ in range(3):
+            codes = np.array([rng.integers(0, 2 ** oracle.CODE_BITS[int(k)]) for k in kinds], dtype=np.uint8)
+            want = oc.rows_from_outcomes(oc.run_codes(codes)[0])
+            got = _evaluate(M, c, _assignment(mv, codes))
+            assert np.array_equal(got, want)
 
 
 def test_random_measurements_get_variables():
@@ -138,11 +184,37 @@ def test_zero_probability_locations_not_drawn():
 
 @pytest.mark.parametrize("text,code", [("T 0\n", sp._capi.SP_E_UNSUPPORTED), ("CX 0\n", sp._capi.SP_E_PARSE),
                                        ("X_ERROR(1.5) 0\n", sp._capi.SP_E_PARSE), ("M x\n", sp._capi.SP_E_PARSE),
-                                       ("H(0.1) 0\n", sp._capi.SP_E_PARSE), ("DEPOLARIZE2(0.1) 3 3\n", sp._capi.SP_E_PARSE)])
+                                       ("H(0.1) 0\n", sp._capi.SP_E_PARSE), ("DEPOLARIZE2(0.1) 3 3\n", sp._capi.SP_E_PARSE),
+                                       ("CX rec[-1] 0\n", sp._capi.SP_E_PARSE),
+                                       ("M 0\nCX rec[-2] 1\n", sp._capi.SP_E_PARSE),
+                                       ("M 0\nCX 1 rec[-1]\n", sp._capi.SP_E_PARSE),
+                                       ("CZ 0 1\n", sp._capi.SP_E_UNSUPPORTED),
+                                       ("M 0\nDETECTOR 0\n", sp._capi.SP_E_PARSE),
+                                       ("M 0\nOBSERVABLE_INCLUDE rec[-1]\n", sp._capi.SP_E_PARSE),
+                                       ("M 0\nOBSERVABLE_INCLUDE(a) rec[-1]\n", sp._capi.SP_E_PARSE),
+                                       ("M 0\nH rec[-1]\n", sp._capi.SP_E_PARSE),
+                                       ("M 0\nDETECTOR rec[0]\n", sp._capi.SP_E_PARSE),
+                                       ("M 0\nDETECTOR(1, 2 rec[-1]\n", sp._capi.SP_E_PARSE)])
 def test_parse_errors(text, code):
     with pytest.raises(sp.SymphaseError) as ei:
         sp.Circuit(text)
     assert ei.value.code == code
+
+
+def test_circuit_counts_and_record_arithmetic():
+    """rec[-k] counts recorded measurements only (M and MR, not R), across
+    instructions; DETECTOR arguments are ignored; the observable count is
+    one more than the largest index."""
+    text = ("M 0 1\nR 2\nMR 2\nDETECTOR(0.5, 1, 0) rec[-1] rec[-3]\nDETECTOR\n"
+            "OBSERVABLE_INCLUDE(2) rec[-2]\nCX rec[-3] 4 0 1\n")
+    c = sp.Circuit(text)
+    assert (c.n_qubits, c.n_meas, c.n_detectors, c.n_observables) == (5, 3, 2, 3)
+    oc = oracle.Circuit(text, outputs="detectors")
+    assert (oc.n_detectors, oc.n_observables) == (2, 3)
+    m = sp.Model(text, outputs="detectors")
+    assert m.n_meas == 5
+    with pytest.raises(ValueError):
+        sp.Model(text, outputs="bits")
 
 
 def test_empty_circuit():

@@ -16,6 +16,10 @@ Instruction set:
   DEPOLARIZE1(p)       X, Y, Z each with probability p/3
   DEPOLARIZE2(p)       each of the 15 non-identity two-qubit Paulis w.p. p/15,
                        targets taken in pairs
+  CX/CY/CZ rec[-k] q   X/Y/Z on q when the k-th most recent recorded
+                       measurement was 1 (a Pauli controlled by an outcome)
+  DETECTOR rec[-k] ... XOR of recorded measurements (a detector)
+  OBSERVABLE_INCLUDE(i) rec[-k] ...  XOR of records into observable i
 
 The gate set is that of stabilizer circuits (H, S, CNOT, Z measurement,
 |0...0> start) from the paper's background section, plus the Pauli gates and
@@ -51,6 +55,8 @@ class Circuit:
     n_qubits: int = 0
     n_meas: int = 0
     meta: dict = field(default_factory=dict)
+    n_detectors: int = 0
+    n_observables: int = 0
 
     def op(self, name: str, targets, p: float | str | None = None):
         targets = [int(t) for t in targets]
@@ -70,6 +76,37 @@ class Circuit:
 
     def tick(self):
         self.lines.append("TICK")
+        return self
+
+    def feedback(self, pauli: str, pairs):
+        """Pauli X/Y/Z on q when record rec[-k] was 1, for each (k, q)."""
+        if pauli not in ("X", "Y", "Z"):
+            raise ValueError(pauli)
+        tg = []
+        for k, q in pairs:
+            if not 1 <= int(k) <= self.n_meas:
+                raise ValueError(f"rec[-{k}] with {self.n_meas} measurements recorded")
+            tg += [f"rec[-{int(k)}]", str(int(q))]
+            self.n_qubits = max(self.n_qubits, int(q) + 1)
+        if tg:
+            self.lines.append(" ".join([f"C{pauli}"] + tg))
+        return self
+
+    def _recs(self, ks):
+        for k in ks:
+            if not 1 <= int(k) <= self.n_meas:
+                raise ValueError(f"rec[-{k}] with {self.n_meas} measurements recorded")
+        return [f"rec[-{int(k)}]" for k in ks]
+
+    def detector(self, ks, coords=None):
+        head = "DETECTOR" if coords is None else "DETECTOR(" + ", ".join(str(x) for x in coords) + ")"
+        self.lines.append(" ".join([head] + self._recs(ks)))
+        self.n_detectors += 1
+        return self
+
+    def observable(self, index: int, ks):
+        self.lines.append(" ".join([f"OBSERVABLE_INCLUDE({int(index)})"] + self._recs(ks)))
+        self.n_observables = max(self.n_observables, int(index) + 1)
         return self
 
     def text(self) -> str:
@@ -106,20 +143,26 @@ def bell_example(p: str = "0.1") -> Circuit:
 # QEC memory experiments.
 # --------------------------------------------------------------------------
 
-def repetition_memory(d: int, rounds: int, p: float | str = 1e-3) -> Circuit:
+def repetition_memory(d: int, rounds: int, p: float | str = 1e-3, detectors: bool = False) -> Circuit:
     """Bit-flip repetition-code memory.
 
     Data qubits 0,2,..,2(d-1); ancilla 2i+1 checks data 2i and 2i+2.  Each
     round: X_ERROR(p) on data, CNOT data->ancilla (ancilla 2i+1 collects
     2i then 2i+2), X_ERROR(p) on the ancillas, M ancillas, R ancillas.
     After the rounds: X_ERROR(p) on data, M data.
+
+    With detectors: each round, one detector per ancilla (its outcome, XORed
+    with its previous outcome after the first round); after the data
+    measurement, one per ancilla comparing the parity of its two data qubits
+    with its last outcome; observable 0 = data qubit 0.  Without noise every
+    detector and the observable are 0.
     """
     if d < 2 or rounds < 1:
         raise ValueError("need d >= 2 and rounds >= 1")
     data = [2 * i for i in range(d)]
     anc = [2 * i + 1 for i in range(d - 1)]
     c = Circuit(meta={"family": "repetition", "d": d, "rounds": rounds, "p": str(p)})
-    for _ in range(rounds):
+    for r in range(rounds):
         c.op("X_ERROR", data, p)
         pairs = []
         for i, a in enumerate(anc):
@@ -131,10 +174,20 @@ def repetition_memory(d: int, rounds: int, p: float | str = 1e-3) -> Circuit:
         c.op("CX", pairs)
         c.op("X_ERROR", anc, p)
         c.op("M", anc)
+        if detectors:
+            na = d - 1
+            for i in range(na):
+                ks = [na - i] if r == 0 else [na - i, 2 * na - i]
+                c.detector(ks, coords=(2 * i + 1, r))
         c.op("R", anc)
         c.tick()
     c.op("X_ERROR", data, p)
     c.op("M", data)
+    if detectors:
+        na = d - 1
+        for i in range(na):
+            c.detector([d - i, d - i - 1, d + na - i], coords=(2 * i + 1, rounds))
+        c.observable(0, [d])
     c.n_qubits = 2 * d - 1
     return c
 
@@ -175,7 +228,19 @@ def _surface_layout(d: int):
 _ORDER = {"X": ("NW", "NE", "SW", "SE"), "Z": ("NW", "SW", "NE", "SE")}
 
 
-def surface_memory(d: int, rounds: int, p: float | str = 1e-3) -> Circuit:
+def _logical_z_support(d: int, checks) -> list:
+    """Data qubits of a Z-type logical: a full row or column of the d x d
+    data grid that overlaps every X check on an even number of qubits."""
+    cands = [[r * d + col for col in range(d)] for r in range(d)] + \
+            [[r * d + col for r in range(d)] for col in range(d)]
+    for cand in cands:
+        s = set(cand)
+        if all(len(s & set(corners.values())) % 2 == 0 for typ, corners in checks if typ == "X"):
+            return cand
+    raise AssertionError("no Z logical among rows and columns")
+
+
+def surface_memory(d: int, rounds: int, p: float | str = 1e-3, detectors: bool = False) -> Circuit:
     """Rotated surface-code memory-Z experiment with circuit-level noise.
 
     Per round, TICK-separated layers:
@@ -183,6 +248,14 @@ def surface_memory(d: int, rounds: int, p: float | str = 1e-3) -> Circuit:
     Noise: X_ERROR(p) after R and before M; DEPOLARIZE1(p) after each H and
     on every qubit idle in a layer; DEPOLARIZE2(p) after each CNOT.
     Finally X_ERROR(p) on data and M on all data qubits.
+
+    With detectors: every round, one detector per Z check (its outcome, XORed
+    with its previous one after the first round) and, from the second round
+    on, one per X check (XOR of consecutive outcomes; the first X outcomes
+    are random); after the data measurement, one per Z check comparing the
+    parity of its data qubits with its last outcome; observable 0 = the
+    parity of a row of data qubits that commutes with every X check.
+    Without noise every detector and the observable are 0.
     """
     if d < 3 or d % 2 == 0 or rounds < 1:
         raise ValueError("need odd d >= 3 and rounds >= 1")
@@ -209,7 +282,8 @@ def surface_memory(d: int, rounds: int, p: float | str = 1e-3) -> Circuit:
         layers.append(pairs)
 
     c = Circuit(meta={"family": "surface", "d": d, "rounds": rounds, "p": str(p)})
-    for _ in range(rounds):
+    nc = len(checks)
+    for r in range(rounds):
         c.op("R", anc)
         c.op("X_ERROR", anc, p)
         c.op("DEPOLARIZE1", data, p)
@@ -230,10 +304,24 @@ def surface_memory(d: int, rounds: int, p: float | str = 1e-3) -> Circuit:
         c.tick()
         c.op("X_ERROR", anc, p)
         c.op("M", anc)
+        if detectors:
+            for i, (typ, _) in enumerate(checks):
+                if r == 0 and typ == "Z":
+                    c.detector([nc - i], coords=(i, r))
+                elif r > 0:
+                    c.detector([nc - i, 2 * nc - i], coords=(i, r))
         c.op("DEPOLARIZE1", data, p)
         c.tick()
     c.op("X_ERROR", data, p)
     c.op("M", data)
+    if detectors:
+        for i, (typ, corners) in enumerate(checks):
+            if typ != "Z":
+                continue
+            ks = [n_data - q for q in sorted(corners.values())]
+            c.detector(ks + [n_data + nc - i], coords=(i, rounds))
+        row = _logical_z_support(d, checks)
+        c.observable(0, [n_data - q for q in row])
     c.n_qubits = n
     c.meta.update({"n_x_checks": len(x_anc), "n_z_checks": len(z_anc)})
     return c
@@ -248,12 +336,15 @@ _NOISE1 = ("X_ERROR", "Y_ERROR", "Z_ERROR", "DEPOLARIZE1")
 
 
 def random_clifford_circuit(seed: int, n: int, n_ops: int,
-                            p_choices=("0.1", "0.25", "0.5", "0.75", "1")) -> Circuit:
+                            p_choices=("0.1", "0.25", "0.5", "0.75", "1"),
+                            feedback: bool = False, detectors: bool = False) -> Circuit:
     """Random noisy stabilizer circuit on n qubits (for brute-force checks).
-    Mixes every instruction of the format uniformly."""
+    Mixes every instruction of the format uniformly; with `feedback`, also
+    Paulis controlled by earlier records; with `detectors`, ends with a few
+    detectors and observables over random records."""
     rng = np.random.default_rng(seed)
     c = Circuit(meta={"family": "random_clifford", "seed": seed, "n": n})
-    kinds = ("g1", "cx", "m", "r", "mr", "n1", "n2")
+    kinds = ("g1", "cx", "m", "r", "mr", "n1", "n2") + (("fb",) if feedback else ())
     for _ in range(n_ops):
         k = kinds[rng.integers(len(kinds))]
         if k == "g1":
@@ -274,7 +365,15 @@ def random_clifford_circuit(seed: int, n: int, n_ops: int,
             a, b = rng.choice(n, 2, replace=False)
             p = p_choices[rng.integers(len(p_choices))]
             c.op("DEPOLARIZE2", [a, b], p)
+        elif k == "fb" and c.n_meas > 0:
+            c.feedback("XYZ"[rng.integers(3)], [(1 + rng.integers(c.n_meas), rng.integers(n))])
     c.op("M", list(range(n)))
+    if detectors:
+        for _ in range(1 + rng.integers(4)):
+            k = 1 + rng.integers(min(4, c.n_meas))
+            c.detector(sorted(set(1 + rng.integers(c.n_meas, size=k))))
+        for i in range(1 + rng.integers(2)):
+            c.observable(i, sorted(set(1 + rng.integers(c.n_meas, size=1 + rng.integers(3)))))
     c.n_qubits = max(c.n_qubits, n)
     return c
 
