@@ -39,8 +39,8 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
-    ap.add_argument("--legs", default="rep,d15,mix,small,serving",
-                    help="comma list of the other workloads to run (rep, d15, mix, small, serving)")
+    ap.add_argument("--legs", default="rep,d15,outputs,mix,small,serving",
+                    help="comma list of the other workloads to run (rep, d15, outputs, mix, small, serving)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -166,7 +166,7 @@ def main():
     legs = set() if args.no_extra else {x.strip() for x in args.legs.split(",") if x.strip()}
     if args.no_serving:
         legs.discard("serving")
-    unknown = legs - {"rep", "d15", "mix", "small", "serving"}
+    unknown = legs - {"rep", "d15", "outputs", "mix", "small", "serving"}
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
         sys.exit(2)
@@ -190,6 +190,8 @@ def extra_workloads(sp, torch, surface_memory, repetition_memory, legs) -> dict:
         res.update(_repetition_leg(sp, torch, repetition_memory))
     if "d15" in legs:
         res.update(_d15_leg(sp, torch, surface_memory))
+    if "outputs" in legs:
+        res.update(_outputs_leg(sp, torch, surface_memory))
     return res
 
 
@@ -205,29 +207,49 @@ def _repetition_leg(sp, torch, repetition_memory) -> dict:
     return res
 
 
+def _d15_run(sp, torch, text, outputs="measurements") -> dict:
+    """10^7 shots of one d=15 model in 2^20-shot launches."""
+    m = sp.Model(text, outputs=outputs)
+    dm = sp.DeviceModel(m, path="sparse")
+    total, batch = 10_000_000, 1 << 20
+    out = torch.empty((m.n_meas, batch // 64), dtype=torch.int64, device="cuda")
+    starts = list(range(0, total, batch))
+
+    def one(i):
+        f = starts[i % len(starts)]
+        dm.sample(min(batch, total - f), seed=0, first_shot=f, out=out)
+
+    one(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(len(starts)):
+        one(i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ops = total * (PHILOX_OPS * m.dims.n_draw_blocks + m.dims.n_drawn)
+    return {"bits_per_s": total * m.n_meas / dt, "rows": m.n_meas, "seconds": dt, "batches": len(starts),
+            "launch": list(dm.launch), "valu_frac": ops / dt / PEAK_VALU, "nnz": int(m.dims.nnz)}
+
+
 def _d15_leg(sp, torch, surface_memory) -> dict:
     """Distance-15 surface code, 15 rounds, 10^7 shots in 2^20-shot batches."""
     res = {}
     for p in ("0.001", "0.005"):
-        m = sp.Model(surface_memory(15, 15, p).text())
-        dm = sp.DeviceModel(m, path="sparse")
-        total, batch = 10_000_000, 1 << 20
-        out = torch.empty((m.n_meas, batch // 64), dtype=torch.int64, device="cuda")
-        starts = list(range(0, total, batch))
+        res[f"surface_d15_r15_p{p}_1e7_shots"] = _d15_run(sp, torch, surface_memory(15, 15, p).text())
+    return res
 
-        def one(i):
-            f = starts[i % len(starts)]
-            dm.sample(min(batch, total - f), seed=0, first_shot=f, out=out)
 
-        one(0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(len(starts)):
-            one(i)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        res[f"surface_d15_r15_p{p}_1e7_shots"] = {"bits_per_s": total * m.n_meas / dt, "seconds": dt,
-                                                   "batches": len(starts), "launch": list(dm.launch)}
+def _outputs_leg(sp, torch, surface_memory) -> dict:
+    """The same d=15 workload with detector outputs (each row a detector or
+    the observable: sums of measurement rows, so M is sparser), and as a
+    dynamic circuit whose ancillas are reset by X controlled by their last
+    outcome (measurement outputs)."""
+    res = {}
+    for p in ("0.001", "0.005"):
+        res[f"surface_d15_r15_p{p}_detectors_1e7_shots"] = _d15_run(
+            sp, torch, surface_memory(15, 15, p, detectors=True).text(), outputs="detectors")
+        res[f"surface_d15_r15_p{p}_feedback_reset_1e7_shots"] = _d15_run(
+            sp, torch, surface_memory(15, 15, p, reset="feedback").text())
     return res
 
 

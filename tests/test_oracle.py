@@ -195,11 +195,13 @@ def test_repetition_detectors_closed_form(d, rounds):
             assert np.array_equal(rows, want), (t, j)
 
 
+@pytest.mark.parametrize("reset", ["reset", "feedback"])
 @pytest.mark.parametrize("d,rounds", [(3, 3), (5, 3)])
-def test_surface_noiseless_detectors_are_zero(d, rounds):
+def test_surface_noiseless_detectors_are_zero(d, rounds, reset):
     """p = 0 memory-Z with detectors: every detector and the observable is
-    0 in every shot, although the first round's X checks are random."""
-    circ = surface_memory(d, rounds, "0", detectors=True)
+    0 in every shot, although the first round's X checks are random; also
+    when the ancillas are reset by X controlled by their last outcome."""
+    circ = surface_memory(d, rounds, "0", detectors=True, reset=reset)
     det = oracle.Circuit(circ.text(), outputs="detectors")
     meas = oracle.Circuit(circ.text())
     assert det.n_detectors == circ.n_detectors and det.n_observables == 1

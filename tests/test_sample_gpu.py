@@ -107,6 +107,18 @@ def test_feedback_circuits_full(seed, outputs):
     assert np.array_equal(got, oc.sample(seed=seed, first_shot=0, shots=5000))
 
 
+@pytest.mark.parametrize("outputs", ["measurements", "detectors"])
+def test_surface_feedback_reset_full(outputs):
+    """Surface d=5, 5 rounds, p = 5e-3, ancillas reset by X controlled by
+    their previous outcome (a dynamic circuit): every word equals the
+    oracle's."""
+    text = surface_memory(5, 5, "0.005", detectors=True, reset="feedback").text()
+    _say(f"surface d5 feedback reset outputs={outputs} 20000 shots")
+    m, dm, oc = _models(text, "auto", outputs)
+    got = _gpu(dm, 20_000, seed=6)
+    assert np.array_equal(got, oc.sample(seed=6, first_shot=0, shots=20_000))
+
+
 def test_surface_d15_detectors_sampled():
     """Surface d=15, 15 rounds, p = 5e-3, detector outputs, one 2^20-shot
     launch at first_shot = 2^20: 1024 shots equal the oracle's rows."""

@@ -75,8 +75,9 @@ def test_model_equals_oracle_probing(circ):
                                   repetition_memory(5, 4, "0.01", detectors=True),
                                   surface_memory(3, 3, 1e-3, detectors=True),
                                   surface_memory(5, 2, "0.002", detectors=True),
-                                  random_clifford_circuit(11, 4, 40, feedback=True, detectors=True)],
-                         ids=["rep3", "rep5", "surf3", "surf5r2", "random_feedback"])
+                                  random_clifford_circuit(11, 4, 40, feedback=True, detectors=True),
+                                  surface_memory(3, 3, "0.01", detectors=True, reset="feedback")],
+                         ids=["rep3", "rep5", "surf3", "surf5r2", "random_feedback", "surf3_feedback_reset"])
 def test_detector_model_equals_oracle_probing(circ):
     """Detector outputs: the rows of (M, c) are the detectors' and
     observables' expressions, read off the oracle's detector rows."""

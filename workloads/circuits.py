@@ -240,7 +240,8 @@ def _logical_z_support(d: int, checks) -> list:
     raise AssertionError("no Z logical among rows and columns")
 
 
-def surface_memory(d: int, rounds: int, p: float | str = 1e-3, detectors: bool = False) -> Circuit:
+def surface_memory(d: int, rounds: int, p: float | str = 1e-3, detectors: bool = False,
+                   reset: str = "reset") -> Circuit:
     """Rotated surface-code memory-Z experiment with circuit-level noise.
 
     Per round, TICK-separated layers:
@@ -256,7 +257,13 @@ def surface_memory(d: int, rounds: int, p: float | str = 1e-3, detectors: bool =
     parity of its data qubits with its last outcome; observable 0 = the
     parity of a row of data qubits that commutes with every X check.
     Without noise every detector and the observable are 0.
+
+    reset="feedback" replaces the ancilla reset of every round after the
+    first by an X controlled by the ancilla's previous outcome (an active
+    reset: CX rec[-k] a), so the circuit is dynamic.
     """
+    if reset not in ("reset", "feedback"):
+        raise ValueError(reset)
     if d < 3 or d % 2 == 0 or rounds < 1:
         raise ValueError("need odd d >= 3 and rounds >= 1")
     checks = _surface_layout(d)
@@ -281,10 +288,13 @@ def surface_memory(d: int, rounds: int, p: float | str = 1e-3, detectors: bool =
         assert len(used) == len(set(used)), "CNOT layer touches a qubit twice"
         layers.append(pairs)
 
-    c = Circuit(meta={"family": "surface", "d": d, "rounds": rounds, "p": str(p)})
+    c = Circuit(meta={"family": "surface", "d": d, "rounds": rounds, "p": str(p), "reset": reset})
     nc = len(checks)
     for r in range(rounds):
-        c.op("R", anc)
+        if reset == "feedback" and r > 0:
+            c.feedback("X", [(nc - i, a) for i, a in enumerate(anc)])
+        else:
+            c.op("R", anc)
         c.op("X_ERROR", anc, p)
         c.op("DEPOLARIZE1", data, p)
         c.tick()
