@@ -341,10 +341,12 @@ def serving_leg(sp, torch) -> dict:
     burst = loadgen.poisson_plan(128, 1e9, len(models), 1_000, 1_000_000, seed=1)
     sat = loadgen.run(srv, models, burst, first_id=1_000_000)
     mu = sat["bits_per_s"] / mean_bits
-    out = {"saturation": {"bits_per_s": sat["bits_per_s"], "requests_per_s": mu, "p50_ms": sat["p50_ms"],
-                          "p99_ms": sat["p99_ms"], "requests": sat["requests"]},
-           "arena_bytes": 16 << 30, "max_active": 16, "sweep": []}
     blocks = [m.dims.n_draw_blocks for m in models]
+    sat_ops = sum(int(s) * (PHILOX_OPS * blocks[mi] + models[mi].dims.n_drawn) for mi, s in zip(burst[1], burst[2]))
+    out = {"saturation": {"bits_per_s": sat["bits_per_s"], "requests_per_s": mu, "p50_ms": sat["p50_ms"],
+                          "p99_ms": sat["p99_ms"], "requests": sat["requests"],
+                          "valu_frac": sat_ops / sat["span_s"] / PEAK_VALU if sat["span_s"] > 0 else None},
+           "arena_bytes": 16 << 30, "max_active": 16, "sweep": []}
     for k, f in enumerate((0.25, 0.5, 0.75, 0.9, 1.0, 1.2)):
         plan = loadgen.poisson_plan(240, f * mu, len(models), 1_000, 1_000_000, seed=10 + k)
         r = loadgen.run(srv, models, plan, first_id=k * 10_000)
