@@ -39,8 +39,8 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
-    ap.add_argument("--legs", default="rep,d15,outputs,mix,small,serving",
-                    help="comma list of the other workloads to run (rep, d15, outputs, mix, small, serving)")
+    ap.add_argument("--legs", default="rep,d15,outputs,fig3,mix,small,serving",
+                    help="comma list of the other workloads to run (rep, d15, outputs, fig3, mix, small, serving)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -166,12 +166,14 @@ def main():
     legs = set() if args.no_extra else {x.strip() for x in args.legs.split(",") if x.strip()}
     if args.no_serving:
         legs.discard("serving")
-    unknown = legs - {"rep", "d15", "outputs", "mix", "small", "serving"}
+    unknown = legs - {"rep", "d15", "outputs", "fig3", "mix", "small", "serving"}
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
         sys.exit(2)
     if legs:
         rec["extra"] = extra_workloads(sp, torch, surface_memory, repetition_memory, legs)
+        if "fig3" in legs:
+            rec["extra"]["paper_fig3_layered_random"] = fig3_leg(sp, torch)
         if "mix" in legs:
             rec["extra"]["batched_mix_64"] = batched_mix_leg(sp, torch)
         if "small" in legs:
@@ -250,6 +252,35 @@ def _outputs_leg(sp, torch, surface_memory) -> dict:
             sp, torch, surface_memory(15, 15, p, detectors=True).text(), outputs="detectors")
         res[f"surface_d15_r15_p{p}_feedback_reset_1e7_shots"] = _d15_run(
             sp, torch, surface_memory(15, 15, p, reset="feedback").text())
+    return res
+
+
+def fig3_leg(sp, torch) -> dict:
+    """The paper's own benchmark family (Fig. 3): layered random interaction
+    circuits, n qubits x n layers; each layer H/S/nothing per qubit, CNOTs
+    on 5 (3a) or floor(n/2) (3b, 3c) random disjoint pairs, single-qubit
+    depolarizing noise on every qubit (3c, p = 1e-3), then a Z measurement
+    of 5% of the qubits; all qubits measured at the end.  Reported: host
+    Initialization time and GPU time to generate 10^4 samples (the paper's
+    sampling metric), and 10^6 samples for throughput."""
+    from workloads import random_layered_circuit
+    res = {}
+    for n in (100, 200):
+        for fig, kw in (("3a", {"cnot_pairs": 5}), ("3b", {}), ("3c", {"p_dep": "0.001"})):
+            text = random_layered_circuit(n, seed=0, **kw).text()
+            t0 = time.perf_counter()
+            m = sp.Model(text)
+            t_init = time.perf_counter() - t0
+            dm = sp.DeviceModel(m)
+            r = {"n_meas": m.n_meas, "n_vars": m.n_vars, "nnz": int(m.dims.nnz), "drawn": int(m.dims.n_drawn),
+                 "path": dm.path, "init_s": t_init}
+            for shots in (10_000, 1_000_000):
+                out = torch.empty((m.n_meas, (shots + 63) // 64), dtype=torch.int64, device="cuda")
+                lat = _event_ms(lambda: dm.sample(shots, seed=0, out=out), 10, torch)
+                ms = pct(lat, 50)
+                r[f"ms_{shots}"] = ms
+                r[f"bits_per_s_{shots}"] = shots * m.n_meas / (ms * 1e-3)
+            res[f"fig{fig}_n{n}"] = r
     return res
 
 

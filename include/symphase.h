@@ -60,6 +60,8 @@
  *     qubit and X^(bit2) Z^(bit3) on the second.
  *   - A measurement whose outcome is random (Init-M, first case) takes the
  *     bit [u(l) < 2^31]; a determined one draws nothing.
+ *   - A location on which no output row depends is not drawn at all; no
+ *     output depends on its draw, and no other draw changes.
  *   - Variables (columns of M) are numbered in location order; a noise
  *     location owns one variable per code bit (bit order), a random
  *     measurement owns one, a determined measurement none.
@@ -102,7 +104,8 @@ typedef struct {
   uint32_t n_locs;        /* locations */
   uint32_t n_vars;        /* variables = columns of M (the constant excluded) */
   uint32_t n_random_meas; /* M/R/MR locations whose outcome is random */
-  uint32_t n_drawn;       /* locations the sampler draws for (p > 0 or random) */
+  uint32_t n_drawn;       /* locations the sampler draws for: p > 0 or random, and
+                             some output row depends on them */
   uint32_t n_draw_blocks; /* distinct l/4 over drawn locations = Philox blocks per shot */
   uint32_t reserved;
   uint64_t nnz;           /* nonzero entries of M (the constant column excluded) */

@@ -76,8 +76,7 @@ int sp_model_dims(const sp_model* m, sp_dims* d) {
   uint32_t drawn = 0, blocks = 0;
   int64_t last_block = -1;
   for (uint32_t l = 0; l < m->n_locs; ++l) {
-    int32_t ch = m->loc_chan[l];
-    if (ch >= 0 && m->channels[ch].T[m->channels[ch].m] > 0) {
+    if (sp::loc_drawn(*m, l)) {
       ++drawn;
       if ((int64_t)(l >> 2) != last_block) {
         ++blocks;
@@ -96,11 +95,9 @@ int sp_model_expected_work(const sp_model* m, double* fired_per_word, double* en
   if (!m) return set_error(SP_E_INVALID, "null model");
   double fired = 0, entries = 0;
   for (uint32_t l = 0; l < m->n_locs; ++l) {
-    const int32_t ch = m->loc_chan[l];
-    if (ch < 0) continue;
-    const sp::Channel& c = m->channels[ch];
+    if (!sp::loc_drawn(*m, l)) continue;
+    const sp::Channel& c = m->channels[m->loc_chan[l]];
     const double q = (double)c.T[c.m] / 4294967296.0;
-    if (q <= 0) continue;
     const double f = 1.0 - std::pow(1.0 - q, 64.0);
     fired += f;
     const uint32_t v0 = (uint32_t)m->loc_var0[l];

@@ -577,11 +577,10 @@ HostBlocks build_blocks(const sp_model& m) {
   if (m.n_locs >= (1u << 24)) throw sp::Error(SP_E_LIMIT, "more than 2^24 locations");
   int64_t cur = -1;
   for (uint32_t l = 0; l < m.n_locs; ++l) {
+    if (!sp::loc_drawn(m, l)) continue;   // never fires, or reaches no output row
     const int32_t ch = m.loc_chan[l];
-    if (ch < 0) continue;
     const sp::Channel& c = m.channels[ch];
     const uint64_t Tm = c.T[c.m];
-    if (Tm == 0) continue;  // never fires
     const int64_t blk = l >> 2;
     if (blk != cur) {
       H.hot.insert(H.hot.end(), 8, 0u);

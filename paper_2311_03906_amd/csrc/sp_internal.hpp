@@ -82,6 +82,17 @@ struct sp_model {
 };
 
 namespace sp {
+// A location the sampler draws for: a channel that can fire (T_m > 0) whose
+// variables reach at least one output row.  Any other location cannot change
+// an output, and since every draw is keyed by its own location, leaving it
+// out changes no other draw.
+inline bool loc_drawn(const sp_model& m, uint32_t l) {
+  const int32_t ch = m.loc_chan[l];
+  if (ch < 0 || m.channels[ch].T[m.channels[ch].m] == 0) return false;
+  const uint32_t v0 = (uint32_t)m.loc_var0[l];
+  return m.col_ptr[v0 + loc_bits(m.loc_kind[l])] > m.col_ptr[v0];
+}
+
 sp_circuit* parse_circuit(const char* text, size_t len);
 sp_model* symbolize(const sp_circuit& c, int outputs);
 }  // namespace sp

@@ -71,6 +71,18 @@ def test_surface_d5_full(path, p):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("fig,kw", [("3a", {"cnot_pairs": 5}), ("3b", {}), ("3c", {"p_dep": "0.001"})])
+@pytest.mark.parametrize("path", ["sparse", "dense"])
+def test_paper_fig3_circuits_full(fig, kw, path):
+    """The paper's benchmark family at n = 60 (Fig. 3a/b/c): 10^4 samples,
+    every word equals the oracle's, on both evaluation paths."""
+    text = random_layered_circuit(60, seed=2, **kw).text()
+    _say(f"fig{fig} n=60 10^4 shots path={path}")
+    m, dm, oc = _models(text, path)
+    got = _gpu(dm, 10_000, seed=9)
+    assert np.array_equal(got, oc.sample(seed=9, first_shot=0, shots=10_000))
+
+
 def test_layered_random_circuit_full():
     text = random_layered_circuit(24, seed=5, cnot_pairs=12, p_dep="0.01").text()
     _say("layered n=24 3000 shots")

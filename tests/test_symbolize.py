@@ -173,14 +173,36 @@ def test_dims_and_csc_consistent():
     for j in range(0, m.n_vars, 37):
         rows = ri[cp[j]:cp[j + 1]]
         assert list(rows) == list(np.nonzero(M[:, j])[0])
+    # Drawn: noise or random-measurement locations on which some output
+    # depends; the dependence is read off the oracle (a location matters iff
+    # setting one of its code bits alone changes an outcome).
     kinds = oc.location_kinds()
-    noise = sum(1 for k in kinds if k in oracle.NOISE_KINDS)
-    assert d.n_drawn == noise + d.n_random_meas
+    zero = np.zeros(oc.n_locs, dtype=np.uint8)
+    base, was_random = oc.run_codes(zero)
+    matters = 0
+    for l, k in enumerate(kinds):
+        if not (k in oracle.NOISE_KINDS or was_random[l]):
+            continue
+        for b in range(oracle.CODE_BITS[int(k)]):
+            codes = zero.copy()
+            codes[l] = 1 << b
+            if not np.array_equal(oc.run_codes(codes)[0], base):
+                matters += 1
+                break
+    assert d.n_drawn == matters
 
 
 def test_zero_probability_locations_not_drawn():
     m = sp.Model("X_ERROR(0) 0\nX_ERROR(0.5) 1\nH 2\nM 0 1 2\n")
     assert m.dims.n_vars == 3 and m.dims.n_drawn == 2 and m.dims.n_random_meas == 1
+
+
+def test_locations_without_effect_not_drawn():
+    """A Z fault right before a Z measurement, and a fault on a qubit that
+    is never measured again, reach no output: they get variables but no
+    draw."""
+    m = sp.Model("Z_ERROR(0.5) 0\nM 0\nX_ERROR(0.5) 0\nX_ERROR(0.5) 1\nM 1\n")
+    assert m.dims.n_vars == 3 and m.dims.n_drawn == 1 and m.dims.n_draw_blocks == 1
 
 
 @pytest.mark.parametrize("text,code", [("T 0\n", sp._capi.SP_E_UNSUPPORTED), ("CX 0\n", sp._capi.SP_E_PARSE),
