@@ -93,6 +93,19 @@ inline bool loc_drawn(const sp_model& m, uint32_t l) {
   return m.col_ptr[v0 + loc_bits(m.loc_kind[l])] > m.col_ptr[v0];
 }
 
+// A phase expression over GF(2): the constant bit plus the ascending list of
+// variable indices present (variable j = symbol s_{j+1} of Section 3.2.1).
+struct Expr {
+  uint8_t c = 0;
+  std::vector<uint32_t> v;
+};
+
 sp_circuit* parse_circuit(const char* text, size_t len);
 sp_model* symbolize(const sp_circuit& c, int outputs);
+// The model from one Initialization pass: loc_var0 per location (-1 for a
+// determined measurement), the variable count, and the expression of every
+// recorded measurement.  Builds the location table, the output rows
+// (measurements, or detectors then observables) and (M, c) as column lists.
+sp_model* assemble_model(const sp_circuit& c, int outputs, std::vector<int32_t> loc_var0, uint32_t n_vars,
+                         uint32_t n_random, const std::vector<Expr>& outcomes);
 }  // namespace sp

@@ -38,10 +38,7 @@
 namespace sp {
 namespace {
 
-struct Phase {
-  uint8_t c = 0;               // coefficient of s_0
-  std::vector<uint32_t> v;     // ascending variable indices (variable j = symbol s_{j+1})
-};
+using Phase = Expr;   // c: coefficient of s_0; v: ascending variable indices
 
 // a <- a + b over GF(2)
 void phase_add(Phase& a, const Phase& b, std::vector<uint32_t>& tmp) {
@@ -196,40 +193,20 @@ class SymTableau {
 }  // namespace
 
 sp_model* symbolize(const sp_circuit& c, int outputs) {
-  auto* mdl = new sp_model();
+  SymTableau tab(c.n_qubits);
+  std::vector<Phase> outcomes;
+  outcomes.reserve(c.n_meas);
+  std::vector<int32_t> loc_var0;
+  loc_var0.reserve(c.n_locs);
+  uint64_t n_vars = 0;
+  uint32_t n_random = 0;
+  auto take_vars = [&](uint32_t k) {
+    uint64_t v = n_vars;
+    n_vars += k;
+    if (n_vars >= (1ull << 24)) throw Error(SP_E_LIMIT, "more than 2^24 variables");
+    return v;
+  };
   try {
-    mdl->n_qubits = c.n_qubits;
-    mdl->outputs = outputs;
-    mdl->n_locs = c.n_locs;
-    mdl->channels = c.channels;
-    mdl->loc_kind.reserve(c.n_locs);
-    mdl->loc_chan.reserve(c.n_locs);
-    mdl->loc_var0.reserve(c.n_locs);
-
-    SymTableau tab(c.n_qubits);
-    std::vector<Phase> outcomes, dets, obs(c.n_observables);
-    std::vector<uint32_t> tmp;
-    outcomes.reserve(c.n_meas);
-    uint64_t n_vars = 0;
-
-    auto new_loc = [&](uint8_t kind, int32_t chan, int64_t var0) {
-      mdl->loc_kind.push_back(kind);
-      mdl->loc_chan.push_back(chan);
-      mdl->loc_var0.push_back((int32_t)var0);
-      if (var0 >= 0) {
-        for (uint32_t b = 0; b < loc_bits(kind); ++b) {
-          mdl->var_loc.push_back((uint32_t)(mdl->loc_kind.size() - 1));
-          mdl->var_bit.push_back((uint8_t)b);
-        }
-      }
-    };
-    auto take_vars = [&](uint32_t k) {
-      uint64_t v = n_vars;
-      n_vars += k;
-      if (n_vars >= (1ull << 24)) throw Error(SP_E_LIMIT, "more than 2^24 variables");
-      return v;
-    };
-
     for (const Op& op : c.ops) {
       const auto& t = op.targets;
       switch (op.kind) {
@@ -239,7 +216,7 @@ sp_model* symbolize(const sp_circuit& c, int outputs) {
         case OpKind::Y: for (uint32_t q : t) tab.pauli_const(q, 1, 1); break;
         case OpKind::Z: for (uint32_t q : t) tab.pauli_const(q, 0, 1); break;
         case OpKind::CX: for (size_t i = 0; i < t.size(); i += 2) tab.cx(t[i], t[i + 1]); break;
-        case OpKind::TICK: break;
+        case OpKind::TICK: case OpKind::DET: case OpKind::OBS: break;
         case OpKind::FX: case OpKind::FY: case OpKind::FZ: {
           const int px = op.kind != OpKind::FZ, pz = op.kind != OpKind::FX;
           for (size_t i = 0; i < t.size(); i += 2) {
@@ -248,6 +225,94 @@ sp_model* symbolize(const sp_circuit& c, int outputs) {
           }
           break;
         }
+        case OpKind::XERR: case OpKind::YERR: case OpKind::ZERR: {
+          const int px = op.kind != OpKind::ZERR, pz = op.kind != OpKind::XERR;
+          for (uint32_t q : t) {
+            uint32_t v = (uint32_t)take_vars(1);
+            loc_var0.push_back((int32_t)v);
+            tab.pauli_var(q, px, pz, v);  // Y^s = X^s Z^s: rows with x xor z
+          }
+          break;
+        }
+        case OpKind::DEP1:
+          for (uint32_t q : t) {
+            uint32_t v = (uint32_t)take_vars(2);
+            loc_var0.push_back((int32_t)v);
+            tab.pauli_var(q, 1, 0, v);       // bit 0: X^{s}
+            tab.pauli_var(q, 0, 1, v + 1);   // bit 1: Z^{s'}
+          }
+          break;
+        case OpKind::DEP2:
+          for (size_t i = 0; i < t.size(); i += 2) {
+            uint32_t v = (uint32_t)take_vars(4);
+            loc_var0.push_back((int32_t)v);
+            tab.pauli_var(t[i], 1, 0, v);
+            tab.pauli_var(t[i], 0, 1, v + 1);
+            tab.pauli_var(t[i + 1], 1, 0, v + 2);
+            tab.pauli_var(t[i + 1], 0, 1, v + 3);
+          }
+          break;
+        case OpKind::M: case OpKind::R: case OpKind::MR:
+          for (uint32_t q : t) {
+            Phase e;
+            bool rnd = tab.measure(q, (uint32_t)n_vars, e);
+            if (rnd) {
+              loc_var0.push_back((int32_t)take_vars(1));
+              ++n_random;
+            } else {
+              loc_var0.push_back(-1);
+            }
+            if (op.kind != OpKind::R) outcomes.push_back(e);
+            if (op.kind != OpKind::M) tab.pauli_expr(q, 1, 0, e);
+          }
+          break;
+      }
+    }
+  } catch (const std::bad_alloc&) {
+    throw Error(SP_E_NOMEM, "out of host memory in symbolize");
+  }
+  return assemble_model(c, outputs, std::move(loc_var0), (uint32_t)n_vars, n_random, outcomes);
+}
+
+sp_model* assemble_model(const sp_circuit& c, int outputs, std::vector<int32_t> loc_var0, uint32_t n_vars,
+                         uint32_t n_random, const std::vector<Expr>& outcomes) {
+  if (loc_var0.size() != c.n_locs || outcomes.size() != c.n_meas)
+    throw Error(SP_E_INVALID, "inconsistent Initialization result");
+  auto* mdl = new sp_model();
+  try {
+    mdl->n_qubits = c.n_qubits;
+    mdl->outputs = outputs;
+    mdl->n_locs = c.n_locs;
+    mdl->channels = c.channels;
+    mdl->n_vars = n_vars;
+    mdl->n_random = n_random;
+    mdl->loc_var0 = std::move(loc_var0);
+    mdl->loc_kind.reserve(c.n_locs);
+    mdl->loc_chan.reserve(c.n_locs);
+    std::vector<Phase> dets, obs(c.n_observables);
+    std::vector<uint32_t> tmp;
+    auto loc = [&](uint8_t kind, int32_t chan) {
+      const uint32_t l = (uint32_t)mdl->loc_kind.size();
+      const int32_t v0 = mdl->loc_var0[l];
+      mdl->loc_kind.push_back(kind);
+      mdl->loc_chan.push_back(v0 < 0 ? -1 : chan);
+      if (v0 >= 0)
+        for (uint32_t b = 0; b < loc_bits(kind); ++b) {
+          mdl->var_loc.push_back(l);
+          mdl->var_bit.push_back((uint8_t)b);
+        }
+    };
+    for (const Op& op : c.ops) {
+      const auto& t = op.targets;
+      switch (op.kind) {
+        case OpKind::XERR: for (size_t i = 0; i < t.size(); ++i) loc(L_XERR, op.chan); break;
+        case OpKind::YERR: for (size_t i = 0; i < t.size(); ++i) loc(L_YERR, op.chan); break;
+        case OpKind::ZERR: for (size_t i = 0; i < t.size(); ++i) loc(L_ZERR, op.chan); break;
+        case OpKind::DEP1: for (size_t i = 0; i < t.size(); ++i) loc(L_DEP1, op.chan); break;
+        case OpKind::DEP2: for (size_t i = 0; i < t.size(); i += 2) loc(L_DEP2, op.chan); break;
+        case OpKind::M: for (size_t i = 0; i < t.size(); ++i) loc(L_M, 0); break;
+        case OpKind::R: for (size_t i = 0; i < t.size(); ++i) loc(L_R, 0); break;
+        case OpKind::MR: for (size_t i = 0; i < t.size(); ++i) loc(L_MR, 0); break;
         case OpKind::DET: {
           Phase d;
           for (uint32_t k : t) phase_add(d, outcomes[k], tmp);
@@ -257,57 +322,13 @@ sp_model* symbolize(const sp_circuit& c, int outputs) {
         case OpKind::OBS:
           for (size_t i = 1; i < t.size(); ++i) phase_add(obs[t[0]], outcomes[t[i]], tmp);
           break;
-        case OpKind::XERR: case OpKind::YERR: case OpKind::ZERR: {
-          const int px = op.kind != OpKind::ZERR, pz = op.kind != OpKind::XERR;
-          const uint8_t lk = op.kind == OpKind::XERR ? L_XERR : op.kind == OpKind::YERR ? L_YERR : L_ZERR;
-          for (uint32_t q : t) {
-            uint32_t v = (uint32_t)take_vars(1);
-            new_loc(lk, op.chan, v);
-            tab.pauli_var(q, px, pz, v);  // Y^s = X^s Z^s: rows with x xor z
-          }
-          break;
-        }
-        case OpKind::DEP1:
-          for (uint32_t q : t) {
-            uint32_t v = (uint32_t)take_vars(2);
-            new_loc(L_DEP1, op.chan, v);
-            tab.pauli_var(q, 1, 0, v);       // bit 0: X^{s}
-            tab.pauli_var(q, 0, 1, v + 1);   // bit 1: Z^{s'}
-          }
-          break;
-        case OpKind::DEP2:
-          for (size_t i = 0; i < t.size(); i += 2) {
-            uint32_t v = (uint32_t)take_vars(4);
-            new_loc(L_DEP2, op.chan, v);
-            tab.pauli_var(t[i], 1, 0, v);
-            tab.pauli_var(t[i], 0, 1, v + 1);
-            tab.pauli_var(t[i + 1], 1, 0, v + 2);
-            tab.pauli_var(t[i + 1], 0, 1, v + 3);
-          }
-          break;
-        case OpKind::M: case OpKind::R: case OpKind::MR: {
-          const uint8_t lk = op.kind == OpKind::M ? L_M : op.kind == OpKind::R ? L_R : L_MR;
-          for (uint32_t q : t) {
-            Phase e;
-            bool rnd = tab.measure(q, (uint32_t)n_vars, e);
-            if (rnd) {
-              uint32_t v = (uint32_t)take_vars(1);
-              new_loc(lk, 0, v);
-              ++mdl->n_random;
-            } else {
-              new_loc(lk, -1, -1);
-            }
-            if (op.kind != OpKind::R) outcomes.push_back(e);
-            if (op.kind != OpKind::M) tab.pauli_expr(q, 1, 0, e);
-          }
-          break;
-        }
+        default: break;
       }
     }
-    mdl->n_vars = (uint32_t)n_vars;
+    if (mdl->var_loc.size() != n_vars) throw Error(SP_E_INVALID, "inconsistent variable count");
 
     // The output rows: recorded measurements, or detectors then observables.
-    std::vector<Phase>* rows = &outcomes;
+    const std::vector<Phase>* rows = &outcomes;
     if (outputs == SP_OUT_DETECTORS) {
       for (Phase& o : obs) dets.push_back(std::move(o));
       rows = &dets;
@@ -315,7 +336,7 @@ sp_model* symbolize(const sp_circuit& c, int outputs) {
     mdl->n_meas = (uint32_t)rows->size();
 
     // M as column lists, rows ascending; c as bits.
-    mdl->col_ptr.assign(n_vars + 1, 0);
+    mdl->col_ptr.assign((size_t)n_vars + 1, 0);
     mdl->c_bits.assign((rows->size() + 63) / 64 + 1, 0);
     for (const Phase& p : *rows)
       for (uint32_t v : p.v) mdl->col_ptr[v + 1]++;
