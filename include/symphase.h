@@ -148,6 +148,31 @@ int sp_symbolize(const sp_circuit* circuit, sp_model** out);
 int sp_symbolize_outputs(const sp_circuit* circuit, int outputs, sp_model** out);
 void sp_model_free(sp_model* model);
 
+/* Initialization (Section 3.2.2, Algorithm 1) on the GPU: the same pass as
+ * sp_symbolize_outputs, and the same model, bit for bit, computed by one
+ * 1024-thread workgroup on `stream` over a bit-packed tableau in the
+ * caller's device work buffer.  Circuits of up to 1024 qubits.
+ *
+ * sp_symbolize_device_work_bytes: the work-buffer size that always holds the
+ * tableau, the phase rows (n_qubits x ceil((n_vars + 1)/64) uint64 words at
+ * most) and the outcome records, plus room for the index lists of
+ * determined outcomes (their worst case, capped at 2^26 entries).
+ *
+ * sp_symbolize_device: d_work is device memory, 256-byte aligned, of
+ * work_bytes bytes (any size at least the fixed part; what is left holds the
+ * index lists); the library clears and uses it, and it is free again when
+ * the call returns.  The call is synchronous with respect to the host: it
+ * uploads the instruction stream, runs the kernel, copies the results back
+ * and assembles the model on the host (column lists, output rows) like
+ * sp_symbolize_outputs.  *out is owned by the caller (sp_model_free).
+ * Errors: SP_E_INVALID (null, misaligned or too small buffer, unknown
+ * outputs), SP_E_LIMIT (more than 1024 qubits or 2^24 variables, or the
+ * lists outgrow the buffer: the message gives a size that suffices),
+ * SP_E_NOMEM, SP_E_DEVICE. */
+int sp_symbolize_device_work_bytes(const sp_circuit* circuit, size_t* bytes);
+int sp_symbolize_device(const sp_circuit* circuit, int outputs, void* d_work, size_t work_bytes, void* stream,
+                        sp_model** out);
+
 int sp_model_dims(const sp_model* model, sp_dims* out);
 
 /* Expected work of one 64-shot word: fired locations (sum over drawn

@@ -81,19 +81,38 @@ _OUTPUTS = {"measurements": _capi.SP_OUT_MEASUREMENTS, "detectors": _capi.SP_OUT
 
 
 class Model:
-    """(M, c) and the location table (sp_symbolize_outputs): Algorithm 1,
-    Initialization.  outputs="measurements" gives one row per recorded
-    measurement; outputs="detectors" one row per detector, then one per
-    observable."""
+    """(M, c) and the location table: Algorithm 1, Initialization.
+    outputs="measurements" gives one row per recorded measurement;
+    outputs="detectors" one row per detector, then one per observable.
+    init="host" runs the pass on the CPU (sp_symbolize_outputs),
+    init="device" on the GPU (sp_symbolize_device, up to 1024 qubits) with a
+    work buffer from torch on `device`; both give the same model."""
 
-    def __init__(self, circuit: Circuit | str, outputs: str = "measurements"):
+    def __init__(self, circuit: Circuit | str, outputs: str = "measurements", init: str = "host", device=None,
+                 stream=None):
         if isinstance(circuit, str):
             circuit = Circuit(circuit)
         if outputs not in _OUTPUTS:
             raise ValueError(f"outputs must be one of {sorted(_OUTPUTS)}")
+        if init not in ("host", "device"):
+            raise ValueError("init must be 'host' or 'device'")
         self.outputs = outputs
         h = ctypes.c_void_p()
-        check(lib().sp_symbolize_outputs(circuit.handle, _OUTPUTS[outputs], ctypes.byref(h)))
+        if init == "host":
+            check(lib().sp_symbolize_outputs(circuit.handle, _OUTPUTS[outputs], ctypes.byref(h)))
+        else:
+            if not torch.cuda.is_available():
+                raise SymphaseError(-5, "no GPU: device Initialization runs only on the device")
+            device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+            n = ctypes.c_size_t()
+            check(lib().sp_symbolize_device_work_bytes(circuit.handle, ctypes.byref(n)))
+            with torch.cuda.device(device):
+                work = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
+                base = work.data_ptr()
+                off = (-base) % 256
+                check(lib().sp_symbolize_device(circuit.handle, _OUTPUTS[outputs], ctypes.c_void_p(base + off),
+                                                n.value, ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))
+            del work
         self._h = h
         d = sp_dims()
         check(lib().sp_model_dims(h, ctypes.byref(d)))

@@ -23,7 +23,7 @@ SP_OUT_MEASUREMENTS, SP_OUT_DETECTORS = 0, 1
 #: every function the header declares (checked by the tests)
 EXPORTS = (
     "sp_circuit_parse", "sp_circuit_free", "sp_circuit_counts", "sp_symbolize", "sp_symbolize_outputs",
-    "sp_model_free", "sp_model_dims",
+    "sp_symbolize_device_work_bytes", "sp_symbolize_device", "sp_model_free", "sp_model_dims",
     "sp_model_expected_work",
     "sp_model_export_dense", "sp_model_export_csc", "sp_model_export_vars", "sp_model_device_bytes",
     "sp_model_upload", "sp_dmodel_free", "sp_dmodel_dims", "sp_dmodel_get_launch", "sp_dmodel_set_launch",
@@ -89,6 +89,8 @@ def lib():
         "sp_circuit_free": ([vp], None),
         "sp_symbolize": ([vp, P(vp)], ctypes.c_int),
         "sp_symbolize_outputs": ([vp, ctypes.c_int, P(vp)], ctypes.c_int),
+        "sp_symbolize_device_work_bytes": ([vp, P(sz)], ctypes.c_int),
+        "sp_symbolize_device": ([vp, ctypes.c_int, vp, sz, vp, P(vp)], ctypes.c_int),
         "sp_circuit_counts": ([vp, P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32)],
                               ctypes.c_int),
         "sp_model_free": ([vp], None),

@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libsymphase_hip.so")
 
 ARCH = os.environ.get("SYMPHASE_ARCH", "gfx950")
 HOST_SRCS = ["circuit.cpp", "symbolize.cpp", "api.cpp"]
-HIP_SRCS = ["sample.hip", "batch.hip", "server.hip"]
+HIP_SRCS = ["sample.hip", "batch.hip", "server.hip", "init.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include")]
 # Packed FP32 instructions are disabled for all device code.

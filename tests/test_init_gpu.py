@@ -1,0 +1,235 @@
+"""Initialization on the GPU (sp_symbolize_device through the C ABI).
+
+The device pass is checked against the oracle: the paper's printed
+examples, (M, c) read off the oracle by probing one variable at a time,
+and M b + c against the oracle's outcomes for random fault codes.  Larger
+circuits, which the oracle cannot probe in seconds, are checked against
+the host pass (itself pinned to the oracle in test_symbolize.py) and by
+sampling the device-built model on the GPU against the oracle."""
+
+from __future__ import annotations
+
+import ctypes
+import re
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2311_03906_amd as sp
+from paper_2311_03906_amd import _capi
+from golden_io import example
+from workloads import random_clifford_circuit, random_layered_circuit, repetition_memory, surface_memory
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _device_model(text, outputs="measurements"):
+    return sp.Model(text, outputs=outputs, init="device")
+
+
+def _same_model(a, b):
+    """Bit-identical models: sizes, variable table, column lists, c."""
+    for f in ("n_qubits", "n_meas", "n_locs", "n_vars", "n_random_meas", "n_drawn", "n_draw_blocks", "nnz"):
+        assert getattr(a.dims, f) == getattr(b.dims, f), f
+    for x, y in zip(a.export_vars(), b.export_vars()):
+        assert np.array_equal(x, y)
+    for x, y in zip(a.export_csc(), b.export_csc()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.export_dense()[1], b.export_dense()[1])
+
+
+def _assignment(model_vars, codes):
+    var_loc, var_bit = model_vars
+    return ((codes[var_loc] >> var_bit) & 1).astype(np.uint8)
+
+
+def _evaluate(M, c, b):
+    return ((M.astype(np.int64) @ b.astype(np.int64)) + c) % 2
+
+
+@pytest.mark.parametrize("name", ["fig1.txt", "bell.txt"])
+def test_paper_examples_on_device(name):
+    """The paper's printed outcome expressions (Fig. 1 and the Bell
+    example), built on the GPU."""
+    text, symbols, outcomes = example(name)
+    _say(f"device init {name}")
+    m = _device_model(text)
+    M, c = m.export_dense()
+    var_loc, var_bit = m.export_vars()
+    col_of = {(int(l), int(b)): j for j, (l, b) in enumerate(zip(var_loc, var_bit))}
+    assert m.n_vars == len(symbols)
+    want = np.zeros((len(outcomes), m.n_vars), dtype=np.uint8)
+    for k, terms in enumerate(outcomes):
+        for s in terms:
+            want[k, col_of[symbols[s]]] ^= 1
+    assert np.array_equal(M, want)
+    assert not c.any()
+
+
+_SMALL = [("rep3", repetition_memory(3, 3, 1e-3, detectors=True)),
+          ("surf3", surface_memory(3, 3, "0.01", detectors=True)),
+          ("surf3_feedback", surface_memory(3, 3, "0.01", detectors=True, reset="feedback")),
+          ("layered12", random_layered_circuit(12, seed=1, cnot_pairs=6, p_dep="0.01")),
+          ("random_feedback", random_clifford_circuit(11, 4, 40, feedback=True, detectors=True))]
+
+
+@pytest.mark.parametrize("outputs", ["measurements", "detectors"])
+@pytest.mark.parametrize("name,circ", _SMALL, ids=[n for n, _ in _SMALL])
+def test_device_model_equals_oracle_probing(name, circ, outputs):
+    """(M, c) of the device pass equal the oracle's outputs with one code
+    bit set at a time (columns) and none set (c)."""
+    if outputs == "detectors" and circ.n_detectors + circ.n_observables == 0:
+        pytest.skip("no detectors")
+    text = circ.text()
+    _say(f"device init probing {name} {outputs}")
+    m = _device_model(text, outputs)
+    oc = oracle.Circuit(text, outputs=outputs)
+    var_loc, var_bit = m.export_vars()
+    zero = np.zeros(oc.n_locs, dtype=np.uint8)
+    c0 = oc.rows_from_outcomes(oc.run_codes(zero)[0])
+    cols = []
+    for l, b in zip(var_loc, var_bit):
+        codes = zero.copy()
+        codes[l] = 1 << b
+        cols.append(oc.rows_from_outcomes(oc.run_codes(codes)[0]) ^ c0)
+    M_or = np.array(cols, dtype=np.uint8).T if cols else np.zeros((oc.n_rows, 0), dtype=np.uint8)
+    M, c = m.export_dense()
+    assert np.array_equal(M, M_or)
+    assert np.array_equal(c, c0)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_device_model_matches_oracle_on_random_circuits(seed):
+    """Random noisy Clifford circuits with resets, feedback, detectors and
+    observables: M b + c of the device model equals the oracle's outputs for
+    random codes at every location (a location the device wrongly took as
+    determined, or a wrong variable, changes some output)."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 9))
+    n_ops = int(rng.integers(1, 80))
+    text = random_clifford_circuit(seed, n, n_ops, feedback=True, detectors=True).text()
+    for outputs in ("measurements", "detectors"):
+        oc = oracle.Circuit(text, outputs=outputs)
+        m = _device_model(text, outputs)
+        M, c = m.export_dense()
+        mv = m.export_vars()
+        kinds = oc.location_kinds()
+        for _ in range(4):
+            codes = np.array([rng.integers(0, 2 ** oracle.CODE_BITS[int(k)]) for k in kinds], dtype=np.uint8)
+            want = oc.rows_from_outcomes(oc.run_codes(codes)[0])
+            assert np.array_equal(_evaluate(M, c, _assignment(mv, codes)), want)
+
+
+_LARGE = [("surf5", lambda: surface_memory(5, 5, 1e-3, detectors=True)),
+          ("surf7_feedback", lambda: surface_memory(7, 7, "0.005", detectors=True, reset="feedback")),
+          ("rep25", lambda: repetition_memory(25, 25, "0.01", detectors=True)),
+          ("fig3a_n60", lambda: random_layered_circuit(60, seed=2, cnot_pairs=5)),
+          ("fig3b_n60", lambda: random_layered_circuit(60, seed=2)),
+          ("fig3c_n60", lambda: random_layered_circuit(60, seed=2, p_dep="0.001")),
+          ("fig3c_n130", lambda: random_layered_circuit(130, seed=4, p_dep="0.001")),
+          ("random_feedback_64q", lambda: random_clifford_circuit(5, 64, 3000, feedback=True, detectors=True))]
+
+
+@pytest.mark.parametrize("outputs", ["measurements", "detectors"])
+@pytest.mark.parametrize("name,make", _LARGE, ids=[n for n, _ in _LARGE])
+def test_device_model_equals_host_model(name, make, outputs):
+    """Several tableau words per column, several phase words per row, many
+    instructions split into runs: the device model is bit-identical to the
+    host pass."""
+    circ = make()
+    if outputs == "detectors" and circ.n_detectors + circ.n_observables == 0:
+        pytest.skip("no detectors")
+    text = circ.text()
+    _say(f"device init vs host {name} {outputs}")
+    _same_model(_device_model(text, outputs), sp.Model(text, outputs=outputs))
+
+
+def test_surface_d15_detectors_device_model():
+    """The served workload's circuit (surface d=15, 15 rounds, 449 qubits,
+    p = 5e-3, detector outputs): device model equals the host model."""
+    text = surface_memory(15, 15, "0.005", detectors=True).text()
+    _say("device init surface d15 detectors")
+    _same_model(_device_model(text, "detectors"), sp.Model(text, outputs="detectors"))
+
+
+def test_max_qubits():
+    """1024 qubits (the limit: 32 tableau words per column) with
+    measurements, resets and faults on the highest qubits."""
+    n = 1024
+    rng = np.random.default_rng(7)
+    lines = [f"H {' '.join(map(str, range(0, n, 2)))}"]
+    for _ in range(6):
+        perm = rng.permutation(n)
+        lines.append("CX " + " ".join(map(str, perm)))
+        lines.append("DEPOLARIZE1(0.001) " + " ".join(map(str, rng.choice(n, 64, replace=False))))
+        lines.append("S " + " ".join(map(str, rng.choice(n, 300, replace=False))))
+        lines.append("M " + " ".join(map(str, rng.choice(n, 40, replace=False))))
+        lines.append("CX rec[-1] 1023 rec[-2] 1000")
+    lines.append("MR 1023 1022 0")
+    lines.append("M " + " ".join(map(str, range(n))))
+    text = "\n".join(lines) + "\n"
+    _say("device init 1024 qubits")
+    _same_model(_device_model(text), sp.Model(text))
+
+
+def test_device_model_samples_equal_oracle():
+    """The whole device path: a model built on the GPU, uploaded and sampled
+    on the GPU, equals the oracle's samples word for word."""
+    text = surface_memory(5, 5, "0.005", detectors=True, reset="feedback").text()
+    _say("device init + sample surface d5 feedback detectors")
+    m = _device_model(text, "detectors")
+    dm = sp.DeviceModel(m)
+    out = dm.sample(20_000, seed=4)
+    torch.cuda.synchronize()
+    got = sp.to_numpy_bits(out)[: dm.n_meas]
+    want = oracle.Circuit(text, outputs="detectors").sample(seed=4, first_shot=0, shots=20_000)
+    assert np.array_equal(got, want)
+
+
+def test_degenerate_circuits():
+    """No instructions, no measurements, only gates, only faults."""
+    for text in ["", "H 0\nS 1\nCX 0 1\n", "X_ERROR(0.1) 0 1 2\n", "M 0\n", "R 0 1\nM 1\n"]:
+        _say(f"device init degenerate {text!r}")
+        _same_model(_device_model(text), sp.Model(text))
+
+
+def test_index_list_overflow_is_reported():
+    """A buffer with no room for the determined outcomes' index lists gives
+    SP_E_LIMIT (the kernel flags it and ends normally); a buffer of the size
+    the message names then gives the host pass's model."""
+    text = repetition_memory(5, 5, "0.01").text()
+    c = sp.Circuit(text)
+    L = _capi.lib()
+    need = ctypes.c_size_t()
+    _capi.check(L.sp_symbolize_device_work_bytes(c.handle, ctypes.byref(need)))
+    work = torch.zeros(need.value + 256, dtype=torch.uint8, device="cuda")
+    base = ctypes.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
+    h = ctypes.c_void_p()
+    # too small for the fixed part: rejected before any device work
+    assert L.sp_symbolize_device(c.handle, 0, base, 256, None, ctypes.byref(h)) == _capi.SP_E_INVALID
+    fixed = int(re.search(r"need at least (\d+)", L.sp_last_error().decode()).group(1))
+    assert 256 < fixed < need.value
+    _say("device init list overflow")
+    assert L.sp_symbolize_device(c.handle, 0, base, fixed, None, ctypes.byref(h)) == _capi.SP_E_LIMIT
+    enough = int(re.search(r"at most (\d+) bytes suffice", L.sp_last_error().decode()).group(1))
+    assert enough <= need.value
+    _capi.check(L.sp_symbolize_device(c.handle, 0, base, enough, None, ctypes.byref(h)))
+    try:
+        ref = sp.Model(text)
+        d = _capi.sp_dims()
+        _capi.check(L.sp_model_dims(h, ctypes.byref(d)))
+        assert (d.n_vars, d.nnz, d.n_meas) == (ref.dims.n_vars, ref.dims.nnz, ref.dims.n_meas)
+        cp = np.zeros(d.n_vars + 1, dtype=np.uint32)
+        ri = np.zeros(max(1, d.nnz), dtype=np.uint32)
+        _capi.check(L.sp_model_export_csc(h, cp.ctypes.data, ri.ctypes.data))
+        want_cp, want_ri = ref.export_csc()
+        assert np.array_equal(cp, want_cp) and np.array_equal(ri[: d.nnz], want_ri)
+    finally:
+        L.sp_model_free(h)

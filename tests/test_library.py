@@ -58,3 +58,29 @@ def test_sampling_requires_a_gpu_and_has_no_fallback():
     m = sp.Model("X_ERROR(0.1) 0\nM 0\n")
     with pytest.raises(sp.SymphaseError):
         sp.DeviceModel(m)
+
+
+def test_device_initialization_checks_arguments_before_device_work():
+    """sp_symbolize_device rejects what it cannot do before it touches the
+    device: the pointer below is never dereferenced."""
+    import ctypes
+    import paper_2311_03906_amd as sp
+    L, E = sp.lib(), sp._capi
+    fake = ctypes.c_void_p(1 << 20)   # 256-byte aligned, never used
+    h = ctypes.c_void_p()
+    c = sp.Circuit("H 0\nCX 0 1\nX_ERROR(0.1) 1\nM 0 1\n")
+    need = ctypes.c_size_t()
+    assert L.sp_symbolize_device_work_bytes(c.handle, ctypes.byref(need)) == 0 and need.value > 0
+    assert L.sp_symbolize_device(None, 0, fake, need.value, None, ctypes.byref(h)) == E.SP_E_INVALID
+    assert L.sp_symbolize_device(c.handle, 0, None, need.value, None, ctypes.byref(h)) == E.SP_E_INVALID
+    assert L.sp_symbolize_device(c.handle, 7, fake, need.value, None, ctypes.byref(h)) == E.SP_E_INVALID
+    assert L.sp_symbolize_device(c.handle, 0, ctypes.c_void_p((1 << 20) + 8), need.value, None,
+                                 ctypes.byref(h)) == E.SP_E_INVALID
+    assert b"aligned" in L.sp_last_error()
+    assert L.sp_symbolize_device(c.handle, 0, fake, 256, None, ctypes.byref(h)) == E.SP_E_INVALID
+    assert b"need at least" in L.sp_last_error()
+    big = sp.Circuit("M 1024\n")   # 1025 qubits
+    assert L.sp_symbolize_device_work_bytes(big.handle, ctypes.byref(need)) == E.SP_E_LIMIT
+    assert L.sp_symbolize_device(big.handle, 0, fake, 1 << 30, None, ctypes.byref(h)) == E.SP_E_LIMIT
+    assert b"1024 qubits" in L.sp_last_error()
+    assert h.value is None
