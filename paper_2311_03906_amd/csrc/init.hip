@@ -13,7 +13,8 @@
 //   P     the symbol part of each stabilizer's phase, one dense bit row of W
 //         words per stabilizer (bit j = variable j): the (n_s+1)-bit phase
 //         rows of Eq. 3 without the constant.
-//   E     the expression of the latest determined measurement (W words).
+//   E     the expression of a determined measurement (two alternating
+//         buffers of W words).
 // Destabilizer phases are never read (as on the host).
 //
 // Init-P: the fault variable j on qubit q adds s_j to the stabilizer rows
@@ -55,6 +56,7 @@ constexpr uint32_t kThreads = 1024;
 constexpr uint32_t kMaxQubits = 1024;
 constexpr uint32_t kMaxRW = 2 * kMaxQubits / 64;   // 32
 constexpr uint32_t kChunks = 32;                   // column chunks of the random-branch g sums
+constexpr size_t kStaticLds = 32 * 1024;           // at least the kernel's static LDS
 
 // Device instruction stream: a header word (opcode | count << 8), then
 // `count` items.
@@ -112,6 +114,14 @@ __device__ __forceinline__ void g_masks(uint64_t lx, uint64_t lz, uint64_t rx, u
 }
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+  return (uint64_t)uni((uint32_t)v) | (uint64_t)uni((uint32_t)(v >> 32)) << 32;
+}
+// Lane `src`'s value (src uniform).
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t src) {
+  return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)src) |
+         (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)src) << 32;
+}
 
 // A vector load of memory this kernel writes, also where the address is
 // uniform (a scalar-cache load would not see the workgroup's own stores).
@@ -120,65 +130,82 @@ __device__ __forceinline__ T ld(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// TAB_LDS: the tableau lives in dynamic LDS (2 n RW words), else in the
+// work buffer.
+template <bool TAB_LDS>
 __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
+  extern __shared__ uint64_t s_tab[];
   __shared__ uint64_t s_C[kMaxRW];      // constant phase bit of every row
-  __shared__ uint64_t s_mask[kMaxRW];
-  __shared__ uint64_t s_t[kMaxRW];
+  __shared__ uint64_t s_mask[kMaxRW];   // x_a of every row but p, before a random measurement's update
   __shared__ uint64_t s_c0[kMaxRW * kChunks];
   __shared__ uint64_t s_c1[kMaxRW * kChunks];
-  __shared__ uint32_t s_rows[kMaxQubits];
+  __shared__ uint32_t s_rows[kMaxQubits];    // rows of the current measurement's row operations
+  __shared__ uint32_t s_rows2[kMaxQubits];   // stabilizer rows with z_a, for a reset
+  __shared__ uint32_t s_cnt[2];
+  __shared__ uint32_t s_red[kThreads / 64];
   __shared__ uint32_t s_scan[kThreads / 64];
-  __shared__ uint32_t s_u32[4];
-
   const uint32_t tid = threadIdx.x;
   const uint32_t n = d.n, RW = d.RW, W = d.W;
 
-  // |0...0>: destabilizer i = X_i, stabilizer i = Z_i (buffers arrive zeroed).
+  uint64_t* const X = TAB_LDS ? s_tab : d.X;
+  uint64_t* const Z = TAB_LDS ? s_tab + (size_t)n * RW : d.Z;
+  if (TAB_LDS) {
+    for (uint32_t i = tid; i < 2 * n * RW; i += kThreads) s_tab[i] = 0;
+    __syncthreads();
+  }
+  // |0...0>: destabilizer i = X_i, stabilizer i = Z_i (the work buffer arrives zeroed).
   if (tid < kMaxRW) s_C[tid] = 0;
   for (uint32_t q = tid; q < n; q += kThreads) {
-    d.X[(size_t)q * RW + (q >> 6)] |= 1ull << (q & 63);
-    d.Z[(size_t)q * RW + ((n + q) >> 6)] |= 1ull << ((n + q) & 63);
+    X[(size_t)q * RW + (q >> 6)] |= 1ull << (q & 63);
+    Z[(size_t)q * RW + ((n + q) >> 6)] |= 1ull << ((n + q) & 63);
   }
   __syncthreads();
 
   uint32_t vars = 0, n_random = 0, nloc = 0, nrec = 0, listu = 0, overflow = 0;
+  const uint32_t lane = tid & 63u, wave = tid >> 6;
+  const uint32_t sw0 = n >> 6, sw1 = n ? (2 * n - 1) >> 6 : 0;   // words holding stabilizer rows
 
-  // Rows of s_mask (its stabilizer or its destabilizer part) into s_rows,
-  // ascending; returns the count.  One wave: lane l places bit l of each word.
-  auto list_rows = [&](bool stab) -> uint32_t {
-    if (tid < 64) {
-      uint32_t cnt = 0;
-      for (uint32_t w = 0; w < RW; ++w) {
-        const uint64_t m = s_mask[w] & (stab ? stab_mask(w, n) : destab_mask(w, n));
-        if ((m >> tid) & 1u) s_rows[cnt + (uint32_t)__builtin_popcountll(m & ((1ull << tid) - 1))] = w * 64 + tid;
-        cnt += (uint32_t)__builtin_popcountll(m);
+  // A uniform loop over the set stabilizer rows of a mask, run by every wave
+  // alike (no barrier, no shared list): word(w) returns mask word w (a
+  // uniform value).
+  auto for_stab_rows = [&](auto word, auto body) {
+    for (uint32_t w = sw0; n && w <= sw1; ++w) {
+      uint64_t m = word(w) & stab_mask(w, n);
+      while (m) {
+        body(w * 64 + (uint32_t)__builtin_ctzll(m));
+        m &= m - 1;
       }
-      if (tid == 0) s_u32[1] = cnt;
     }
-    __syncthreads();
-    return uni(s_u32[1]);
+  };
+  // Mask word w of the rows anticommuting with X^px Z^pz on qubit q.
+  auto pauli_rows = [&](uint32_t q, uint32_t px, uint32_t pz, uint32_t w) -> uint64_t {
+    return uni64((px ? ld(Z + (size_t)q * RW + w) : 0ull) ^ (pz ? ld(X + (size_t)q * RW + w) : 0ull));
   };
 
-  // X^(px e) Z^(pz e) on qubit q for an outcome expression e: adds e to the
-  // stabilizer rows the Pauli anticommutes with (Fact 1 with a vector
-  // exponent).  e is the single variable e_var, or (e_var < 0) the first Wt
-  // words of E, plus the constant e_c.
-  auto add_expr = [&](uint32_t q, uint32_t px, uint32_t pz, int32_t e_var, uint32_t e_c, uint32_t Wt) {
-    if (tid < RW)
-      s_mask[tid] = ((px ? d.Z[(size_t)q * RW + tid] : 0ull) ^ (pz ? d.X[(size_t)q * RW + tid] : 0ull)) &
-                    stab_mask(tid, n);
-    __syncthreads();
-    const uint32_t nr = list_rows(true);
-    if (e_var >= 0) {
-      for (uint32_t i = tid; i < nr; i += kThreads)
-        d.P[(size_t)(s_rows[i] - n) * W + ((uint32_t)e_var >> 6)] ^= 1ull << ((uint32_t)e_var & 63);
-    } else {
-      for (uint32_t i = tid; i < nr * Wt; i += kThreads) {
-        const uint32_t r = s_rows[i / Wt], w = i % Wt;
-        d.P[(size_t)(r - n) * W + w] ^= d.E[w];
+  // Wave 0 lists the set rows of a mask (its stabilizer or destabilizer
+  // part) into dst, ascending, and the count into s_cnt[slot]; the others
+  // read them after the next barrier.  word(w) returns mask word w, loaded
+  // by lane w at once.
+  auto rows_to_lds = [&](uint32_t* dst, uint32_t slot, auto word, bool stab) {
+    if (wave == 0) {
+      const uint64_t mw = lane < RW ? word(lane) & (stab ? stab_mask(lane, n) : destab_mask(lane, n)) : 0ull;
+      uint32_t cnt = 0;
+      for (uint32_t w = 0; w < RW; ++w) {
+        const uint64_t m = readlane64(mw, w);
+        if ((m >> lane) & 1u) dst[cnt + (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1))] = w * 64 + lane;
+        cnt += (uint32_t)__builtin_popcountll(m);
       }
+      if (lane == 0) s_cnt[slot] = cnt;
     }
-    if (e_c && tid < RW) s_C[tid] ^= s_mask[tid];
+  };
+  // X^(px s) Z^(pz s) on qubit q for a single variable s adds s to the
+  // stabilizer rows the Pauli anticommutes with (Fact 1).  Ends with a barrier.
+  auto add_var = [&](uint32_t q, uint32_t px, uint32_t pz, uint32_t var) {
+    if (tid < n) {
+      const uint32_t row = n + tid;
+      const uint32_t c = (px & bit_of(Z + (size_t)q * RW, row)) ^ (pz & bit_of(X + (size_t)q * RW, row));
+      if (c) d.P[(size_t)tid * W + (var >> 6)] ^= 1ull << (var & 63);
+    }
     __syncthreads();
   };
 
@@ -194,18 +221,18 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
         const uint32_t item = it[k];
         if (op == D_CX) {
           const uint32_t a = item & 0xFFFFu, b = item >> 16;
-          uint64_t& xa = d.X[(size_t)a * RW + w];
-          uint64_t& za = d.Z[(size_t)a * RW + w];
-          uint64_t& xb = d.X[(size_t)b * RW + w];
-          uint64_t& zb = d.Z[(size_t)b * RW + w];
+          uint64_t& xa = X[(size_t)a * RW + w];
+          uint64_t& za = Z[(size_t)a * RW + w];
+          uint64_t& xb = X[(size_t)b * RW + w];
+          uint64_t& zb = Z[(size_t)b * RW + w];
           const uint64_t vxa = xa, vza = za, vxb = xb, vzb = zb;
           const uint64_t t = vxa & vzb & ~(vxb ^ vza);
           if (t) atomicXor((unsigned long long*)&s_C[w], (unsigned long long)t);
           xb = vxb ^ vxa;
           za = vza ^ vzb;
         } else {
-          uint64_t& x = d.X[(size_t)item * RW + w];
-          uint64_t& z = d.Z[(size_t)item * RW + w];
+          uint64_t& x = X[(size_t)item * RW + w];
+          uint64_t& z = Z[(size_t)item * RW + w];
           const uint64_t vx = x, vz = z;
           uint64_t t;
           if (op == D_H || op == D_S) t = vx & vz;
@@ -242,21 +269,22 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
       const uint32_t sw0 = n >> 6, sw1 = (2 * n - 1) >> 6;
       for (uint32_t vw = vw0 + (tid >> 6); vw <= vw1; vw += kThreads / 64) {
         const uint32_t v = vw * 64 + lane;
-        const uint64_t* col_z = nullptr;
-        const uint64_t* col_x = nullptr;
+        bool use_z = false, use_x = false;
+        uint32_t qc = 0;
         if (v >= vars && v < vars + nv) {
           const uint32_t rel = v - vars, item = it[rel >> lg], b = rel & ((1u << lg) - 1u);
           const uint32_t kind = item >> 28;
           const uint32_t q = b >= 2 ? (item >> 14) & 0x3FFFu : item & 0x3FFFu;
           const bool xf = kind == F_X || kind == F_Y || ((kind == F_DEP1 || kind == F_DEP2) && !(b & 1u));
           const bool zf = kind == F_Z || kind == F_Y || ((kind == F_DEP1 || kind == F_DEP2) && (b & 1u));
-          if (xf) col_z = d.Z + (size_t)q * RW;
-          if (zf) col_x = d.X + (size_t)q * RW;
+          use_z = xf;
+          use_x = zf;
+          qc = q;
         }
         for (uint32_t w = sw0; w <= sw1; ++w) {
           uint64_t col = 0;
-          if (col_z) col ^= col_z[w];
-          if (col_x) col ^= col_x[w];
+          if (use_z) col ^= Z[(size_t)qc * RW + w];
+          if (use_x) col ^= X[(size_t)qc * RW + w];
           col &= stab_mask(w, n);
           if (__ballot(col != 0) == 0) continue;
           uint64_t out = 0;
@@ -276,38 +304,39 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
       continue;
     }
 
-    // Outcome records written by one thread are read by all below.
-    __syncthreads();
-
     if (op == D_FB) {
+      // Outcome records written by one thread are read by all below.
+      __syncthreads();
       for (uint32_t k = 0; k < cnt; ++k) {
         const uint32_t rec = uni(it[2 * k]), qp = uni(it[2 * k + 1]);
         const uint32_t q = qp & 0xFFFFu, pauli = qp >> 16;   // 1 X, 2 Y, 3 Z
         const uint32_t px = pauli != 3, pz = pauli != 1;
         const int32_t rv = (int32_t)uni((uint32_t)ld(d.rec_var + rec));
         const uint32_t ec = uni(ld(d.rec_c + rec));
-        const uint32_t off = uni(ld(d.rec_off + rec)), len = uni(ld(d.rec_len + rec));
-        const uint32_t Wt = (vars + 63) >> 6;
-        if (rv < 0) {
-          // E <- the recorded list as a dense row; the first entry of each
-          // word gathers that word's entries (the list is ascending).
-          for (uint32_t w = tid; w < Wt; w += kThreads) d.E[w] = 0;
-          __syncthreads();
-          for (uint32_t i = tid; i < len; i += kThreads) {
-            const uint32_t s0 = ld(d.list + off + i), w = s0 >> 6;
-            if (i == 0 || (ld(d.list + off + i - 1) >> 6) != w) {
-              uint64_t e = 0;
-              for (uint32_t j = i; j < len; ++j) {
-                const uint32_t sj = ld(d.list + off + j);
-                if ((sj >> 6) != w) break;
-                e |= 1ull << (sj & 63);
-              }
-              d.E[w] = e;
-            }
-          }
-          __syncthreads();
+        if (rv >= 0) {   // a random record: its variable alone, constant 0
+          add_var(q, px, pz, (uint32_t)rv);
+          continue;
         }
-        add_expr(q, px, pz, rv, ec, Wt);
+        // A determined record: its ascending index list, by words; the first
+        // entry of each word gathers that word and adds it to the rows.
+        const uint32_t off = uni(ld(d.rec_off + rec)), len = uni(ld(d.rec_len + rec));
+        for (uint32_t i = tid; i < len; i += kThreads) {
+          const uint32_t w = ld(d.list + off + i) >> 6;
+          if (i == 0 || (ld(d.list + off + i - 1) >> 6) != w) {
+            uint64_t e = 0;
+            for (uint32_t j = i; j < len; ++j) {
+              const uint32_t sj = ld(d.list + off + j);
+              if ((sj >> 6) != w) break;
+              e |= 1ull << (sj & 63);
+            }
+            for_stab_rows([&](uint32_t ww) { return pauli_rows(q, px, pz, ww); },
+                          [&](uint32_t r) { d.P[(size_t)(r - n) * W + w] ^= e; });
+          }
+        }
+        if (ec && tid < RW)
+          s_C[tid] ^= ((px ? Z[(size_t)q * RW + tid] : 0ull) ^ (pz ? X[(size_t)q * RW + tid] : 0ull)) &
+                      stab_mask(tid, n);
+        __syncthreads();
       }
       continue;
     }
@@ -315,38 +344,56 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
     // D_M, D_R, D_MR: one location per target, in order.
     for (uint32_t k = 0; k < cnt; ++k) {
       const uint32_t a = uni(it[k]);
-      const uint64_t* xa = d.X + (size_t)a * RW;
-      if (tid == 0) s_u32[0] = 0xFFFFFFFFu;
-      __syncthreads();
-      if (tid < RW) {
-        const uint64_t m = xa[tid] & stab_mask(tid, n);
-        if (m) atomicMin(&s_u32[0], tid * 64 + (uint32_t)__builtin_ctzll(m));
+      const uint64_t* xa = X + (size_t)a * RW;
+      // Pivot: the first stabilizer row with x_a = 1, found by every wave.
+      uint32_t p = 0xFFFFFFFFu;
+      {
+        const uint64_t m = lane < RW ? ld(xa + lane) & stab_mask(lane, n) : 0ull;
+        const uint64_t nz = __ballot(m != 0);
+        if (nz) {
+          const uint32_t w = (uint32_t)__builtin_ctzll(nz);
+          p = w * 64 + (uint32_t)__builtin_ctzll(readlane64(m, w));
+        }
+        p = uni(p);
       }
-      __syncthreads();
-      const uint32_t p = uni(s_u32[0]);
       int32_t e_var = -1;
       uint32_t e_c = 0;
       const uint32_t Wt = (vars + 1 + 63) >> 6;   // words holding every variable so far, and one more
+      // Two alternating buffers: a buffer is rewritten two measurements
+      // later, after barriers every thread passes only once done with it.
+      uint64_t* const Ecur = d.E + (size_t)(nloc & 1u) * W;
 
       if (p != 0xFFFFFFFFu) {
-        // ---- random outcome: a fresh variable -----------------------------
+        // ---- random outcome: a fresh variable ------------------------------
         e_var = (int32_t)vars;
         if (tid == 0) d.loc_var0[nloc] = (int32_t)vars;
         ++vars;
         ++n_random;
-        if (tid < RW) s_mask[tid] = xa[tid] & ~(tid == (p >> 6) ? (1ull << (p & 63)) : 0ull);
-        __syncthreads();
+        const uint32_t pw = p >> 6;
+        const uint64_t pb = 1ull << (p & 63);
+        rows_to_lds(s_rows, 0, [&](uint32_t w) { return ld(xa + w) & ~(w == pw ? pb : 0ull); }, true);
+        if (tid < RW) s_mask[tid] = ld(xa + tid) & ~(tid == pw ? pb : 0ull);
+        const uint32_t cp = bit_of(s_C, p);
+        // Row p's symbols move to Ecur, to be added to the rows below; row p
+        // becomes the fresh variable alone.
+        {
+          uint64_t* pp = d.P + (size_t)(p - n) * W;
+          for (uint32_t w = tid; w < Wt; w += kThreads) {
+            Ecur[w] = pp[w];
+            pp[w] = w == ((uint32_t)e_var >> 6) ? 1ull << ((uint32_t)e_var & 63) : 0ull;
+          }
+        }
         // g sums of every row against row p, bit-sliced mod 4, per (word, column chunk).
         {
           const uint32_t w = tid % kMaxRW, chunk = tid / kMaxRW;
           if (w < RW) {
             uint64_t c0 = 0, c1 = 0;
-            const uint64_t mw = s_mask[w];
+            const uint64_t mw = ld(xa + w) & ~(w == pw ? pb : 0ull);
             if (mw) {
               for (uint32_t q = chunk; q < n; q += kChunks) {
-                const uint64_t* xq = d.X + (size_t)q * RW;
-                const uint64_t* zq = d.Z + (size_t)q * RW;
-                const uint64_t lx = bit_of(xq, p) ? ~0ull : 0ull, lz = bit_of(zq, p) ? ~0ull : 0ull;
+                const uint64_t* xq = X + (size_t)q * RW;
+                const uint64_t* zq = Z + (size_t)q * RW;
+                const uint64_t lx = (xq[pw] & pb) ? ~0ull : 0ull, lz = (zq[pw] & pb) ? ~0ull : 0ull;
                 if (!(lx | lz)) continue;
                 uint64_t plus, minus;
                 g_masks(lx, lz, xq[w], zq[w], plus, minus);
@@ -362,6 +409,8 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
           }
         }
         __syncthreads();
+        // Constants of the rows taking row p (the sums are even for
+        // commuting rows: bit 1 says "2 mod 4"); row p's becomes 0.
         if (tid < RW) {
           uint64_t c0 = 0, c1 = 0;
           for (uint32_t ch = 0; ch < kChunks; ++ch) {
@@ -369,129 +418,125 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
             c1 ^= b1 ^ (c0 & b0);
             c0 ^= b0;
           }
-          s_t[tid] = c1;   // the sums are even for commuting rows: bit 1 says "2 mod 4"
+          uint64_t cw = s_C[tid] ^ (s_mask[tid] & stab_mask(tid, n) & (c1 ^ (cp ? ~0ull : 0ull)));
+          if (tid == pw) cw &= ~pb;
+          s_C[tid] = cw;
         }
-        const uint32_t cp = bit_of(s_C, p);
-        const uint32_t nrows = list_rows(true);   // stabilizer rows taking row p (also syncs s_t)
-        // Constants, then symbols of the stabilizer rows, then x/z of every row.
-        if (tid < RW) {
-          const uint64_t m = s_mask[tid] & stab_mask(tid, n);
-          s_C[tid] ^= m & (s_t[tid] ^ (cp ? ~0ull : 0ull));
-        }
+        // Symbols: every stabilizer row with x_a adds row p's old ones.
         {
-          const uint64_t* pp = d.P + (size_t)(p - n) * W;
-          for (uint32_t i = tid; i < nrows * Wt; i += kThreads) {
+          const uint32_t nr = s_cnt[0];
+          for (uint32_t i = tid; i < nr * Wt; i += kThreads) {
             const uint32_t r = s_rows[i / Wt], w = i % Wt;
-            d.P[(size_t)(r - n) * W + w] ^= pp[w];
+            const uint64_t v = Ecur[w];
+            if (v) d.P[(size_t)(r - n) * W + w] ^= v;
           }
         }
-        for (uint32_t i = tid; i < n * RW; i += kThreads) {
-          const uint32_t q = i / RW, w = i % RW;
-          uint64_t* xq = d.X + (size_t)q * RW;
-          uint64_t* zq = d.Z + (size_t)q * RW;
-          const uint64_t lx = bit_of(xq, p) ? ~0ull : 0ull, lz = bit_of(zq, p) ? ~0ull : 0ull;
-          xq[w] ^= s_mask[w] & lx;
-          zq[w] ^= s_mask[w] & lz;
-        }
-        __syncthreads();
-        // Destabilizer p-n <- row p; row p <- Z_a with phase +s_var.
+        // Tableau, one thread per column: rows with x_a take row p's x/z;
+        // destabilizer p-n becomes row p; row p becomes Z_a.
         for (uint32_t q = tid; q < n; q += kThreads) {
-          uint64_t* xq = d.X + (size_t)q * RW;
-          uint64_t* zq = d.Z + (size_t)q * RW;
-          const uint32_t bx = bit_of(xq, p), bz = bit_of(zq, p);
-          const uint32_t dr = p - n;
-          xq[dr >> 6] = (xq[dr >> 6] & ~(1ull << (dr & 63))) | ((uint64_t)bx << (dr & 63));
-          zq[dr >> 6] = (zq[dr >> 6] & ~(1ull << (dr & 63))) | ((uint64_t)bz << (dr & 63));
-          xq[p >> 6] &= ~(1ull << (p & 63));
-          zq[p >> 6] = (zq[p >> 6] & ~(1ull << (p & 63))) | ((q == a ? 1ull : 0ull) << (p & 63));
-        }
-        if (tid == 0) s_C[p >> 6] &= ~(1ull << (p & 63));
-        {
-          uint64_t* pp = d.P + (size_t)(p - n) * W;
-          const uint32_t Wn = (vars + 63) >> 6;
-          for (uint32_t w = tid; w < Wn; w += kThreads)
-            pp[w] = (w == ((uint32_t)e_var >> 6)) ? (1ull << ((uint32_t)e_var & 63)) : 0ull;
-        }
-        __syncthreads();
-      } else {
-        // ---- determined outcome --------------------------------------------
-        if (tid == 0) d.loc_var0[nloc] = -1;
-        if (tid < RW) s_mask[tid] = xa[tid] & destab_mask(tid, n);
-        __syncthreads();
-        const uint32_t ns = list_rows(false);   // destabilizer rows i: the product takes stabilizer n+i
-        // g sums, column by column, of the ordered product into the scratch row.
-        uint32_t g = 0;
-        for (uint32_t q = tid; q < n; q += kThreads) {
-          const uint64_t* xq = d.X + (size_t)q * RW;
-          const uint64_t* zq = d.Z + (size_t)q * RW;
-          uint32_t xs = 0, zs = 0;
-          for (uint32_t j = 0; j < ns; ++j) {
-            const uint32_t r = n + s_rows[j];
-            const uint32_t xi = bit_of(xq, r), zi = bit_of(zq, r);
-            uint64_t plus, minus;
-            g_masks(xi ? 1ull : 0ull, zi ? 1ull : 0ull, xs, zs, plus, minus);
-            g += (uint32_t)plus - (uint32_t)minus;   // mod 2^32, reduced mod 4 below
-            xs ^= xi;
-            zs ^= zi;
+          uint64_t* xq = X + (size_t)q * RW;
+          uint64_t* zq = Z + (size_t)q * RW;
+          const uint64_t bx = xq[pw] & pb, bz = zq[pw] & pb;
+          const uint64_t lx = bx ? ~0ull : 0ull, lz = bz ? ~0ull : 0ull;
+          for (uint32_t w = 0; w < RW; ++w) {
+            const uint64_t m = s_mask[w];
+            xq[w] ^= m & lx;
+            zq[w] ^= m & lz;
           }
-        }
-        // Constant: the selected stabilizers' constants and the g correction.
-        uint32_t cpar = 0;
-        for (uint32_t j = tid; j < ns; j += kThreads) cpar ^= bit_of(s_C, n + s_rows[j]);
-        if (tid == 0) {
-          s_u32[2] = 0;
-          s_u32[3] = 0;
-        }
-        __syncthreads();
-        if (g & 3u) atomicAdd(&s_u32[2], g & 3u);
-        if (cpar) atomicXor(&s_u32[3], 1u);
-        // Symbols: E = XOR of the selected stabilizers' P rows.
-        for (uint32_t w = tid; w < Wt; w += kThreads) {
-          uint64_t e = 0;
-          for (uint32_t j = 0; j < ns; ++j) e ^= d.P[(size_t)s_rows[j] * W + w];
-          d.E[w] = e;
+          const uint32_t dr = p - n, dw = dr >> 6;
+          const uint64_t db = 1ull << (dr & 63);
+          xq[dw] = (xq[dw] & ~db) | (bx ? db : 0ull);
+          zq[dw] = (zq[dw] & ~db) | (bz ? db : 0ull);
+          xq[pw] &= ~pb;
+          zq[pw] = (zq[pw] & ~pb) | (q == a ? pb : 0ull);
         }
         __syncthreads();
-        e_c = uni(s_u32[3]) ^ (((uni(s_u32[2]) & 3u) == 2u) ? 1u : 0u);
-      }
-
-      // Record the outcome (M, MR).
-      if (op != D_R) {
-        if (e_var >= 0) {
+        if (op != D_R) {
           if (tid == 0) {
             d.rec_var[nrec] = e_var;
             d.rec_c[nrec] = 0;
             d.rec_off[nrec] = 0;
             d.rec_len[nrec] = 0;
           }
-        } else {
-          // Sorted list of E's set bits: per-thread word ranges, a block scan.
-          const uint32_t per = (Wt + kThreads - 1) / kThreads;
-          const uint32_t w0 = tid * per, w1 = min(Wt, w0 + per);
-          uint32_t mine = 0;
-          for (uint32_t w = w0; w < w1; ++w) mine += (uint32_t)__builtin_popcountll(d.E[w]);
-          // Exclusive scan of the counts: within each wave by shuffles, then
-          // over the waves' totals.
-          const uint32_t lane = tid & 63u, wave = tid >> 6;
-          uint32_t incl = mine;
-          for (uint32_t off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
+          ++nrec;
+        }
+        // Reset (R, MR): X^e on qubit a, e the fresh variable.
+        if (op != D_M) add_var(a, 1, 0, (uint32_t)e_var);
+      } else {
+        // ---- determined outcome ----------------------------------------------
+        // The product of the stabilizers n+i for the destabilizers i with
+        // x_a = 1, in order: its g sums column by column (thread = column),
+        // its constant, and its symbols E (each thread a range of words).
+        if (tid == 0) d.loc_var0[nloc] = -1;
+        rows_to_lds(s_rows, 0, [&](uint32_t w) { return ld(xa + w); }, false);
+        if (op != D_M) rows_to_lds(s_rows2, 1, [&](uint32_t w) { return ld(Z + (size_t)a * RW + w); }, true);
+        __syncthreads();
+        const uint32_t ns = uni(s_cnt[0]);
+        uint32_t g = 0, cpar = 0;
+        if (tid < n) {
+          const uint64_t* xq = X + (size_t)tid * RW;
+          const uint64_t* zq = Z + (size_t)tid * RW;
+          uint32_t xs = 0, zs = 0;
+          for (uint32_t j = 0; j < ns; ++j) {
+            const uint32_t r = n + s_rows[j];
+            const uint32_t xi = bit_of(xq, r), zi = bit_of(zq, r);
+            uint64_t plus, minus;
+            g_masks(xi, zi, xs, zs, plus, minus);
+            g += (uint32_t)plus - (uint32_t)minus;   // mod 2^32, reduced mod 4 below
+            xs ^= xi;
+            zs ^= zi;
           }
-          if (lane == 63) s_scan[wave] = incl;
-          __syncthreads();
-          uint32_t before = 0, total = 0;
-          for (uint32_t k = 0; k < kThreads / 64; ++k) {
-            const uint32_t t = s_scan[k];
-            before += k < wave ? t : 0u;
-            total += t;
+        }
+        for (uint32_t j = 0; j < ns; ++j) cpar ^= bit_of(s_C, n + s_rows[j]);
+        const uint32_t per = (Wt + kThreads - 1) / kThreads;
+        const uint32_t w0 = min(Wt, tid * per), w1 = min(Wt, w0 + per);
+        // This thread's words of E: the first two stay in registers, any
+        // further ones (more than 2^17 variables) go to Ecur; only this
+        // thread reads them back.
+        uint64_t e0 = 0, e1 = 0;
+        auto e_word = [&](uint32_t w) { return w == w0 ? e0 : w == w0 + 1 ? e1 : Ecur[w]; };
+        uint32_t mine = 0;
+        for (uint32_t w = w0; w < w1; ++w) {
+          uint64_t e = 0;
+          uint32_t j = 0;
+          for (; j + 4 <= ns; j += 4) {   // four independent loads in flight
+            const uint64_t v0 = d.P[(size_t)s_rows[j] * W + w], v1 = d.P[(size_t)s_rows[j + 1] * W + w];
+            const uint64_t v2 = d.P[(size_t)s_rows[j + 2] * W + w], v3 = d.P[(size_t)s_rows[j + 3] * W + w];
+            e ^= v0 ^ v1 ^ v2 ^ v3;
           }
-          total = uni(total);
-          const uint32_t fits = (uint64_t)listu + total <= d.list_cap;
+          for (; j < ns; ++j) e ^= d.P[(size_t)s_rows[j] * W + w];
+          if (w == w0) e0 = e;
+          else if (w == w0 + 1) e1 = e;
+          else Ecur[w] = e;
+          mine += (uint32_t)__builtin_popcountll(e);
+        }
+        const uint64_t g0 = __ballot(g & 1u), g1 = __ballot(g & 2u);
+        if (lane == 0) s_red[wave] = (uint32_t)__builtin_popcountll(g0) + 2u * (uint32_t)__builtin_popcountll(g1);
+        // Positions of the outcome's index list: a scan of the counts,
+        // within each wave by shuffles, then over the waves' totals.
+        uint32_t incl = mine;
+        for (uint32_t off = 1; off < 64; off <<= 1) {
+          const uint32_t y = __shfl_up(incl, off, 64);
+          if (lane >= off) incl += y;
+        }
+        if (lane == 63) s_scan[wave] = incl;
+        __syncthreads();
+        uint32_t G = 0, before = 0, total = 0;
+        for (uint32_t i = 0; i < kThreads / 64; ++i) {
+          G += s_red[i];
+          const uint32_t t = s_scan[i];
+          before += i < wave ? t : 0u;
+          total += t;
+        }
+        e_c = cpar ^ ((G & 3u) == 2u ? 1u : 0u);
+        total = uni(total);
+        if (op != D_R) {
+          // The ascending list of E's set bits (each thread its own words).
+          const bool fits = (uint64_t)listu + total <= d.list_cap;
           if (fits) {
             uint32_t pos = listu + before + incl - mine;
             for (uint32_t w = w0; w < w1; ++w) {
-              uint64_t e = d.E[w];
+              uint64_t e = e_word(w);
               while (e) {
                 d.list[pos++] = w * 64 + (uint32_t)__builtin_ctzll(e);
                 e &= e - 1;
@@ -507,12 +552,32 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
             d.rec_len[nrec] = fits ? total : 0u;
           }
           if (fits) listu += total;
+          ++nrec;
+        }
+        // Reset (R, MR): X^e on qubit a adds e to the stabilizer rows with z_a.
+        if (op != D_M) {
+          const uint32_t nr = s_cnt[1];
+          for (uint32_t w = w0; w < w1; ++w) {
+            const uint64_t e = e_word(w);
+            if (!e) continue;
+            uint32_t j = 0;
+            for (; j + 4 <= nr; j += 4) {   // four independent read-modify-writes in flight
+              uint64_t* p0 = d.P + (size_t)(s_rows2[j] - n) * W + w;
+              uint64_t* p1 = d.P + (size_t)(s_rows2[j + 1] - n) * W + w;
+              uint64_t* p2 = d.P + (size_t)(s_rows2[j + 2] - n) * W + w;
+              uint64_t* p3 = d.P + (size_t)(s_rows2[j + 3] - n) * W + w;
+              const uint64_t v0 = *p0, v1 = *p1, v2 = *p2, v3 = *p3;
+              *p0 = v0 ^ e;
+              *p1 = v1 ^ e;
+              *p2 = v2 ^ e;
+              *p3 = v3 ^ e;
+            }
+            for (; j < nr; ++j) d.P[(size_t)(s_rows2[j] - n) * W + w] ^= e;
+          }
+          if (e_c && tid < RW) s_C[tid] ^= Z[(size_t)a * RW + tid] & stab_mask(tid, n);
           __syncthreads();
         }
-        ++nrec;
       }
-      // Reset (R, MR): X^e on qubit a.
-      if (op != D_M) add_expr(a, 1, 0, e_var, e_c, Wt);
       ++nloc;
     }
   }
@@ -635,7 +700,7 @@ InitLayout layout(const sp_circuit& c, const DevProgram& P, size_t list_min, siz
   L.X = take(8ull * n * L.RW);
   L.Z = take(8ull * n * L.RW);
   L.P = take(8ull * n * L.W);
-  L.E = take(8ull * L.W);
+  L.E = take(16ull * L.W);
   L.loc = take(4ull * P.n_locs);
   L.rec_var = take(4ull * P.n_rec);
   L.rec_off = take(4ull * P.n_rec);
@@ -720,7 +785,19 @@ int sp_symbolize_device(const sp_circuit* circuit, int outputs, void* d_work, si
     d.list = (uint32_t*)(base + L.list);
     d.list_cap = L.list_cap;
     d.status = (uint32_t*)(base + L.status);
-    hipLaunchKernelGGL(init_kernel, dim3(1), dim3(kThreads), 0, s, d);
+    // The tableau goes to LDS when it fits beside the kernel's own arrays.
+    int dev = 0, lds_max = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t tab_bytes = 16ull * c.n_qubits * L.RW;
+    if (tab_bytes + kStaticLds <= (size_t)lds_max) {
+      if (tab_bytes > 64 * 1024)
+        HIP_TRY(hipFuncSetAttribute((const void*)init_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)tab_bytes));
+      hipLaunchKernelGGL(init_kernel<true>, dim3(1), dim3(kThreads), tab_bytes, s, d);
+    } else {
+      hipLaunchKernelGGL(init_kernel<false>, dim3(1), dim3(kThreads), 0, s, d);
+    }
     HIP_TRY(hipGetLastError());
 
     uint32_t status[6];
