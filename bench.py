@@ -39,8 +39,8 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
-    ap.add_argument("--legs", default="rep,d15,outputs,fig3,mix,small,serving",
-                    help="comma list of the other workloads to run (rep, d15, outputs, fig3, mix, small, serving)")
+    ap.add_argument("--legs", default="rep,d15,outputs,init,fig3,mix,small,serving",
+                    help="comma list of the other workloads to run (rep, d15, outputs, init, fig3, mix, small, serving)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -166,12 +166,14 @@ def main():
     legs = set() if args.no_extra else {x.strip() for x in args.legs.split(",") if x.strip()}
     if args.no_serving:
         legs.discard("serving")
-    unknown = legs - {"rep", "d15", "outputs", "fig3", "mix", "small", "serving"}
+    unknown = legs - {"rep", "d15", "outputs", "init", "fig3", "mix", "small", "serving"}
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
         sys.exit(2)
     if legs:
         rec["extra"] = extra_workloads(sp, torch, surface_memory, repetition_memory, legs)
+        if "init" in legs:
+            rec["extra"]["initialization_d15"] = init_leg(sp, torch, surface_memory)
         if "fig3" in legs:
             rec["extra"]["paper_fig3_layered_random"] = fig3_leg(sp, torch)
         if "mix" in legs:
@@ -268,12 +270,14 @@ def fig3_leg(sp, torch) -> dict:
     for n in (100, 200):
         for fig, kw in (("3a", {"cnot_pairs": 5}), ("3b", {}), ("3c", {"p_dep": "0.001"})):
             text = random_layered_circuit(n, seed=0, **kw).text()
+            circ = sp.Circuit(text)
             t0 = time.perf_counter()
-            m = sp.Model(text)
+            m = sp.Model(circ)
             t_init = time.perf_counter() - t0
+            t_dev = _device_init_s(sp, torch, circ, "measurements")
             dm = sp.DeviceModel(m)
             r = {"n_meas": m.n_meas, "n_vars": m.n_vars, "nnz": int(m.dims.nnz), "drawn": int(m.dims.n_drawn),
-                 "path": dm.path, "init_s": t_init}
+                 "path": dm.path, "init_s": t_init, "init_device_s": t_dev}
             for shots in (10_000, 1_000_000):
                 out = torch.empty((m.n_meas, (shots + 63) // 64), dtype=torch.int64, device="cuda")
                 lat = _event_ms(lambda: dm.sample(shots, seed=0, out=out), 10, torch)
@@ -281,6 +285,38 @@ def fig3_leg(sp, torch) -> dict:
                 r[f"ms_{shots}"] = ms
                 r[f"bits_per_s_{shots}"] = shots * m.n_meas / (ms * 1e-3)
             res[f"fig{fig}_n{n}"] = r
+    return res
+
+
+def _device_init_s(sp, torch, circ, outputs, reps=3) -> float:
+    """Median wall time of Initialization on the GPU (sp_symbolize_device,
+    synchronous: instruction upload, kernel, copy-back, host assembly)."""
+    sp.Model(circ, outputs=outputs, init="device")
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sp.Model(circ, outputs=outputs, init="device")
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2]
+
+
+def init_leg(sp, torch, surface_memory) -> dict:
+    """Initialization (the symbolic-phase tableau pass) of the d=15 surface
+    code, 15 rounds (449 qubits, about 10^5 fault variables), on the host
+    and on the GPU; the model is the same bit for bit."""
+    res = {}
+    for p, outputs in (("0.001", "measurements"), ("0.005", "detectors")):
+        circ = sp.Circuit(surface_memory(15, 15, p, detectors=outputs == "detectors").text())
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            m = sp.Model(circ, outputs=outputs)
+            ts.append(time.perf_counter() - t0)
+        host = sorted(ts)[1]
+        dev = _device_init_s(sp, torch, circ, outputs)
+        res[f"surface_d15_r15_p{p}_{outputs}"] = {"n_vars": m.n_vars, "nnz": int(m.dims.nnz), "host_s": host,
+                                                  "device_s": dev, "speedup": host / dev}
     return res
 
 
