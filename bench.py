@@ -91,7 +91,18 @@ def cpu_baseline(text: str, n_meas: int) -> dict:
     dt = time.perf_counter() - t0
     return {"value": shots * n_meas / dt, "unit": "bits/s", "cores": cores, "kind": "oracle",
             "sample": f"{shots} shots of the same circuit (seed 0), concrete A-G tableau per shot, "
-                      f"{cores} threads, {dt:.2f} s"}
+                      f"{cores} threads, {dt:.2f} s", "cpu": _cpu_model()}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():

@@ -8,8 +8,10 @@
  * into Initialization(C) -> m_1..m_nm and Sampling(n_smp, P_C, m_1..m_nm) ->
  * M_samples.  This library maps those to
  *
- *   sp_circuit_parse + sp_symbolize   Initialization, on the host
+ *   sp_circuit_parse (+ sp_circuit_add_noise for a noise model P_C)
+ *   sp_symbolize                      Initialization, on the host
  *                                     (Section 3.2.2: Init-C, Init-P, Init-M)
+ *   sp_symbolize_device               the same Initialization on the GPU
  *   sp_model_upload                   make (M, c, P_C) resident on the GPU
  *   sp_sample                         Sampling, on the GPU (Section 3.2.3, Eq. 4)
  *
@@ -128,6 +130,32 @@ enum {
  * Errors: SP_E_INVALID (null), SP_E_PARSE, SP_E_UNSUPPORTED. */
 int sp_circuit_parse(const char* text, size_t len, sp_circuit** out);
 void sp_circuit_free(sp_circuit* circuit);
+
+/* A noise model P_C (Algorithm 1's input) as circuit-level channels, each
+ * probability a decimal literal (thresholds are exact, as for channels in
+ * the text), NULL or "" for none:
+ *   p_1q     DEPOLARIZE1 after every target of H, S, X, Y, Z
+ *   p_2q     DEPOLARIZE2 after every pair of CX
+ *   p_meas   X_ERROR before every target of M and MR
+ *   p_reset  X_ERROR after every target of R and MR
+ *   p_idle   at every TICK, DEPOLARIZE1 on each qubit that no gate,
+ *            measurement, reset or controlled Pauli touched since the
+ *            previous TICK (qubits ascending); after the last TICK, none.
+ * Each channel follows (or, for p_meas, precedes) its instruction, so
+ * locations are numbered as if the channels were written in the text. */
+typedef struct {
+  const char* p_1q;
+  const char* p_2q;
+  const char* p_meas;
+  const char* p_reset;
+  const char* p_idle;
+} sp_noise;
+
+/* A new circuit: `circuit` with the noise model's channels added (the
+ * channels already in the text stay).  *out is owned by the caller
+ * (sp_circuit_free).  Errors: SP_E_INVALID (null), SP_E_PARSE (a
+ * probability literal that is malformed or above 1), SP_E_LIMIT. */
+int sp_circuit_add_noise(const sp_circuit* circuit, const sp_noise* noise, sp_circuit** out);
 
 /* Counts of a parsed circuit (any pointer may be NULL): qubits, recorded
  * measurements, detectors, observables (1 + the largest index used). */

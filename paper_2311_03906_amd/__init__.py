@@ -60,10 +60,12 @@ def _stream_handle(stream) -> int:
 class Circuit:
     """Parsed circuit (sp_circuit_parse)."""
 
-    def __init__(self, text: str):
-        b = text.encode()
-        h = ctypes.c_void_p()
-        check(lib().sp_circuit_parse(b, len(b), ctypes.byref(h)))
+    def __init__(self, text: str | None = None, _handle=None):
+        h = _handle
+        if h is None:
+            b = text.encode()
+            h = ctypes.c_void_p()
+            check(lib().sp_circuit_parse(b, len(b), ctypes.byref(h)))
         self._h = h
         v = [ctypes.c_uint32() for _ in range(4)]
         check(lib().sp_circuit_counts(h, *[ctypes.byref(x) for x in v]))
@@ -72,6 +74,15 @@ class Circuit:
     @property
     def handle(self):
         return self._h
+
+    def with_noise(self, p_1q=None, p_2q=None, p_meas=None, p_reset=None, p_idle=None) -> "Circuit":
+        """A new circuit with a circuit-level noise model added
+        (sp_circuit_add_noise); each probability is a decimal string or None."""
+        enc = lambda p: None if p is None else str(p).encode()
+        nz = _capi.sp_noise(enc(p_1q), enc(p_2q), enc(p_meas), enc(p_reset), enc(p_idle))
+        h = ctypes.c_void_p()
+        check(lib().sp_circuit_add_noise(self._h, ctypes.byref(nz), ctypes.byref(h)))
+        return Circuit(_handle=h)
 
     def __del__(self, _rel=_release):
         _rel(self, "sp_circuit_free")

@@ -22,7 +22,7 @@ SP_OUT_MEASUREMENTS, SP_OUT_DETECTORS = 0, 1
 
 #: every function the header declares (checked by the tests)
 EXPORTS = (
-    "sp_circuit_parse", "sp_circuit_free", "sp_circuit_counts", "sp_symbolize", "sp_symbolize_outputs",
+    "sp_circuit_parse", "sp_circuit_free", "sp_circuit_add_noise", "sp_circuit_counts", "sp_symbolize", "sp_symbolize_outputs",
     "sp_symbolize_device_work_bytes", "sp_symbolize_device", "sp_model_free", "sp_model_dims",
     "sp_model_expected_work",
     "sp_model_export_dense", "sp_model_export_csc", "sp_model_export_vars", "sp_model_device_bytes",
@@ -32,6 +32,11 @@ EXPORTS = (
     "sp_server_work_bytes", "sp_server_create", "sp_server_submit", "sp_server_status", "sp_server_wait",
     "sp_server_release", "sp_server_stats", "sp_server_destroy", "sp_last_error",
 )
+
+
+class sp_noise(ctypes.Structure):
+    _fields_ = [("p_1q", ctypes.c_char_p), ("p_2q", ctypes.c_char_p), ("p_meas", ctypes.c_char_p),
+                ("p_reset", ctypes.c_char_p), ("p_idle", ctypes.c_char_p)]
 
 
 class sp_dims(ctypes.Structure):
@@ -87,6 +92,7 @@ def lib():
     sig = {
         "sp_circuit_parse": ([ctypes.c_char_p, sz, P(vp)], ctypes.c_int),
         "sp_circuit_free": ([vp], None),
+        "sp_circuit_add_noise": ([vp, P(sp_noise), P(vp)], ctypes.c_int),
         "sp_symbolize": ([vp, P(vp)], ctypes.c_int),
         "sp_symbolize_outputs": ([vp, ctypes.c_int, P(vp)], ctypes.c_int),
         "sp_symbolize_device_work_bytes": ([vp, P(sz)], ctypes.c_int),

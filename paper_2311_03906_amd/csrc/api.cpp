@@ -41,6 +41,16 @@ int sp_circuit_parse(const char* text, size_t len, sp_circuit** out) {
 
 void sp_circuit_free(sp_circuit* c) { delete c; }
 
+int sp_circuit_add_noise(const sp_circuit* c, const sp_noise* noise, sp_circuit** out) {
+  SP_GUARD_BEGIN
+  if (!out) return set_error(SP_E_INVALID, "out is null");
+  *out = nullptr;
+  if (!c || !noise) return set_error(SP_E_INVALID, "null argument");
+  *out = sp::add_noise(*c, *noise);
+  return SP_OK;
+  SP_GUARD_END
+}
+
 int sp_circuit_counts(const sp_circuit* c, uint32_t* n_qubits, uint32_t* n_meas, uint32_t* n_detectors,
                       uint32_t* n_observables) {
   if (!c) return set_error(SP_E_INVALID, "null circuit");

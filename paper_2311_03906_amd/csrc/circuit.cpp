@@ -302,4 +302,99 @@ sp_circuit* parse_circuit(const char* text, size_t len) {
   }
 }
 
+// Circuit-level noise added to a circuit (the noise model P_C): a channel
+// after every one-qubit gate (DEPOLARIZE1) and every CNOT pair
+// (DEPOLARIZE2), X_ERROR before every M/MR and after every R/MR, and, at
+// each TICK, DEPOLARIZE1 on every qubit that no gate, measurement, reset or
+// controlled Pauli of the layer since the previous TICK touched.  A null or
+// empty probability adds nothing.
+sp_circuit* add_noise(const sp_circuit& in, const sp_noise& spec) {
+  auto* c = new sp_circuit(in);
+  try {
+    std::map<std::pair<uint32_t, std::string>, int32_t> chan_index;
+    for (size_t k = 1; k < c->channels.size(); ++k)
+      chan_index.emplace(std::make_pair(c->channels[k].kind, c->channels[k].ptext), (int32_t)k);
+    auto chan = [&](uint32_t kind, uint32_t m, const std::string& p) {
+      auto key = std::make_pair(kind, p);
+      auto it = chan_index.find(key);
+      if (it != chan_index.end()) return it->second;
+      c->channels.push_back(make_channel(kind, m, p));
+      return chan_index.emplace(key, (int32_t)c->channels.size() - 1).first->second;
+    };
+    struct Chan {
+      bool on;
+      OpKind kind;
+      int32_t idx;
+    };
+    auto make = [&](const char* p, OpKind kind, uint32_t ck, uint32_t m) {
+      Chan r{p && *p, kind, -1};
+      if (r.on) r.idx = chan(ck, m, p);
+      return r;
+    };
+    const Chan g1 = make(spec.p_1q, OpKind::DEP1, CH_DEP1, 3), g2 = make(spec.p_2q, OpKind::DEP2, CH_DEP2, 15);
+    const Chan meas = make(spec.p_meas, OpKind::XERR, CH_XERR, 1), reset = make(spec.p_reset, OpKind::XERR, CH_XERR, 1);
+    const Chan idle = make(spec.p_idle, OpKind::DEP1, CH_DEP1, 3);
+
+    std::vector<Op> ops;
+    uint64_t n_locs = 0;
+    std::vector<uint8_t> touched(c->n_qubits, 0);
+    auto noise = [&](const Chan& ch, const std::vector<uint32_t>& targets) {
+      if (!ch.on || targets.empty()) return;
+      Op op;
+      op.kind = ch.kind;
+      op.chan = ch.idx;
+      op.targets = targets;
+      n_locs += ch.kind == OpKind::DEP2 ? targets.size() / 2 : targets.size();
+      ops.push_back(std::move(op));
+    };
+    for (const Op& op : in.ops) {
+      switch (op.kind) {
+        case OpKind::H: case OpKind::S: case OpKind::X: case OpKind::Y: case OpKind::Z: case OpKind::CX:
+          for (uint32_t q : op.targets) touched[q] = 1;
+          ops.push_back(op);
+          noise(op.kind == OpKind::CX ? g2 : g1, op.targets);
+          break;
+        case OpKind::M: case OpKind::MR: case OpKind::R:
+          for (uint32_t q : op.targets) touched[q] = 1;
+          if (op.kind != OpKind::R) noise(meas, op.targets);
+          ops.push_back(op);
+          n_locs += op.targets.size();
+          if (op.kind != OpKind::M) noise(reset, op.targets);
+          break;
+        case OpKind::FX: case OpKind::FY: case OpKind::FZ:
+          for (size_t k = 1; k < op.targets.size(); k += 2) touched[op.targets[k]] = 1;
+          ops.push_back(op);
+          break;
+        case OpKind::TICK: {
+          std::vector<uint32_t> idle_q;
+          for (uint32_t q = 0; q < c->n_qubits; ++q)
+            if (!touched[q]) idle_q.push_back(q);
+          noise(idle, idle_q);
+          std::fill(touched.begin(), touched.end(), 0);
+          ops.push_back(op);
+          break;
+        }
+        case OpKind::XERR: case OpKind::YERR: case OpKind::ZERR: case OpKind::DEP1:
+          n_locs += op.targets.size();
+          ops.push_back(op);
+          break;
+        case OpKind::DEP2:
+          n_locs += op.targets.size() / 2;
+          ops.push_back(op);
+          break;
+        default:
+          ops.push_back(op);
+          break;
+      }
+      if (n_locs >= (1ull << 32)) throw Error(SP_E_LIMIT, "more than 2^32 locations");
+    }
+    c->ops.swap(ops);
+    c->n_locs = (uint32_t)n_locs;
+    return c;
+  } catch (...) {
+    delete c;
+    throw;
+  }
+}
+
 }  // namespace sp

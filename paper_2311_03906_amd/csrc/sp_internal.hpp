@@ -101,6 +101,9 @@ struct Expr {
 };
 
 sp_circuit* parse_circuit(const char* text, size_t len);
+// A copy of the circuit with the channels of a circuit-level noise model
+// added (see sp_circuit_add_noise).
+sp_circuit* add_noise(const sp_circuit& c, const sp_noise& noise);
 sp_model* symbolize(const sp_circuit& c, int outputs);
 // The model from one Initialization pass: loc_var0 per location (-1 for a
 // determined measurement), the variable count, and the expression of every

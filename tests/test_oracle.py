@@ -15,6 +15,7 @@ import pytest
 from hypothesis import given, settings, strategies as st
 
 import oracle
+import piling_up
 import statevector
 from golden_io import example, rows
 from workloads import random_clifford_circuit, repetition_memory, surface_memory
@@ -358,3 +359,23 @@ def test_sample_is_shot_addressable():
 def test_parse_rejects(text):
     with pytest.raises(oracle.OracleError):
         oracle.Circuit(text)
+
+
+@pytest.mark.parametrize("name,circ,outputs", [
+    ("surf3_meas", surface_memory(3, 3, "0.02", detectors=True), "measurements"),
+    ("surf3_det", surface_memory(3, 3, "0.02", detectors=True), "detectors"),
+    ("rep5_det", repetition_memory(5, 5, "0.03", detectors=True), "detectors"),
+    ("random_all_channels", random_clifford_circuit(21, 6, 90, feedback=True, detectors=True), "measurements"),
+])
+def test_output_marginals_match_piling_up_lemma(name, circ, outputs):
+    """Per-row frequencies of the oracle's sampled outputs against the
+    piling-up closed form (independent locations, exact code
+    probabilities, rows built by probing): within 5 sigma, and rows of
+    probability 0 or 1 constant."""
+    text = circ.text()
+    p = piling_up.expected_marginals(text, outputs)
+    assert ((p > 0.01) & (p < 0.99)).sum() >= 5   # the check has teeth
+    oc = oracle.Circuit(text, outputs=outputs)
+    shots = 40_000
+    counts = piling_up.ones_per_row(oc.sample(seed=5, first_shot=0, shots=shots), shots)
+    piling_up.check_marginals(counts, shots, p)

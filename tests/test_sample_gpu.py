@@ -15,6 +15,7 @@ import pytest
 import torch
 
 import oracle
+import piling_up
 import paper_2311_03906_amd as sp
 from workloads import random_clifford_circuit, random_layered_circuit, repetition_memory, surface_memory
 
@@ -329,3 +330,63 @@ def test_launch_shape_rejects_oversized_slabs():
         dm.launch = (8, 8)       # words_per_group must be 1, 2 or 4
     with pytest.raises(sp.SymphaseError):
         dm.launch = (0, 1)
+
+
+@pytest.mark.parametrize("outputs", ["measurements", "detectors"])
+def test_output_marginals_match_piling_up_lemma(outputs):
+    """Surface d=5, 5 rounds, p = 5e-3, 2^20 shots on the GPU: every output
+    row's frequency of ones is within 5 sigma of the piling-up closed form
+    computed from the oracle (exact code probabilities, rows probed one code
+    bit at a time)."""
+    text = surface_memory(5, 5, "0.005", detectors=True).text()
+    _say(f"piling-up marginals surface d5 {outputs} 2^20 shots")
+    p = piling_up.expected_marginals(text, outputs)
+    m, dm, oc = _models(text, "auto", outputs)
+    shots = 1 << 20
+    counts = piling_up.ones_per_row(_gpu(dm, shots, seed=17), shots)
+    piling_up.check_marginals(counts, shots, p)
+
+
+def test_noise_model_circuit_full():
+    """A noiseless surface code (d=5, 5 rounds) with the noise model added
+    through the C ABI (distinct probabilities per channel class), sampled on
+    the GPU: every word equals the oracle's samples of the same circuit with
+    the channels written out in the text."""
+    noisy = surface_memory(5, 5, "0.001", detectors=True).text()
+    clean = "\n".join(l for l in noisy.splitlines() if not l.startswith(("X_ERROR", "DEPOLARIZE"))) + "\n"
+    ps = {"p_1q": "0.002", "p_2q": "0.006", "p_meas": "0.01", "p_reset": "0.003", "p_idle": "0.0005"}
+    _say("noise model surface d5 20000 shots")
+    circ = sp.Circuit(clean).with_noise(**ps)
+    m = sp.Model(circ, outputs="detectors")
+    dm = sp.DeviceModel(m)
+    want_text = _written_noise(clean, ps, circ.n_qubits)
+    oc = oracle.Circuit(want_text, outputs="detectors")
+    got = _gpu(dm, 20_000, seed=2)
+    assert np.array_equal(got, oc.sample(seed=2, first_shot=0, shots=20_000))
+
+
+def _written_noise(text, ps, n_qubits):
+    """The noise model's placement written out as circuit text."""
+    out, touched = [], set()
+    for line in text.splitlines():
+        parts = line.split()
+        head, targets = parts[0], parts[1:]
+        if head == "TICK":
+            idle = [q for q in range(n_qubits) if q not in touched]
+            if idle:
+                out.append(f"DEPOLARIZE1({ps['p_idle']}) " + " ".join(map(str, idle)))
+            touched = set()
+            out.append(line)
+            continue
+        if head in ("H", "S", "CX", "M", "R", "MR"):
+            touched |= {int(q) for q in targets}
+        if head in ("M", "MR"):
+            out.append(f"X_ERROR({ps['p_meas']}) " + " ".join(targets))
+        out.append(line)
+        if head in ("H", "S"):
+            out.append(f"DEPOLARIZE1({ps['p_1q']}) " + " ".join(targets))
+        if head == "CX":
+            out.append(f"DEPOLARIZE2({ps['p_2q']}) " + " ".join(targets))
+        if head in ("R", "MR"):
+            out.append(f"X_ERROR({ps['p_reset']}) " + " ".join(targets))
+    return "\n".join(out) + "\n"

@@ -245,3 +245,106 @@ def test_empty_circuit():
     assert (m.dims.n_meas, m.dims.n_vars, m.dims.n_locs) == (0, 0, 0)
     m = sp.Model("TICK\n# only a comment\n")
     assert m.dims.n_meas == 0
+
+
+def _noise_by_rule(text, p1=None, p2=None, pm=None, pr=None, pi=None, n_qubits=None):
+    """The noise model's documented placement, written out on circuit text:
+    DEPOLARIZE1(p1) after 1-qubit gates, DEPOLARIZE2(p2) after CNOT pairs,
+    X_ERROR(pm) before M/MR, X_ERROR(pr) after R/MR, DEPOLARIZE1(pi) at each
+    TICK on the qubits the layer left untouched (ascending)."""
+    out, touched = [], set()
+    for line in text.splitlines():
+        parts = line.split()
+        if not parts:
+            continue
+        head, targets = parts[0], parts[1:]
+        qubits = [t for t in targets if not t.startswith("rec[")]
+        if head == "TICK":
+            idle = [q for q in range(n_qubits) if q not in touched]
+            if pi is not None and idle:
+                out.append(f"DEPOLARIZE1({pi}) " + " ".join(map(str, idle)))
+            touched = set()
+            out.append(line)
+            continue
+        if head in ("H", "S", "X", "Y", "Z", "CX", "CY", "CZ", "M", "R", "MR"):
+            touched |= {int(q) for q in qubits}
+        if head in ("M", "MR") and pm is not None:
+            out.append(f"X_ERROR({pm}) " + " ".join(targets))
+        out.append(line)
+        if head in ("H", "S", "X", "Y", "Z") and p1 is not None:
+            out.append(f"DEPOLARIZE1({p1}) " + " ".join(targets))
+        if head == "CX" and p2 is not None and not any(t.startswith("rec[") for t in targets):
+            out.append(f"DEPOLARIZE2({p2}) " + " ".join(targets))
+        if head in ("R", "MR") and pr is not None:
+            out.append(f"X_ERROR({pr}) " + " ".join(targets))
+    return "\n".join(out) + "\n"
+
+
+def _same_host_model(a, b):
+    for f in ("n_qubits", "n_meas", "n_locs", "n_vars", "n_random_meas", "n_drawn", "n_draw_blocks", "nnz"):
+        assert getattr(a.dims, f) == getattr(b.dims, f), f
+    for x, y in zip(a.export_vars(), b.export_vars()):
+        assert np.array_equal(x, y)
+    for x, y in zip(a.export_csc(), b.export_csc()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.export_dense()[1], b.export_dense()[1])
+
+
+@pytest.mark.parametrize("d,rounds,p", [(3, 3, "0.001"), (5, 5, "0.005")])
+def test_noise_model_reproduces_the_surface_generator(d, rounds, p):
+    """The surface-code generator writes its circuit-level noise by hand; the
+    noiseless circuit plus sp_circuit_add_noise at the same p gives the same
+    model (locations, variables, (M, c)), for both output kinds."""
+    noisy = surface_memory(d, rounds, p, detectors=True).text()
+    clean = "\n".join(l for l in noisy.splitlines() if not l.startswith(("X_ERROR", "DEPOLARIZE"))) + "\n"
+    c = sp.Circuit(clean).with_noise(p, p, p, p, p)
+    for outputs in ("measurements", "detectors"):
+        _same_host_model(sp.Model(c, outputs=outputs), sp.Model(noisy, outputs=outputs))
+
+
+@settings(max_examples=60, deadline=None)
+@given(seed=st.integers(0, 2 ** 31), n=st.integers(1, 6), n_ops=st.integers(1, 50),
+       which=st.lists(st.booleans(), min_size=5, max_size=5))
+def test_noise_model_matches_its_rule(seed, n, n_ops, which):
+    """Random circuits with TICK layers and feedback, each noise parameter
+    on or off with its own probability: the added channels are where the
+    rule puts them (same model as the rule written out as text), and M b + c
+    of the result equals the oracle on that text."""
+    rng = np.random.default_rng(seed)
+    body = random_clifford_circuit(seed, n, n_ops, feedback=True).text().splitlines()
+    lines = []
+    for ln in body:
+        if not ln.startswith(("X_ERROR", "Y_ERROR", "Z_ERROR", "DEPOLARIZE")):
+            lines.append(ln)
+        if rng.random() < 0.3:
+            lines.append("TICK")
+    text = "\n".join(lines) + "\n"
+    ps = [p if on else None for p, on in zip(("0.01", "0.02", "0.03", "0.04", "0.05"), which)]
+    circ = sp.Circuit(text)
+    want = _noise_by_rule(text, *ps, n_qubits=circ.n_qubits)
+    m = sp.Model(circ.with_noise(*ps))
+    _same_host_model(m, sp.Model(want))
+    oc = oracle.Circuit(want)
+    M, c = m.export_dense()
+    mv = m.export_vars()
+    kinds = oc.location_kinds()
+    for _ in range(2):
+        codes = np.array([rng.integers(0, 2 ** oracle.CODE_BITS[int(k)]) for k in kinds], dtype=np.uint8)
+        assert np.array_equal(_evaluate(M, c, _assignment(mv, codes)), oc.run_codes(codes)[0])
+
+
+def test_noise_model_errors():
+    import ctypes
+    L = sp.lib()
+    c = sp.Circuit("H 0\nM 0\n")
+    with pytest.raises(sp.SymphaseError) as e:
+        c.with_noise(p_1q="1.5")
+    assert e.value.code == sp._capi.SP_E_PARSE
+    with pytest.raises(sp.SymphaseError) as e:
+        c.with_noise(p_meas="abc")
+    assert e.value.code == sp._capi.SP_E_PARSE
+    h = ctypes.c_void_p()
+    assert L.sp_circuit_add_noise(c.handle, None, ctypes.byref(h)) == sp._capi.SP_E_INVALID
+    assert h.value is None
+    # nothing requested: the same circuit
+    _same_host_model(sp.Model(c.with_noise()), sp.Model("H 0\nM 0\n"))
