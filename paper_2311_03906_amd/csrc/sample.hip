@@ -252,6 +252,14 @@ __device__ __forceinline__ void flush_events(const DevModel& m, uint64_t* slab, 
     uint64_t* sl = slab + (size_t)(info & 3u) * m.n_meas;
     const guint32_p p1 = (guint32_p)m.entries + hi;
     guint32_p p = (guint32_p)m.entries + lo;
+    for (; p + 8 <= p1; p += 8) {   // eight loads in flight
+      uint32_t e[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) e[i] = p[i];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (__builtin_amdgcn_ubfe(code, e[i], 1)) atomicXor((unsigned long long*)&row_of(sl, e[i]), (unsigned long long)bit);
+    }
     for (; p + 4 <= p1; p += 4) {   // four loads in flight
       const uint32_t e0 = p[0], e1 = p[1], e2 = p[2], e3 = p[3];
       if (__builtin_amdgcn_ubfe(code, e0, 1)) atomicXor((unsigned long long*)&row_of(sl, e0), (unsigned long long)bit);
