@@ -229,12 +229,28 @@ int sp_model_device_bytes(const sp_model* model, int path, size_t* bytes);
  * caller keeps d_buf alive and unmodified until sp_dmodel_free.  The copy is
  * asynchronous on `stream`; the host model may be freed after the call
  * returns (staging is internal and synchronous with respect to the host).
- * Errors: SP_E_INVALID, SP_E_LIMIT (n_meas too large for one LDS slab),
- * SP_E_DEVICE. */
+ *
+ * Row tiles: the sampling kernel keeps a 64-shot word's output rows in one
+ * LDS slab (19,456 rows at most on gfx950 with room for 16 waves' event
+ * queues).  A model with more rows is stored as row tiles of 8,192 rows;
+ * each tile holds only the locations that reach its rows, and sp_sample
+ * launches once per tile.  The draws are keyed by location, so the output
+ * is the same bit for bit whatever the tiling.
+ * Errors: SP_E_INVALID, SP_E_LIMIT (a tile does not fit the device's LDS,
+ * more than 2^27 rows), SP_E_DEVICE. */
 int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_bytes, void* stream,
                     sp_dmodel** out);
+/* The same with an explicit tile size: tile_rows = 0 chooses as above,
+ * otherwise tiles of tile_rows rows (a multiple of 64, at most 19,456).
+ * Errors as above, and SP_E_INVALID for another tile_rows. */
+int sp_model_device_bytes_tiled(const sp_model* model, int path, uint32_t tile_rows, size_t* bytes);
+int sp_model_upload_tiled(const sp_model* model, int path, uint32_t tile_rows, void* d_buf, size_t buf_bytes,
+                          void* stream, sp_dmodel** out);
 void sp_dmodel_free(sp_dmodel* dmodel);
 int sp_dmodel_dims(const sp_dmodel* dmodel, sp_dims* out);
+/* Row tiles of a device model and the rows of the largest (either pointer
+ * may be NULL).  Errors: SP_E_INVALID. */
+int sp_dmodel_tiles(const sp_dmodel* dmodel, uint32_t* n_tiles, uint32_t* rows_max);
 
 /* Algorithm 1, Sampling, for shots [first_shot, first_shot + shots): draws
  * the variables of every drawn location from the keyed Philox stream, packs
@@ -248,8 +264,8 @@ int sp_sample(const sp_dmodel* dmodel, uint64_t seed, uint64_t first_shot, uint6
 
 /* Launch shape of the sampling kernel: a workgroup of waves_per_group
  * wave64s (1..16) owns words_per_group (1, 2 or 4) consecutive 64-shot words,
- * each with its own LDS slab of n_meas uint64 rows (sparse path: plus a
- * 512-byte event queue per wave).  The output does not depend on the launch
+ * each with its own LDS slab of one row tile's uint64 rows (sparse path:
+ * plus a 512-byte event queue per wave).  The output does not depend on the launch
  * shape. */
 typedef struct {
   uint32_t waves_per_group;

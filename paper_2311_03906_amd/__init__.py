@@ -165,27 +165,29 @@ class Model:
         check(lib().sp_model_export_vars(self._h, vl.ctypes.data, vb.ctypes.data))
         return vl[: self.n_vars], vb[: self.n_vars]
 
-    def device_bytes(self, path: str = "auto") -> int:
+    def device_bytes(self, path: str = "auto", tile_rows: int = 0) -> int:
         n = ctypes.c_size_t()
-        check(lib().sp_model_device_bytes(self._h, _PATHS[path], ctypes.byref(n)))
+        check(lib().sp_model_device_bytes_tiled(self._h, _PATHS[path], tile_rows, ctypes.byref(n)))
         return n.value
 
 
 class DeviceModel:
     """Device-resident model (sp_model_upload) in a torch-owned buffer."""
 
-    def __init__(self, model: Model, path: str = "auto", device=None, stream=None):
+    def __init__(self, model: Model, path: str = "auto", device=None, stream=None, tile_rows: int = 0):
+        """tile_rows: 0 for the library's choice (one tile while the rows fit
+        one LDS slab), else row tiles of that many rows."""
         if not torch.cuda.is_available():
             raise SymphaseError(-5, "no GPU: the sampler runs only on the device")
         device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
-        nbytes = model.device_bytes(path)
+        nbytes = model.device_bytes(path, tile_rows)
         with torch.cuda.device(device):
             self.buffer = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
             base = self.buffer.data_ptr()
             off = (-base) % 256
             h = ctypes.c_void_p()
-            check(lib().sp_model_upload(model.handle, _PATHS[path], ctypes.c_void_p(base + off), nbytes,
-                                        ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))
+            check(lib().sp_model_upload_tiled(model.handle, _PATHS[path], tile_rows, ctypes.c_void_p(base + off),
+                                              nbytes, ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))
         self._h = h
         self.device = device
         self.n_meas = model.n_meas
@@ -194,6 +196,9 @@ class DeviceModel:
         d = sp_dims()
         check(lib().sp_dmodel_dims(h, ctypes.byref(d)))
         self.dims = d
+        nt, rm = ctypes.c_uint32(), ctypes.c_uint32()
+        check(lib().sp_dmodel_tiles(h, ctypes.byref(nt), ctypes.byref(rm)))
+        self.n_tiles, self.tile_rows_max = nt.value, rm.value
 
     @property
     def handle(self):

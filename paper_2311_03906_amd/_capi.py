@@ -26,7 +26,8 @@ EXPORTS = (
     "sp_symbolize_device_work_bytes", "sp_symbolize_device", "sp_model_free", "sp_model_dims",
     "sp_model_expected_work",
     "sp_model_export_dense", "sp_model_export_csc", "sp_model_export_vars", "sp_model_device_bytes",
-    "sp_model_upload", "sp_dmodel_free", "sp_dmodel_dims", "sp_dmodel_get_launch", "sp_dmodel_set_launch",
+    "sp_model_upload", "sp_model_device_bytes_tiled", "sp_model_upload_tiled", "sp_dmodel_free", "sp_dmodel_dims",
+    "sp_dmodel_tiles", "sp_dmodel_get_launch", "sp_dmodel_set_launch",
     "sp_sample", "sp_batch_work_bytes", "sp_batch_create", "sp_batch_info", "sp_batch_launch", "sp_batch_free",
     "sp_graph_capture_batch", "sp_graph_capture_plain", "sp_graph_launch", "sp_graph_free",
     "sp_server_work_bytes", "sp_server_create", "sp_server_submit", "sp_server_status", "sp_server_wait",
@@ -107,6 +108,9 @@ def lib():
         "sp_model_export_vars": ([vp, vp, vp], ctypes.c_int),
         "sp_model_device_bytes": ([vp, ctypes.c_int, P(sz)], ctypes.c_int),
         "sp_model_upload": ([vp, ctypes.c_int, vp, sz, vp, P(vp)], ctypes.c_int),
+        "sp_model_device_bytes_tiled": ([vp, ctypes.c_int, u32, P(sz)], ctypes.c_int),
+        "sp_model_upload_tiled": ([vp, ctypes.c_int, u32, vp, sz, vp, P(vp)], ctypes.c_int),
+        "sp_dmodel_tiles": ([vp, P(u32), P(u32)], ctypes.c_int),
         "sp_dmodel_free": ([vp], None),
         "sp_dmodel_dims": ([vp, P(sp_dims)], ctypes.c_int),
         "sp_dmodel_get_launch": ([vp, P(sp_launch)], ctypes.c_int),

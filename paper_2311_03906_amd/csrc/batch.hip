@@ -87,13 +87,13 @@ int make_plan(const sp_batch_item* items, size_t n, const sp_launch* launch, int
     if (!it.model) return set_error(SP_E_INVALID, at + "null model");
     if (it.model->device != dev) return set_error(SP_E_INVALID, at + "model on another device");
     lds_max = it.model->lds_max;
-    if (it.shots == 0 || it.model->m.n_meas == 0) continue;
+    if (it.shots == 0 || it.model->n_meas == 0) continue;
     if (!it.d_out || ((uintptr_t)it.d_out & 7u)) return set_error(SP_E_INVALID, at + "bad output pointer");
     const uint64_t words = (it.shots + 63) / 64;
     if (it.ld_words < words) return set_error(SP_E_INVALID, at + "ld_words < words");
     if (words > 0x7FFFFFFFull) return set_error(SP_E_LIMIT, at + "too many shots");
     if (it.first_shot + it.shots < it.first_shot) return set_error(SP_E_INVALID, at + "shot range overflows");
-    n_meas_max = std::max(n_meas_max, it.model->m.n_meas);
+    n_meas_max = std::max(n_meas_max, it.model->rows_max);
     live.push_back(i);
   }
   if (launch) {
@@ -111,7 +111,7 @@ int make_plan(const sp_batch_item* items, size_t n, const sp_launch* launch, int
     return set_error(SP_E_LIMIT, "the largest model's slabs exceed the LDS of one workgroup");
   // Heavier groups first: with either schedule the light ones fill the tail.
   std::stable_sort(live.begin(), live.end(), [&](size_t x, size_t y) {
-    return items[x].model->m.nb > items[y].model->m.nb;
+    return items[x].model->nb > items[y].model->nb;
   });
   for (int p : {SP_PATH_SPARSE, SP_PATH_DENSE}) {
     SubPlan S;
@@ -119,9 +119,10 @@ int make_plan(const sp_batch_item* items, size_t n, const sp_launch* launch, int
     for (size_t i : live) {
       const sp_batch_item& it = items[i];
       if (it.model->path != p) continue;
+      for (size_t t = 0; t < it.model->tiles.size(); ++t) {   // one job per row tile
       sp::BatchJob J{};
-      J.a.m = it.model->m;
-      J.a.out = it.d_out;
+      J.a.m = it.model->tiles[t];
+      J.a.out = it.d_out + (size_t)it.model->row0[t] * it.ld_words;
       J.a.ld = it.ld_words;
       J.a.first_shot = it.first_shot;
       J.a.shots = it.shots;
@@ -133,15 +134,16 @@ int make_plan(const sp_batch_item* items, size_t n, const sp_launch* launch, int
       J.group_base = (uint32_t)S.total_groups;
       S.total_groups += J.a.n_groups;
       if (S.total_groups >= 0x7FFFFFFFull) return set_error(SP_E_LIMIT, "more than 2^31 groups in one batch");
-      S.n_meas_max = std::max(S.n_meas_max, it.model->m.n_meas);
+      S.n_meas_max = std::max(S.n_meas_max, J.a.m.n_meas);
       const uint32_t j = (uint32_t)S.jobs.size();
       if (schedule == SP_SCHED_PERSISTENT) {
-        const uint32_t k = task_groups(it.model->m.nb);
+        const uint32_t k = task_groups(J.a.m.nb);
         for (uint32_t g = 0; g < J.a.n_groups; g += k) S.tasks.push_back({j, g, std::min(k, J.a.n_groups - g), 0});
       } else {
         S.group_job.insert(S.group_job.end(), J.a.n_groups, j);
       }
       S.jobs.push_back(J);
+      }
     }
     if (!S.jobs.empty()) P.sub[P.n_sub++] = std::move(S);
   }

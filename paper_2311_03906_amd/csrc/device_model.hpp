@@ -79,8 +79,17 @@ int batch_grid(const sp_launch& L, uint32_t n_meas_max, int path, uint32_t* grid
 
 }  // namespace sp
 
+// A device-resident model.  Its output rows are split into row tiles, one
+// unless the rows exceed one LDS slab (or a tile size was asked for): tile t
+// is a model of its own over rows [row0[t], row0[t] + tiles[t].n_meas),
+// drawing only the locations that reach those rows.  Draws are keyed by
+// location, so the tiles agree on every draw they share.
 struct sp_dmodel {
-  sp::DevModel m;
+  std::vector<sp::DevModel> tiles;
+  std::vector<uint32_t> row0;
+  uint32_t n_meas;       // rows over all tiles
+  uint32_t rows_max;     // rows of the largest tile
+  uint32_t nb;           // Philox blocks per shot over all tiles
   int path;
   int device;
   size_t lds_max;

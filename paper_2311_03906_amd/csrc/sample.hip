@@ -579,13 +579,28 @@ struct HostBlocks {
   std::vector<uint32_t> entries;
 };
 
-HostBlocks build_blocks(const sp_model& m) {
+// Output rows [r0, r1) only (a row tile): a location is kept when some row of
+// the range depends on it, and its entries name rows relative to r0.
+bool loc_reaches(const sp_model& m, uint32_t l, uint32_t r0, uint32_t r1) {
+  const uint32_t v0 = (uint32_t)m.loc_var0[l];
+  for (uint32_t b = 0; b < sp::loc_bits(m.loc_kind[l]); ++b) {
+    const uint32_t* lo = m.row_idx.data() + m.col_ptr[v0 + b];
+    const uint32_t* hi = m.row_idx.data() + m.col_ptr[v0 + b + 1];
+    const uint32_t* it = std::lower_bound(lo, hi, r0);   // rows ascend within a column
+    if (it != hi && *it < r1) return true;
+  }
+  return false;
+}
+
+HostBlocks build_blocks(const sp_model& m, uint32_t r0, uint32_t r1) {
   HostBlocks H;
   if (m.n_meas >= (1u << 27)) throw sp::Error(SP_E_LIMIT, "more than 2^27 measurements");
   if (m.n_locs >= (1u << 24)) throw sp::Error(SP_E_LIMIT, "more than 2^24 locations");
+  const bool whole = r0 == 0 && r1 >= m.n_meas;
   int64_t cur = -1;
   for (uint32_t l = 0; l < m.n_locs; ++l) {
     if (!sp::loc_drawn(m, l)) continue;   // never fires, or reaches no output row
+    if (!whole && !loc_reaches(m, l, r0, r1)) continue;
     const int32_t ch = m.loc_chan[l];
     const sp::Channel& c = m.channels[ch];
     const uint64_t Tm = c.T[c.m];
@@ -606,8 +621,10 @@ HostBlocks build_blocks(const sp_model& m) {
     w[s] = (var0 << 8) | (uint32_t)(ch + 1);
     w[4 + s] = (uint32_t)H.entries.size();
     for (uint32_t b = 0; b < sp::loc_bits(m.loc_kind[l]); ++b)
-      for (uint32_t i = m.col_ptr[var0 + b]; i < m.col_ptr[var0 + b + 1]; ++i)
-        H.entries.push_back((m.row_idx[i] << 5) | b);
+      for (uint32_t i = m.col_ptr[var0 + b]; i < m.col_ptr[var0 + b + 1]; ++i) {
+        const uint32_t k = m.row_idx[i];
+        if (k >= r0 && k < r1) H.entries.push_back(((k - r0) << 5) | b);
+      }
     if (H.entries.size() >= (1ull << 32)) throw sp::Error(SP_E_LIMIT, "more than 2^32 entries in M");
     for (uint32_t t = s + 1; t <= 4; ++t) w[4 + t] = (uint32_t)H.entries.size();
   }
@@ -623,24 +640,51 @@ int choose_path(const sp_model& m, int path) {
   return (avg * 4.0 > (double)m.n_meas) ? SP_PATH_DENSE : SP_PATH_SPARSE;
 }
 
-struct Layout {
-  size_t hot, cold, entries, chans, c_mask, dense, total;
-  uint32_t nb, nch, dense_words;
+// Rows of one LDS slab that leave room for the event queues of 16 waves
+// (160 KB of LDS per workgroup on gfx950): a model with more rows is split
+// into row tiles of at most kTileRowsAuto rows.
+constexpr uint32_t kSlabRowsMax = (160u * 1024u - 16u * sp::kQueueCap * 8u) / 8u;
+constexpr uint32_t kTileRowsAuto = 8192;
+
+struct TileLayout {
+  size_t hot, cold, entries, c_mask, dense;
+  uint32_t r0, rows, nb, dense_words;
 };
 
-Layout plan(const sp_model& m, int path, const HostBlocks& H) {
+struct Layout {
+  std::vector<TileLayout> tiles;
+  std::vector<HostBlocks> blocks;
+  size_t chans, total;
+  uint32_t nch;
+};
+
+// tile_rows: 0 picks one tile when the rows fit a slab, else tiles of
+// kTileRowsAuto rows; otherwise tiles of that many rows (a multiple of 64).
+Layout plan(const sp_model& m, int path, uint32_t tile_rows) {
   Layout L{};
-  L.nb = (uint32_t)(H.hot.size() / 8);
+  uint32_t per = tile_rows;
+  if (per == 0) per = m.n_meas <= kSlabRowsMax ? std::max<uint32_t>(m.n_meas, 1) : kTileRowsAuto;
   L.nch = (uint32_t)m.channels.size();
-  L.dense_words = (m.n_meas + 63) / 64;
   size_t off = 0;
-  L.hot = off;     off = align256(off + 32 * std::max<size_t>(L.nb, 1));
-  L.cold = off;    off = align256(off + 64 * std::max<size_t>(L.nb, 1));
-  L.entries = off; off = align256(off + 4 * std::max<size_t>(H.entries.size(), 1));
-  L.chans = off;   off = align256(off + 64 * (size_t)L.nch);
-  L.c_mask = off;  off = align256(off + 8 * std::max<size_t>(L.dense_words, 1));
-  L.dense = off;
-  if (path == SP_PATH_DENSE) off = align256(off + 8 * (size_t)m.n_vars * L.dense_words);
+  L.chans = off;
+  off = align256(off + 64 * (size_t)L.nch);
+  for (uint32_t r0 = 0; r0 < std::max<uint32_t>(m.n_meas, 1); r0 += per) {
+    const uint32_t r1 = std::min<uint32_t>(std::max<uint32_t>(m.n_meas, 1), r0 + per);
+    L.blocks.push_back(build_blocks(m, r0, r1));
+    const HostBlocks& H = L.blocks.back();
+    TileLayout T{};
+    T.r0 = r0;
+    T.rows = m.n_meas ? r1 - r0 : 0;
+    T.nb = (uint32_t)(H.hot.size() / 8);
+    T.dense_words = (T.rows + 63) / 64;
+    T.hot = off;     off = align256(off + 32 * std::max<size_t>(T.nb, 1));
+    T.cold = off;    off = align256(off + 64 * std::max<size_t>(T.nb, 1));
+    T.entries = off; off = align256(off + 4 * std::max<size_t>(H.entries.size(), 1));
+    T.c_mask = off;  off = align256(off + 8 * std::max<size_t>(T.dense_words, 1));
+    T.dense = off;
+    if (path == SP_PATH_DENSE) off = align256(off + 8 * (size_t)m.n_vars * T.dense_words);
+    L.tiles.push_back(T);
+  }
   L.total = off;
   return L;
 }
@@ -749,15 +793,21 @@ namespace {
 sp_launch default_launch(const sp_dmodel& dm) {
   sp_launch L;
   L.waves_per_group = 8;
-  L.words_per_group = (sp::lds_bytes(dm.m.n_meas, 2, 8, dm.path) * 3 <= dm.lds_max) ? 2 : 1;
+  L.words_per_group = (sp::lds_bytes(dm.rows_max, 2, 8, dm.path) * 3 <= dm.lds_max) ? 2 : 1;
   return L;
 }
 
 int validate_launch(const sp_dmodel& dm, const sp_launch& L) {
   if (L.waves_per_group < 1 || L.waves_per_group > 16) return set_error(SP_E_INVALID, "waves_per_group must be 1..16");
   if (!kernel_for(dm.path, L.words_per_group)) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
-  if (sp::lds_bytes(dm.m.n_meas, L.words_per_group, L.waves_per_group, dm.path) > dm.lds_max)
+  if (sp::lds_bytes(dm.rows_max, L.words_per_group, L.waves_per_group, dm.path) > dm.lds_max)
     return set_error(SP_E_LIMIT, "words_per_group slabs exceed the LDS of one workgroup");
+  return SP_OK;
+}
+
+int check_tile_rows(uint32_t tile_rows) {
+  if (tile_rows % 64 != 0 || tile_rows > kSlabRowsMax)
+    return set_error(SP_E_INVALID, "tile_rows must be 0 or a multiple of 64 up to " + std::to_string(kSlabRowsMax));
   return SP_OK;
 }
 
@@ -765,12 +815,12 @@ int validate_launch(const sp_dmodel& dm, const sp_launch& L) {
 
 extern "C" {
 
-int sp_model_device_bytes(const sp_model* model, int path, size_t* bytes) {
+int sp_model_device_bytes_tiled(const sp_model* model, int path, uint32_t tile_rows, size_t* bytes) {
   if (!model || !bytes) return set_error(SP_E_INVALID, "null argument");
   if (path < SP_PATH_AUTO || path > SP_PATH_DENSE) return set_error(SP_E_INVALID, "unknown path");
+  if (int rc = check_tile_rows(tile_rows)) return rc;
   try {
-    HostBlocks H = build_blocks(*model);
-    *bytes = plan(*model, choose_path(*model, path), H).total;
+    *bytes = plan(*model, choose_path(*model, path), tile_rows).total;
   } catch (const sp::Error& e) {
     return set_error(e.code, e.what());
   } catch (const std::bad_alloc&) {
@@ -779,47 +829,64 @@ int sp_model_device_bytes(const sp_model* model, int path, size_t* bytes) {
   return SP_OK;
 }
 
-int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_bytes, void* stream, sp_dmodel** out) {
+int sp_model_device_bytes(const sp_model* model, int path, size_t* bytes) {
+  return sp_model_device_bytes_tiled(model, path, 0, bytes);
+}
+
+int sp_model_upload_tiled(const sp_model* model, int path, uint32_t tile_rows, void* d_buf, size_t buf_bytes,
+                          void* stream, sp_dmodel** out) {
   if (!model || !d_buf || !out) return set_error(SP_E_INVALID, "null argument");
   *out = nullptr;
   if (path < SP_PATH_AUTO || path > SP_PATH_DENSE) return set_error(SP_E_INVALID, "unknown path");
   if (((uintptr_t)d_buf & 255u) != 0) return set_error(SP_E_INVALID, "device buffer must be 256-byte aligned");
   if (model->channels.size() > 255) return set_error(SP_E_LIMIT, "more than 255 distinct channels");
+  if (int rc = check_tile_rows(tile_rows)) return rc;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   int lds_max = 0;
   HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   const int p = choose_path(*model, path);
-  if (sp::lds_bytes(model->n_meas, 1, 1, p) > (size_t)lds_max)
-    return set_error(SP_E_LIMIT, "n_meas " + std::to_string(model->n_meas) + " needs " +
-                                     std::to_string(sp::lds_bytes(model->n_meas, 1, 1, p)) +
-                                     " bytes of LDS; the device allows " + std::to_string(lds_max));
   std::vector<uint8_t> host;
   Layout L;
+  uint32_t rows_max = 0;
   try {
-    HostBlocks H = build_blocks(*model);
-    L = plan(*model, p, H);
+    L = plan(*model, p, tile_rows);
+    for (const TileLayout& T : L.tiles) rows_max = std::max(rows_max, T.rows);
+    if (sp::lds_bytes(rows_max, 1, 1, p) > (size_t)lds_max)
+      return set_error(SP_E_LIMIT, "a tile of " + std::to_string(rows_max) + " rows needs " +
+                                       std::to_string(sp::lds_bytes(rows_max, 1, 1, p)) +
+                                       " bytes of LDS; the device allows " + std::to_string(lds_max));
     if (buf_bytes < L.total)
       return set_error(SP_E_INVALID, "device buffer of " + std::to_string(buf_bytes) + " bytes, need " +
                                          std::to_string(L.total));
     host.assign(L.total, 0);
-    if (!H.hot.empty()) std::memcpy(&host[L.hot], H.hot.data(), 4 * H.hot.size());
-    if (!H.cold.empty()) std::memcpy(&host[L.cold], H.cold.data(), 4 * H.cold.size());
-    if (!H.entries.empty()) std::memcpy(&host[L.entries], H.entries.data(), 4 * H.entries.size());
     for (uint32_t c = 0; c < L.nch; ++c) {
       uint32_t* t = reinterpret_cast<uint32_t*>(&host[L.chans + 64 * (size_t)c]);
       const sp::Channel& ch = model->channels[c];
       t[0] = ch.kind | (ch.m << 8);
       for (uint32_t k = 1; k < 16; ++k) t[k] = k < ch.m ? (uint32_t)ch.T[k] : 0xFFFFFFFFu;
     }
-    std::memcpy(&host[L.c_mask], model->c_bits.data(), 8 * L.dense_words);
-    if (p == SP_PATH_DENSE) {
-      uint64_t* d = reinterpret_cast<uint64_t*>(&host[L.dense]);
-      for (uint32_t j = 0; j < model->n_vars; ++j)
-        for (uint32_t i = model->col_ptr[j]; i < model->col_ptr[j + 1]; ++i) {
-          const uint32_t k = model->row_idx[i];
-          d[(size_t)j * L.dense_words + (k >> 6)] |= 1ull << (k & 63);
-        }
+    for (size_t ti = 0; ti < L.tiles.size(); ++ti) {
+      const TileLayout& T = L.tiles[ti];
+      const HostBlocks& H = L.blocks[ti];
+      if (!H.hot.empty()) std::memcpy(&host[T.hot], H.hot.data(), 4 * H.hot.size());
+      if (!H.cold.empty()) std::memcpy(&host[T.cold], H.cold.data(), 4 * H.cold.size());
+      if (!H.entries.empty()) std::memcpy(&host[T.entries], H.entries.data(), 4 * H.entries.size());
+      // c of rows [r0, r0 + rows), shifted to start at bit 0
+      uint64_t* cm = reinterpret_cast<uint64_t*>(&host[T.c_mask]);
+      for (uint32_t k = 0; k < T.rows; ++k) {
+        const uint32_t g = T.r0 + k;
+        if ((model->c_bits[g >> 6] >> (g & 63)) & 1ull) cm[k >> 6] |= 1ull << (k & 63);
+      }
+      if (p == SP_PATH_DENSE) {
+        uint64_t* d = reinterpret_cast<uint64_t*>(&host[T.dense]);
+        for (uint32_t j = 0; j < model->n_vars; ++j)
+          for (uint32_t i = model->col_ptr[j]; i < model->col_ptr[j + 1]; ++i) {
+            const uint32_t k = model->row_idx[i];
+            if (k < T.r0 || k >= T.r0 + T.rows) continue;
+            d[(size_t)j * T.dense_words + ((k - T.r0) >> 6)] |= 1ull << ((k - T.r0) & 63);
+          }
+      }
     }
   } catch (const sp::Error& e) {
     return set_error(e.code, e.what());
@@ -833,17 +900,30 @@ int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_byt
   auto* dm = new (std::nothrow) sp_dmodel();
   if (!dm) return set_error(SP_E_NOMEM, "out of host memory");
   const uint8_t* base = (const uint8_t*)d_buf;
-  dm->m.hot = (const uint4*)(base + L.hot);
-  dm->m.cold = (const uint4*)(base + L.cold);
-  dm->m.entries = (const uint32_t*)(base + L.entries);
-  dm->m.chans = (const uint32_t*)(base + L.chans);
-  dm->m.c_mask = (const uint64_t*)(base + L.c_mask);
-  dm->m.dense = p == SP_PATH_DENSE ? (const uint64_t*)(base + L.dense) : nullptr;
-  dm->m.nb = L.nb;
-  dm->m.nch = L.nch;
-  dm->m.defer_max = kDeferMax;
-  dm->m.n_meas = model->n_meas;
-  dm->m.dense_words = L.dense_words;
+  try {
+    for (const TileLayout& T : L.tiles) {
+      sp::DevModel m{};
+      m.hot = (const uint4*)(base + T.hot);
+      m.cold = (const uint4*)(base + T.cold);
+      m.entries = (const uint32_t*)(base + T.entries);
+      m.chans = (const uint32_t*)(base + L.chans);
+      m.c_mask = (const uint64_t*)(base + T.c_mask);
+      m.dense = p == SP_PATH_DENSE ? (const uint64_t*)(base + T.dense) : nullptr;
+      m.nb = T.nb;
+      m.nch = L.nch;
+      m.defer_max = kDeferMax;
+      m.n_meas = T.rows;
+      m.dense_words = T.dense_words;
+      dm->tiles.push_back(m);
+      dm->row0.push_back(T.r0);
+      dm->nb += T.nb;
+    }
+  } catch (const std::bad_alloc&) {
+    delete dm;
+    return set_error(SP_E_NOMEM, "out of host memory");
+  }
+  dm->n_meas = model->n_meas;
+  dm->rows_max = rows_max;
   dm->path = p;
   dm->device = dev;
   dm->lds_max = (size_t)lds_max;
@@ -853,11 +933,22 @@ int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_byt
   return SP_OK;
 }
 
+int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_bytes, void* stream, sp_dmodel** out) {
+  return sp_model_upload_tiled(model, path, 0, d_buf, buf_bytes, stream, out);
+}
+
 void sp_dmodel_free(sp_dmodel* dm) { delete dm; }
 
 int sp_dmodel_dims(const sp_dmodel* dm, sp_dims* out) {
   if (!dm || !out) return set_error(SP_E_INVALID, "null argument");
   *out = dm->dims;
+  return SP_OK;
+}
+
+int sp_dmodel_tiles(const sp_dmodel* dm, uint32_t* n_tiles, uint32_t* rows_max) {
+  if (!dm) return set_error(SP_E_INVALID, "null model");
+  if (n_tiles) *n_tiles = (uint32_t)dm->tiles.size();
+  if (rows_max) *rows_max = dm->rows_max;
   return SP_OK;
 }
 
@@ -879,7 +970,7 @@ int sp_dmodel_set_launch(sp_dmodel* dm, const sp_launch* launch) {
 int sp_sample(const sp_dmodel* dm, uint64_t seed, uint64_t first_shot, uint64_t shots, uint64_t* d_out,
               size_t ld_words, void* stream) {
   if (!dm) return set_error(SP_E_INVALID, "null model");
-  if (shots == 0 || dm->m.n_meas == 0) return SP_OK;
+  if (shots == 0 || dm->n_meas == 0) return SP_OK;
   if (!d_out) return set_error(SP_E_INVALID, "null output");
   if (((uintptr_t)d_out & 7u) != 0) return set_error(SP_E_INVALID, "output must be 8-byte aligned");
   const uint64_t words = (shots + 63) / 64;
@@ -891,17 +982,21 @@ int sp_sample(const sp_dmodel* dm, uint64_t seed, uint64_t first_shot, uint64_t 
   if (dev != dm->device) return set_error(SP_E_INVALID, "current device differs from the model's device");
   const sp_launch& L = dm->launch;
 
-  LaunchArgs a;
-  a.m = dm->m;
-  a.out = d_out;
-  a.ld = ld_words;
-  a.first_shot = first_shot;
-  a.shots = shots;
-  a.key0 = (uint32_t)seed;
-  a.key1 = (uint32_t)(seed >> 32);
-  a.n_words = (uint32_t)words;
-  a.n_groups = (uint32_t)((words + L.words_per_group - 1) / L.words_per_group);
-  return sp::launch_sample(a, dm->path, L, (hipStream_t)stream);
+  // One launch per row tile, each writing its own rows of the output.
+  for (size_t t = 0; t < dm->tiles.size(); ++t) {
+    LaunchArgs a;
+    a.m = dm->tiles[t];
+    a.out = d_out + (size_t)dm->row0[t] * ld_words;
+    a.ld = ld_words;
+    a.first_shot = first_shot;
+    a.shots = shots;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.n_words = (uint32_t)words;
+    a.n_groups = (uint32_t)((words + L.words_per_group - 1) / L.words_per_group);
+    if (int rc = sp::launch_sample(a, dm->path, L, (hipStream_t)stream)) return rc;
+  }
+  return SP_OK;
 }
 
 }  // extern "C"

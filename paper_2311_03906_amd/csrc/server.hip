@@ -104,7 +104,7 @@ int stage_and_launch(sp_server* S, int si) {
       const sp::serve::Request* r = S->sched.find(c.ticket);
       const sp_dmodel* dm = (const sp_dmodel*)r->model;
       sp::BatchJob J{};
-      J.a.m = dm->m;
+      J.a.m = dm->tiles[0];
       J.a.ld = r->words;
       J.a.out = (uint64_t*)(S->arena + r->off) + c.w0;
       J.a.first_shot = r->first_shot + 64 * c.w0;
@@ -117,7 +117,7 @@ int stage_and_launch(sp_server* S, int si) {
       for (uint32_t q = 0; q < J.a.n_groups; ++q) map[g + q] = n_jobs[p];
       g += J.a.n_groups;
       groups[p] += J.a.n_groups;
-      n_meas_max[p] = std::max(n_meas_max[p], dm->m.n_meas);
+      n_meas_max[p] = std::max(n_meas_max[p], dm->tiles[0].n_meas);
       jobs[j++] = J;
       ++n_jobs[p];
     }
@@ -265,13 +265,15 @@ int sp_server_submit(sp_server* S, const sp_dmodel* model, uint64_t seed, uint64
   if (model->device != S->device) return set_error(SP_E_INVALID, "model on another device");
   if (first_shot + shots < first_shot) return set_error(SP_E_INVALID, "shot range overflows 64 bits");
   if ((shots + 63) / 64 > 0x7FFFFFFFull) return set_error(SP_E_LIMIT, "too many shots for one request");
-  if (sp::lds_bytes(model->m.n_meas, S->cfg.launch.words_per_group, S->cfg.launch.waves_per_group, model->path) >
-      model->lds_max)
+  if (model->tiles.size() != 1)
+    return set_error(SP_E_LIMIT, "the server takes models of one row tile (at most one LDS slab of rows)");
+  if (sp::lds_bytes(model->tiles[0].n_meas, S->cfg.launch.words_per_group, S->cfg.launch.waves_per_group,
+                    model->path) > model->lds_max)
     return set_error(SP_E_LIMIT, "the model's slabs exceed the LDS of one workgroup with this launch shape");
   sp::serve::Request r;
   r.model = model;
-  r.n_meas = model->m.n_meas;
-  r.nb = model->m.nb;
+  r.n_meas = model->tiles[0].n_meas;
+  r.nb = model->tiles[0].nb;
   r.path = model->path;
   r.seed = seed;
   r.first_shot = first_shot;

@@ -164,3 +164,23 @@ def test_empty_batch(schedule):
     b.launch()
     torch.cuda.synchronize()
     assert b.info()["groups"] == 0
+
+
+@pytest.mark.parametrize("schedule", ["persistent", "flat"])
+def test_batch_with_row_tiled_models(schedule):
+    """A model stored as row tiles becomes one job per tile inside a batch;
+    with untiled jobs beside it, every job equals the oracle."""
+    _say(f"batch with row-tiled models schedule={schedule}")
+    jobs = _small_jobs(dense_too=False)
+    for circ, tile_rows, path, shots, seed in [(surface_memory(5, 5, "0.005"), 64, "sparse", 3000, 11),
+                                               (surface_memory(3, 3, "0.03"), 64, "dense", 700, 12)]:
+        text = circ.text()
+        m = sp.Model(text)
+        dm = sp.DeviceModel(m, path=path, tile_rows=tile_rows)
+        assert dm.n_tiles > 1 or m.n_meas <= tile_rows
+        out = torch.full((m.n_meas, (shots + 63) // 64 + 1), -1, dtype=torch.int64, device="cuda")
+        jobs.append((sp.Job(dm, shots, seed=seed, first_shot=128, out=out), oracle.Circuit(text)))
+    b = sp.Batch([j for j, _ in jobs], schedule=schedule)
+    b.launch()
+    torch.cuda.synchronize()
+    _check_against_oracle(jobs)

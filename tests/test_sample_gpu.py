@@ -390,3 +390,60 @@ def _written_noise(text, ps, n_qubits):
         if head in ("R", "MR"):
             out.append(f"X_ERROR({ps['p_reset']}) " + " ".join(targets))
     return "\n".join(out) + "\n"
+
+
+# ------------------------------------------------------------- row tiles --
+
+@pytest.mark.parametrize("path", ["sparse", "dense"])
+@pytest.mark.parametrize("tile_rows", [64, 128])
+def test_row_tiles_equal_untiled_and_oracle(path, tile_rows):
+    """Surface d=5, 5 rounds, p = 5e-3, split into row tiles of 64 or 128
+    rows (each tile draws only the locations that reach its rows): every
+    word equals the one-tile model's and the oracle's, for measurement and
+    detector rows."""
+    text = surface_memory(5, 5, "0.005", detectors=True).text()
+    for outputs in ("measurements", "detectors"):
+        _say(f"row tiles {tile_rows} path={path} outputs={outputs}")
+        m = sp.Model(text, outputs=outputs)
+        dm = sp.DeviceModel(m, path=path, tile_rows=tile_rows)
+        assert dm.n_tiles == math.ceil(m.n_meas / tile_rows)
+        ref = sp.DeviceModel(m, path=path)
+        assert ref.n_tiles == 1
+        got = _gpu(dm, 10_000, seed=3, first_shot=640)
+        assert np.array_equal(got, _gpu(ref, 10_000, seed=3, first_shot=640))
+        assert np.array_equal(got, oracle.Circuit(text, outputs=outputs).sample(seed=3, first_shot=640, shots=10_000))
+
+
+def _many_rows_circuit(rounds=5000):
+    """25,000 recorded measurements: qubit 0 (random at first, then repeated
+    without reset, so its outcome's symbol and its sparse X faults reach
+    rows across the whole circuit) and four qubits measured and reset every
+    round."""
+    lines = ["H 0", "CX 0 1"]
+    for k in range(rounds):
+        if k % 100 == 0:
+            lines.append("X_ERROR(0.05) 0")
+        lines += ["DEPOLARIZE1(0.002) 1 2 3 4", "CX 1 2", "M 0", "MR 1 2 3 4"]
+    return "\n".join(lines) + "\n"
+
+
+def test_auto_row_tiles_beyond_one_slab():
+    """25,000 output rows, more than one LDS slab holds: the upload splits
+    them into row tiles of 8,192 rows, and 2,048 shots equal the oracle's
+    word for word (every tile, every row)."""
+    text = _many_rows_circuit()
+    _say("auto row tiles 25000 rows 2048 shots")
+    m = sp.Model(text)
+    assert m.n_meas == 25_000
+    dm = sp.DeviceModel(m)
+    assert (dm.n_tiles, dm.tile_rows_max) == (4, 8192)
+    got = _gpu(dm, 2048, seed=21, first_shot=64)
+    assert np.array_equal(got, oracle.Circuit(text).sample(seed=21, first_shot=64, shots=2048))
+
+
+def test_tile_rows_argument_checked():
+    m = sp.Model(surface_memory(3, 3, "0.01").text())
+    for bad in (63, 100, 19_520):
+        with pytest.raises(sp.SymphaseError) as e:
+            sp.DeviceModel(m, tile_rows=bad)
+        assert e.value.code == sp._capi.SP_E_INVALID

@@ -142,3 +142,16 @@ def test_wait_timeout_and_unknown_ticket():
     with pytest.raises(sp.SymphaseError):
         srv.status(t)
     srv.close()
+
+
+def test_refuses_row_tiled_models():
+    """The server serves models of one row tile; a tiled model is refused
+    with SP_E_LIMIT before anything is queued."""
+    m = sp.Model(surface_memory(5, 5, "0.001").text())
+    dm = sp.DeviceModel(m, tile_rows=64)
+    assert dm.n_tiles == 3
+    srv = sp.Server(arena_bytes=64 << 20, max_active=2)
+    with pytest.raises(sp.SymphaseError) as ei:
+        srv.submit(dm, 1000)
+    assert ei.value.code == sp._capi.SP_E_LIMIT
+    srv.close()
