@@ -232,10 +232,11 @@ int sp_model_device_bytes(const sp_model* model, int path, size_t* bytes);
  *
  * Row tiles: the sampling kernel keeps a 64-shot word's output rows in one
  * LDS slab (19,456 rows at most on gfx950 with room for 16 waves' event
- * queues).  A model with more rows is stored as row tiles of 8,192 rows;
- * each tile holds only the locations that reach its rows, and sp_sample
- * launches once per tile.  The draws are keyed by location, so the output
- * is the same bit for bit whatever the tiling.
+ * queues).  A model of more than 9,216 rows (two workgroups' slabs per CU)
+ * is stored as row tiles of 4,096 rows; each tile holds only the locations
+ * that reach its rows, and sp_sample launches once per tile.  The draws are
+ * keyed by location, so the output is the same bit for bit whatever the
+ * tiling.
  * Errors: SP_E_INVALID, SP_E_LIMIT (a tile does not fit the device's LDS,
  * more than 2^27 rows), SP_E_DEVICE. */
 int sp_model_upload(const sp_model* model, int path, void* d_buf, size_t buf_bytes, void* stream,

@@ -641,10 +641,14 @@ int choose_path(const sp_model& m, int path) {
 }
 
 // Rows of one LDS slab that leave room for the event queues of 16 waves
-// (160 KB of LDS per workgroup on gfx950): a model with more rows is split
-// into row tiles of at most kTileRowsAuto rows.
+// (160 KB of LDS per workgroup on gfx950): the largest tile.  The automatic
+// choice keeps one tile while two workgroups' slabs fit a CU (9,216 rows);
+// past that, a single slab leaves too few waves per SIMD to hide the draw's
+// latency, and tiles of 4,096 rows sample faster despite the draws that
+// several tiles repeat.
 constexpr uint32_t kSlabRowsMax = (160u * 1024u - 16u * sp::kQueueCap * 8u) / 8u;
-constexpr uint32_t kTileRowsAuto = 8192;
+constexpr uint32_t kOneTileRowsMax = 9216;
+constexpr uint32_t kTileRowsAuto = 4096;
 
 struct TileLayout {
   size_t hot, cold, entries, c_mask, dense;
@@ -658,12 +662,12 @@ struct Layout {
   uint32_t nch;
 };
 
-// tile_rows: 0 picks one tile when the rows fit a slab, else tiles of
+// tile_rows: 0 picks one tile up to kOneTileRowsMax rows, else tiles of
 // kTileRowsAuto rows; otherwise tiles of that many rows (a multiple of 64).
 Layout plan(const sp_model& m, int path, uint32_t tile_rows) {
   Layout L{};
   uint32_t per = tile_rows;
-  if (per == 0) per = m.n_meas <= kSlabRowsMax ? std::max<uint32_t>(m.n_meas, 1) : kTileRowsAuto;
+  if (per == 0) per = m.n_meas <= kOneTileRowsMax ? std::max<uint32_t>(m.n_meas, 1) : kTileRowsAuto;
   L.nch = (uint32_t)m.channels.size();
   size_t off = 0;
   L.chans = off;

@@ -429,14 +429,14 @@ def _many_rows_circuit(rounds=5000):
 
 def test_auto_row_tiles_beyond_one_slab():
     """25,000 output rows, more than one LDS slab holds: the upload splits
-    them into row tiles of 8,192 rows, and 2,048 shots equal the oracle's
+    them into row tiles of 4,096 rows, and 2,048 shots equal the oracle's
     word for word (every tile, every row)."""
     text = _many_rows_circuit()
     _say("auto row tiles 25000 rows 2048 shots")
     m = sp.Model(text)
     assert m.n_meas == 25_000
     dm = sp.DeviceModel(m)
-    assert (dm.n_tiles, dm.tile_rows_max) == (4, 8192)
+    assert (dm.n_tiles, dm.tile_rows_max) == (7, 4096)
     got = _gpu(dm, 2048, seed=21, first_shot=64)
     assert np.array_equal(got, oracle.Circuit(text).sample(seed=21, first_shot=64, shots=2048))
 
@@ -447,3 +447,24 @@ def test_tile_rows_argument_checked():
         with pytest.raises(sp.SymphaseError) as e:
             sp.DeviceModel(m, tile_rows=bad)
         assert e.value.code == sp._capi.SP_E_INVALID
+
+
+def test_paper_fig3_n700_device_init_and_row_tiles():
+    """Fig. 3a at n = 700 (25,200 rows): Initialization on the GPU with the
+    tableau in device memory (too large for LDS) gives the host's model,
+    and sampling in row tiles gives 48 of 2^16 shots equal to the oracle's."""
+    text = random_layered_circuit(700, seed=3, cnot_pairs=5).text()
+    _say("fig3a n=700 device init + row tiles, 48 sampled shots")
+    m = sp.Model(text, init="device")
+    host = sp.Model(text)
+    assert (m.n_meas, m.n_vars, m.dims.nnz) == (host.n_meas, host.n_vars, host.dims.nnz)
+    for x, y in zip(m.export_csc(), host.export_csc()):
+        assert np.array_equal(x, y)
+    dm = sp.DeviceModel(m)
+    assert dm.n_tiles == math.ceil(m.n_meas / 4096)
+    shots = 1 << 16
+    got = _gpu(dm, shots, seed=5)
+    ids = np.sort(np.random.default_rng(0).choice(shots, 48, replace=False))
+    want = oracle.Circuit(text).sample_shots(seed=5, shot_ids=ids)
+    for i, s in enumerate(ids):
+        assert np.array_equal(_column(got, int(s)), want[i]), int(s)
