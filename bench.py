@@ -40,7 +40,8 @@ def parse_args():
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
     ap.add_argument("--legs", default="rep,d15,outputs,init,fig3,mix,small,serving",
-                    help="comma list of the other workloads to run (rep, d15, outputs, init, fig3, mix, small, serving)")
+                    help="comma list of the other workloads to run (rep, d15, outputs, init, fig3, mix, small, serving; "
+                         "fig3big, not in the default, runs Fig. 3c at n = 600 and 1000)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -177,7 +178,7 @@ def main():
     legs = set() if args.no_extra else {x.strip() for x in args.legs.split(",") if x.strip()}
     if args.no_serving:
         legs.discard("serving")
-    unknown = legs - {"rep", "d15", "outputs", "init", "fig3", "mix", "small", "serving"}
+    unknown = legs - {"rep", "d15", "outputs", "init", "fig3", "fig3big", "mix", "small", "serving"}
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
         sys.exit(2)
@@ -187,6 +188,8 @@ def main():
             rec["extra"]["initialization_d15"] = init_leg(sp, torch, surface_memory)
         if "fig3" in legs:
             rec["extra"]["paper_fig3_layered_random"] = fig3_leg(sp, torch)
+        if "fig3big" in legs:
+            rec["extra"]["paper_fig3c_largest"] = fig3_big_leg(sp, torch)
         if "mix" in legs:
             rec["extra"]["batched_mix_64"] = batched_mix_leg(sp, torch)
         if "small" in legs:
@@ -273,36 +276,64 @@ def fig3_leg(sp, torch) -> dict:
     circuits, n qubits x n layers; each layer H/S/nothing per qubit, CNOTs
     on 5 (3a) or floor(n/2) (3b, 3c) random disjoint pairs, single-qubit
     depolarizing noise on every qubit (3c, p = 1e-3), then a Z measurement
-    of 5% of the qubits; all qubits measured at the end.  Reported: host
-    Initialization time and GPU time to generate 10^4 samples (the paper's
-    sampling metric), and 10^6 samples for throughput."""
+    of 5% of the qubits; all qubits measured at the end.  Reported:
+    Initialization time on the GPU, and on the host where it takes seconds
+    (the host pass grows about as n^3.5 on 3b/3c), then GPU time to generate
+    10^4 samples (the paper's sampling metric) and 10^6 samples; circuits
+    of more than 9,216 rows are sampled in row tiles.  n = 1000 is the
+    paper's largest size (3c there is in the 'fig3big' leg)."""
     from workloads import random_layered_circuit
     res = {}
-    for n in (100, 200):
-        for fig, kw in (("3a", {"cnot_pairs": 5}), ("3b", {}), ("3c", {"p_dep": "0.001"})):
-            text = random_layered_circuit(n, seed=0, **kw).text()
-            circ = sp.Circuit(text)
-            t0 = time.perf_counter()
-            m = sp.Model(circ)
-            t_init = time.perf_counter() - t0
-            t_dev = _device_init_s(sp, torch, circ, "measurements")
-            dm = sp.DeviceModel(m)
-            r = {"n_meas": m.n_meas, "n_vars": m.n_vars, "nnz": int(m.dims.nnz), "drawn": int(m.dims.n_drawn),
-                 "path": dm.path, "init_s": t_init, "init_device_s": t_dev}
-            for shots in (10_000, 1_000_000):
-                out = torch.empty((m.n_meas, (shots + 63) // 64), dtype=torch.int64, device="cuda")
-                lat = _event_ms(lambda: dm.sample(shots, seed=0, out=out), 10, torch)
-                ms = pct(lat, 50)
-                r[f"ms_{shots}"] = ms
-                r[f"bits_per_s_{shots}"] = shots * m.n_meas / (ms * 1e-3)
-            res[f"fig{fig}_n{n}"] = r
+    sizes = [(100, ("3a", "3b", "3c")), (200, ("3a", "3b", "3c")), (400, ("3a", "3b", "3c")),
+             (700, ("3a", "3b")), (1000, ("3a", "3b"))]
+    for n, figs in sizes:
+        for fig in figs:
+            res[f"fig{fig}_n{n}"] = _fig3_case(sp, torch, random_layered_circuit, fig, n)
     return res
 
 
-def _device_init_s(sp, torch, circ, outputs, reps=3) -> float:
+def fig3_big_leg(sp, torch) -> dict:
+    """Fig. 3c at the paper's largest size, n = 1000 (2,000,000 fault
+    variables, 51,000 measurements): Initialization on the GPU only (about
+    a minute; the host pass would take hours), then sampling."""
+    from workloads import random_layered_circuit
+    return {"fig3c_n600": _fig3_case(sp, torch, random_layered_circuit, "3c", 600),
+            "fig3c_n1000": _fig3_case(sp, torch, random_layered_circuit, "3c", 1000)}
+
+
+_FIG3_KW = {"3a": {"cnot_pairs": 5}, "3b": {}, "3c": {"p_dep": "0.001"}}
+# host Initialization is timed where it takes seconds
+_FIG3_HOST_MAX_N = {"3a": 1000, "3b": 400, "3c": 200}
+
+
+def _fig3_case(sp, torch, random_layered_circuit, fig, n) -> dict:
+    print(f"fig{fig} n={n}", file=sys.stderr, flush=True)
+    circ = sp.Circuit(random_layered_circuit(n, seed=0, **_FIG3_KW[fig]).text())
+    t_host = None
+    if n <= _FIG3_HOST_MAX_N[fig]:
+        t0 = time.perf_counter()
+        sp.Model(circ)
+        t_host = time.perf_counter() - t0
+    t_dev = _device_init_s(sp, torch, circ, "measurements", reps=3 if n <= 200 else 1, warm=n <= 200)
+    m = sp.Model(circ, init="device")
+    dm = sp.DeviceModel(m)
+    r = {"n_meas": m.n_meas, "n_vars": m.n_vars, "nnz": int(m.dims.nnz), "drawn": int(m.dims.n_drawn),
+         "path": dm.path, "row_tiles": dm.n_tiles, "init_s": t_host, "init_device_s": t_dev}
+    for shots in (10_000, 1_000_000):
+        out = torch.empty((m.n_meas, (shots + 63) // 64), dtype=torch.int64, device="cuda")
+        lat = _event_ms(lambda: dm.sample(shots, seed=0, out=out), 10 if n <= 400 else 3, torch)
+        ms = pct(lat, 50)
+        r[f"ms_{shots}"] = ms
+        r[f"bits_per_s_{shots}"] = shots * m.n_meas / (ms * 1e-3)
+        del out
+    return r
+
+
+def _device_init_s(sp, torch, circ, outputs, reps=3, warm=True) -> float:
     """Median wall time of Initialization on the GPU (sp_symbolize_device,
     synchronous: instruction upload, kernel, copy-back, host assembly)."""
-    sp.Model(circ, outputs=outputs, init="device")
+    if warm:
+        sp.Model(circ, outputs=outputs, init="device")
     ts = []
     for _ in range(reps):
         torch.cuda.synchronize()

@@ -468,3 +468,21 @@ def test_paper_fig3_n700_device_init_and_row_tiles():
     want = oracle.Circuit(text).sample_shots(seed=5, shot_ids=ids)
     for i, s in enumerate(ids):
         assert np.array_equal(_column(got, int(s)), want[i]), int(s)
+
+
+def test_paper_fig3c_n700_device_init_sampled():
+    """Fig. 3c at n = 700 (980,000 fault variables, 25,200 rows): the model
+    built on the GPU (tableau in device memory, dense phase rows of about
+    15,000 words), sampled in row tiles, gives 16 of 4,096 shots equal to the
+    oracle's (the host pass takes minutes at this size)."""
+    text = random_layered_circuit(700, seed=0, p_dep="0.001").text()
+    _say("fig3c n=700 device init (about 10 s)")
+    m = sp.Model(text, init="device")
+    dm = sp.DeviceModel(m)
+    assert dm.n_tiles > 1
+    got = _gpu(dm, 4096, seed=7)
+    ids = np.array([0, 1, 63, 64, 100, 1000, 2047, 2048, 3000, 3333, 4000, 4095, 17, 555, 777, 1234])
+    _say("fig3c n=700 oracle, 16 shots")
+    want = oracle.Circuit(text).sample_shots(seed=7, shot_ids=ids)
+    for i, s in enumerate(ids):
+        assert np.array_equal(_column(got, int(s)), want[i]), int(s)
