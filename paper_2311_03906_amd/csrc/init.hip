@@ -20,8 +20,8 @@
 // Init-P: the fault variable j on qubit q adds s_j to the stabilizer rows
 // it anticommutes with.  A fault instruction's variables are consecutive, so
 // each wave takes a 64-variable word of P: every lane gathers its variable's
-// column word (z_q for X, x_q for Z) and 64 ballots transpose the 64x64 bit
-// block into the 64 rows' words.
+// column word (z_q for X, x_q for Z) and a 64x64 bit transpose across the
+// wave turns the block into the 64 rows' words.
 //
 // Init-M, random branch (a stabilizer row p has x_q = 1): the g sums of
 // every row against p are accumulated at once as 2-bit bit-sliced counters
@@ -121,6 +121,28 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v) {
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t src) {
   return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)src) |
          (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)src) << 32;
+}
+
+// 64x64 bit transpose across a wave: lane l holds row l (bit j = column j)
+// and gets back column l.  Six rounds; in the round of stride j, lanes l and
+// l ^ j swap the blocks where the row index has bit j set and the column
+// index has it clear (the recursive block transpose, LSB-first bits).
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, uint32_t j) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, (int)j, 64);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), (int)j, 64);
+  return (uint64_t)lo | (uint64_t)hi << 32;
+}
+__device__ __forceinline__ uint64_t transpose64(uint64_t x, uint32_t lane) {
+  constexpr uint64_t kMask[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                                 0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const uint32_t j = 32u >> i;
+    const uint64_t y = shfl_xor64(x, j);
+    if (lane & j) x ^= ((y >> j) ^ x) & kMask[i];            // this lane holds the upper row of the pair
+    else x ^= (((x >> j) ^ y) & kMask[i]) << j;               // the lower row
+  }
+  return x;
 }
 
 // A vector load of memory this kernel writes, also where the address is
@@ -260,10 +282,10 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
       const uint32_t nv = cnt << lg;
       for (uint32_t k = tid; k < cnt; k += kThreads) d.loc_var0[nloc + k] = (int32_t)(vars + (k << lg));
       // One wave per 64-variable word of P.  Lane l takes variable
-      // 64*vw + l, gathers the column word that decides which stabilizer
-      // rows anticommute with its Pauli (z_q for X, x_q for Z, both for Y),
-      // and 64 ballots transpose that word: ballot j is row 64*w + j's
-      // bits for the wave's 64 variables, kept by lane j.
+      // 64*vw + l and gathers the column word that decides which stabilizer
+      // rows anticommute with its Pauli (z_q for X, x_q for Z, both for Y);
+      // a 64x64 bit transpose turns those into row 64*w + j's bits for the
+      // wave's 64 variables, held by lane j.
       const uint32_t lane = tid & 63u;
       const uint32_t vw0 = vars >> 6, vw1 = (vars + nv - 1) >> 6;
       const uint32_t sw0 = n >> 6, sw1 = (2 * n - 1) >> 6;
@@ -287,12 +309,7 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
           if (use_x) col ^= X[(size_t)qc * RW + w];
           col &= stab_mask(w, n);
           if (__ballot(col != 0) == 0) continue;
-          uint64_t out = 0;
-#pragma unroll 16
-          for (uint32_t j = 0; j < 64; ++j) {
-            const uint64_t bal = __ballot((col >> j) & 1u);
-            out = lane == j ? bal : out;
-          }
+          const uint64_t out = transpose64(col, lane);   // lane j: row 64 w + j's bits for the 64 variables
           const uint32_t row = w * 64 + lane;
           if (out) d.P[(size_t)(row - n) * W + vw] |= out;
         }
@@ -390,18 +407,36 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
             uint64_t c0 = 0, c1 = 0;
             const uint64_t mw = ld(xa + w) & ~(w == pw ? pb : 0ull);
             if (mw) {
-              for (uint32_t q = chunk; q < n; q += kChunks) {
-                const uint64_t* xq = X + (size_t)q * RW;
-                const uint64_t* zq = Z + (size_t)q * RW;
-                const uint64_t lx = (xq[pw] & pb) ? ~0ull : 0ull, lz = (zq[pw] & pb) ? ~0ull : 0ull;
-                if (!(lx | lz)) continue;
+              // c += plus; c -= minus (mod 4, per bit), for column q whose row-p
+              // bits are (px, pz) and whose word w is (vx, vz)
+              auto add = [&](uint64_t px, uint64_t pz, uint64_t vx, uint64_t vz) {
+                const uint64_t lx = (px & pb) ? ~0ull : 0ull, lz = (pz & pb) ? ~0ull : 0ull;
                 uint64_t plus, minus;
-                g_masks(lx, lz, xq[w], zq[w], plus, minus);
-                // c += plus; c -= minus (mod 4, per bit)
+                g_masks(lx, lz, vx, vz, plus, minus);
                 c1 ^= c0 & plus;
                 c0 ^= plus;
                 c1 ^= ~c0 & minus;
                 c0 ^= minus;
+              };
+              uint32_t q = chunk;
+              for (; q + kChunks < n; q += 2 * kChunks) {   // two columns' loads in flight
+                uint64_t px[2], pz[2], vx[2], vz[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                  const uint64_t* xq = X + (size_t)(q + i * kChunks) * RW;
+                  const uint64_t* zq = Z + (size_t)(q + i * kChunks) * RW;
+                  px[i] = xq[pw];
+                  pz[i] = zq[pw];
+                  vx[i] = xq[w];
+                  vz[i] = zq[w];
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i) add(px[i], pz[i], vx[i], vz[i]);
+              }
+              for (; q < n; q += kChunks) {
+                const uint64_t* xq = X + (size_t)q * RW;
+                const uint64_t* zq = Z + (size_t)q * RW;
+                add(xq[pw], zq[pw], xq[w], zq[w]);
               }
             }
             s_c0[w * kChunks + chunk] = c0;
@@ -438,11 +473,12 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
           uint64_t* zq = Z + (size_t)q * RW;
           const uint64_t bx = xq[pw] & pb, bz = zq[pw] & pb;
           const uint64_t lx = bx ? ~0ull : 0ull, lz = bz ? ~0ull : 0ull;
-          for (uint32_t w = 0; w < RW; ++w) {
-            const uint64_t m = s_mask[w];
-            xq[w] ^= m & lx;
-            zq[w] ^= m & lz;
-          }
+          if (bx | bz)   // otherwise the column keeps its words
+            for (uint32_t w = 0; w < RW; ++w) {
+              const uint64_t m = s_mask[w];
+              xq[w] ^= m & lx;
+              zq[w] ^= m & lz;
+            }
           const uint32_t dr = p - n, dw = dr >> 6;
           const uint64_t db = 1ull << (dr & 63);
           xq[dw] = (xq[dw] & ~db) | (bx ? db : 0ull);
@@ -477,15 +513,26 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
           const uint64_t* xq = X + (size_t)tid * RW;
           const uint64_t* zq = Z + (size_t)tid * RW;
           uint32_t xs = 0, zs = 0;
-          for (uint32_t j = 0; j < ns; ++j) {
-            const uint32_t r = n + s_rows[j];
-            const uint32_t xi = bit_of(xq, r), zi = bit_of(zq, r);
+          auto step = [&](uint32_t xi, uint32_t zi) {
             uint64_t plus, minus;
             g_masks(xi, zi, xs, zs, plus, minus);
             g += (uint32_t)plus - (uint32_t)minus;   // mod 2^32, reduced mod 4 below
             xs ^= xi;
             zs ^= zi;
+          };
+          uint32_t j = 0;
+          for (; j + 4 <= ns; j += 4) {   // four rows' loads in flight
+            uint32_t xi[4], zi[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const uint32_t r = n + s_rows[j + i];
+              xi[i] = bit_of(xq, r);
+              zi[i] = bit_of(zq, r);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) step(xi[i], zi[i]);
           }
+          for (; j < ns; ++j) step(bit_of(xq, n + s_rows[j]), bit_of(zq, n + s_rows[j]));
         }
         for (uint32_t j = 0; j < ns; ++j) cpar ^= bit_of(s_C, n + s_rows[j]);
         const uint32_t per = (Wt + kThreads - 1) / kThreads;
