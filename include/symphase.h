@@ -201,6 +201,26 @@ int sp_symbolize_device_work_bytes(const sp_circuit* circuit, size_t* bytes);
 int sp_symbolize_device(const sp_circuit* circuit, int outputs, void* d_work, size_t work_bytes, void* stream,
                         sp_model** out);
 
+/* How sp_symbolize_device runs (same model either way):
+ *   SP_INIT_ONE_PASS  one workgroup updates tableau and phase rows together;
+ *   SP_INIT_TWO_PASS  the one-workgroup pass only logs each row operation's
+ *                     rows (the tableau never depends on the phases, Fact 2),
+ *                     then a kernel over the whole GPU replays the log on the
+ *                     phase rows, each workgroup a slice of their words in
+ *                     LDS, and two small kernels turn the determined
+ *                     outcomes' rows into index lists;
+ *   SP_INIT_AUTO      two passes when the phase rows (n_qubits x
+ *                     ceil((variables + 1)/64) words) exceed 32 MiB.
+ * The two-pass work buffer holds the log and, after it, the determined
+ * recorded outcomes' rows and lists; sp_symbolize_device_work_bytes_mode
+ * sizes that room for every recorded outcome, at most 1 GiB; when a call
+ * needs more it fails with SP_E_LIMIT and a message naming a size that
+ * suffices ("at least N bytes"). */
+enum { SP_INIT_AUTO = 0, SP_INIT_ONE_PASS = 1, SP_INIT_TWO_PASS = 2 };
+int sp_symbolize_device_work_bytes_mode(const sp_circuit* circuit, int mode, size_t* bytes);
+int sp_symbolize_device_mode(const sp_circuit* circuit, int outputs, int mode, void* d_work, size_t work_bytes,
+                             void* stream, sp_model** out);
+
 int sp_model_dims(const sp_model* model, sp_dims* out);
 
 /* Expected work of one 64-shot word: fired locations (sum over drawn

@@ -10,6 +10,7 @@ fallback: without the built library, importing the binding raises.
 from __future__ import annotations
 
 import ctypes
+import re
 
 import numpy as np
 import torch
@@ -89,6 +90,7 @@ class Circuit:
 
 
 _OUTPUTS = {"measurements": _capi.SP_OUT_MEASUREMENTS, "detectors": _capi.SP_OUT_DETECTORS}
+_INIT_MODES = {"auto": _capi.SP_INIT_AUTO, "one_pass": _capi.SP_INIT_ONE_PASS, "two_pass": _capi.SP_INIT_TWO_PASS}
 
 
 class Model:
@@ -100,7 +102,7 @@ class Model:
     work buffer from torch on `device`; both give the same model."""
 
     def __init__(self, circuit: Circuit | str, outputs: str = "measurements", init: str = "host", device=None,
-                 stream=None):
+                 stream=None, init_mode: str = "auto"):
         if isinstance(circuit, str):
             circuit = Circuit(circuit)
         if outputs not in _OUTPUTS:
@@ -115,15 +117,25 @@ class Model:
             if not torch.cuda.is_available():
                 raise SymphaseError(-5, "no GPU: device Initialization runs only on the device")
             device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+            mode = _INIT_MODES[init_mode]
             n = ctypes.c_size_t()
-            check(lib().sp_symbolize_device_work_bytes(circuit.handle, ctypes.byref(n)))
+            check(lib().sp_symbolize_device_work_bytes_mode(circuit.handle, mode, ctypes.byref(n)))
+            size = n.value
             with torch.cuda.device(device):
-                work = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
-                base = work.data_ptr()
-                off = (-base) % 256
-                check(lib().sp_symbolize_device(circuit.handle, _OUTPUTS[outputs], ctypes.c_void_p(base + off),
-                                                n.value, ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))
-            del work
+                for attempt in range(2):   # the two-pass mode may name a larger buffer once
+                    work = torch.empty(size + 256, dtype=torch.uint8, device=device)
+                    base = work.data_ptr()
+                    off = (-base) % 256
+                    rc = lib().sp_symbolize_device_mode(circuit.handle, _OUTPUTS[outputs], mode,
+                                                        ctypes.c_void_p(base + off), size,
+                                                        ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h))
+                    del work
+                    msg = lib().sp_last_error().decode(errors="replace") if rc else ""
+                    need = re.search(r"at least (\d+) bytes", msg) if rc == _capi.SP_E_LIMIT else None
+                    if need is None or attempt == 1:
+                        check(rc)
+                        break
+                    size = int(need.group(1)) + (1 << 20)
         self._h = h
         d = sp_dims()
         check(lib().sp_model_dims(h, ctypes.byref(d)))

@@ -19,11 +19,13 @@ SP_REQ_QUEUED, SP_REQ_ACTIVE, SP_REQ_DONE, SP_REQ_FAILED = 0, 1, 2, 3
 SP_PATH_AUTO, SP_PATH_SPARSE, SP_PATH_DENSE = 0, 1, 2
 SP_SCHED_PERSISTENT, SP_SCHED_FLAT = 0, 1
 SP_OUT_MEASUREMENTS, SP_OUT_DETECTORS = 0, 1
+SP_INIT_AUTO, SP_INIT_ONE_PASS, SP_INIT_TWO_PASS = 0, 1, 2
 
 #: every function the header declares (checked by the tests)
 EXPORTS = (
     "sp_circuit_parse", "sp_circuit_free", "sp_circuit_add_noise", "sp_circuit_counts", "sp_symbolize", "sp_symbolize_outputs",
-    "sp_symbolize_device_work_bytes", "sp_symbolize_device", "sp_model_free", "sp_model_dims",
+    "sp_symbolize_device_work_bytes", "sp_symbolize_device", "sp_symbolize_device_work_bytes_mode",
+    "sp_symbolize_device_mode", "sp_model_free", "sp_model_dims",
     "sp_model_expected_work",
     "sp_model_export_dense", "sp_model_export_csc", "sp_model_export_vars", "sp_model_device_bytes",
     "sp_model_upload", "sp_model_device_bytes_tiled", "sp_model_upload_tiled", "sp_dmodel_free", "sp_dmodel_dims",
@@ -98,6 +100,8 @@ def lib():
         "sp_symbolize_outputs": ([vp, ctypes.c_int, P(vp)], ctypes.c_int),
         "sp_symbolize_device_work_bytes": ([vp, P(sz)], ctypes.c_int),
         "sp_symbolize_device": ([vp, ctypes.c_int, vp, sz, vp, P(vp)], ctypes.c_int),
+        "sp_symbolize_device_work_bytes_mode": ([vp, ctypes.c_int, P(sz)], ctypes.c_int),
+        "sp_symbolize_device_mode": ([vp, ctypes.c_int, ctypes.c_int, vp, sz, vp, P(vp)], ctypes.c_int),
         "sp_circuit_counts": ([vp, P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32)],
                               ctypes.c_int),
         "sp_model_free": ([vp], None),

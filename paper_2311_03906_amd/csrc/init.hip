@@ -84,8 +84,27 @@ struct InitDev {
   uint32_t* rec_c;      // constant bit
   uint32_t* list;
   uint32_t list_cap;
-  uint32_t* status;     // n_vars, n_random, list used, overflow, n_locs, n_rec
+  uint32_t* status;     // n_vars, n_random, list used, overflow, n_locs, n_rec, then (logged pass)
+                        // log words and snapshot words (64-bit each, as two halves), recorded determined outcomes
+  // Logged pass only (the phase rows are left to the replay kernel):
+  uint64_t* log;        // row-operation log, see LogKind
+  uint64_t* snap;       // per fault location and qubit: its x and z stabilizer-row masks
+  int32_t* rec_det;     // determined recorded outcome: its index among those, else -1
 };
+
+// Row-operation log of the logged pass.  Every mask is over the
+// stabilizer rows, bit i = stabilizer row n + i = phase row i, in
+// DW = ceil(n/64) words.  Entries, in program order:
+//   FAULT   3 words: kind | fault kind << 8 | lg << 12 | nq << 16 | nv << 32;
+//           first variable; snapshot offset (item k, qubit j: the x mask at
+//           off + (k nq + j) 2 DW, the z mask after it)
+//   RAND    2 words: kind | reset << 8 | (p - n) << 32; variable; then the
+//           rows taking row p (x_a, without p), then (reset) the rows with z_a after
+//   DET     2 words: kind | reset << 8 | recorded << 9 | det << 32; 0; then the
+//           selected rows (destabilizers with x_a), then (reset) the rows with z_a
+//   FB_RAND 2 words: kind | var << 32; 0; then the anticommuting rows
+//   FB_DET  2 words: kind | det << 32; 0; then the anticommuting rows
+enum LogKind : uint32_t { LOG_FAULT = 1, LOG_RAND, LOG_DET, LOG_FB_RAND, LOG_FB_DET };
 
 __device__ __forceinline__ uint32_t bit_of(const uint64_t* col, uint32_t r) { return (uint32_t)(col[r >> 6] >> (r & 63)) & 1u; }
 
@@ -153,8 +172,9 @@ __device__ __forceinline__ T ld(const T* p) {
 }
 
 // TAB_LDS: the tableau lives in dynamic LDS (2 n RW words), else in the
-// work buffer.
-template <bool TAB_LDS>
+// work buffer.  LOG: the logged pass, which leaves the phase rows to the
+// replay kernel and writes the row-operation log instead.
+template <bool TAB_LDS, bool LOG>
 __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
   extern __shared__ uint64_t s_tab[];
   __shared__ uint64_t s_C[kMaxRW];      // constant phase bit of every row
@@ -186,6 +206,23 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
   uint32_t vars = 0, n_random = 0, nloc = 0, nrec = 0, listu = 0, overflow = 0;
   const uint32_t lane = tid & 63u, wave = tid >> 6;
   const uint32_t sw0 = n >> 6, sw1 = n ? (2 * n - 1) >> 6 : 0;   // words holding stabilizer rows
+  // Logged pass: words of the log and of the snapshots written so far, and
+  // determined recorded outcomes so far (all uniform).
+  const uint32_t DW = (n + 63) >> 6, sh = n & 63u;
+  uint64_t lp = 0, snp = 0;
+  uint32_t n_det = 0;
+  // Word k of a mask over phase-row indices (bit i = stabilizer row n + i),
+  // from word(w) of the same mask over tableau rows.
+  auto pword = [&](auto word, uint32_t k) -> uint64_t {
+    const uint32_t w = sw0 + k;
+    uint64_t v = word(w) >> sh;
+    if (sh && w + 1 < RW) v |= word(w + 1) << (64u - sh);
+    if (sh && k == DW - 1) v &= (1ull << sh) - 1ull;
+    return v;
+  };
+  auto log_mask = [&](uint64_t at, auto word) {
+    for (uint32_t k = tid; k < DW; k += kThreads) d.log[at + k] = pword(word, k);
+  };
 
   // A uniform loop over the set stabilizer rows of a mask, run by every wave
   // alike (no barrier, no shared list): word(w) returns mask word w (a
@@ -286,6 +323,31 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
       // rows anticommute with its Pauli (z_q for X, x_q for Z, both for Y);
       // a 64x64 bit transpose turns those into row 64*w + j's bits for the
       // wave's 64 variables, held by lane j.
+      if (LOG) {
+        // Logged pass: the qubits' x and z stabilizer-row masks, for the
+        // replay kernel to transpose into its own words of the phase rows.
+        const uint32_t nq = kind0 == F_DEP2 ? 2u : 1u;
+        const uint32_t per_item = nq * 2u * DW;
+        for (uint32_t i = tid; i < cnt * per_item; i += kThreads) {
+          const uint32_t k = i / per_item, rem = i % per_item;
+          const uint32_t j = rem / (2u * DW), xz = (rem / DW) & 1u, w = rem % DW;
+          const uint32_t item = it[k];
+          const uint32_t q = j ? (item >> 14) & 0x3FFFu : item & 0x3FFFu;
+          const uint64_t* col = (xz ? Z : X) + (size_t)q * RW;
+          d.snap[snp + i] = pword([&](uint32_t ww) { return col[ww]; }, w);
+        }
+        if (tid == 0) {
+          d.log[lp] = LOG_FAULT | kind0 << 8 | lg << 12 | nq << 16 | (uint64_t)nv << 32;
+          d.log[lp + 1] = vars;
+          d.log[lp + 2] = snp;
+        }
+        lp += 3;
+        snp += (uint64_t)cnt * per_item;
+        nloc += cnt;
+        vars += nv;
+        __syncthreads();
+        continue;
+      }
       const uint32_t lane = tid & 63u;
       const uint32_t vw0 = vars >> 6, vw1 = (vars + nv - 1) >> 6;
       const uint32_t sw0 = n >> 6, sw1 = (2 * n - 1) >> 6;
@@ -330,6 +392,22 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
         const uint32_t px = pauli != 3, pz = pauli != 1;
         const int32_t rv = (int32_t)uni((uint32_t)ld(d.rec_var + rec));
         const uint32_t ec = uni(ld(d.rec_c + rec));
+        if (LOG) {
+          const uint32_t ref = rv >= 0 ? (uint32_t)rv : uni((uint32_t)ld(d.rec_det + rec));
+          if (tid == 0) {
+            d.log[lp] = (rv >= 0 ? LOG_FB_RAND : LOG_FB_DET) | (uint64_t)ref << 32;
+            d.log[lp + 1] = 0;
+          }
+          log_mask(lp + 2, [&](uint32_t w) {
+            return (px ? Z[(size_t)q * RW + w] : 0ull) ^ (pz ? X[(size_t)q * RW + w] : 0ull);
+          });
+          lp += 2 + DW;
+          if (ec && tid < RW)
+            s_C[tid] ^= ((px ? Z[(size_t)q * RW + tid] : 0ull) ^ (pz ? X[(size_t)q * RW + tid] : 0ull)) &
+                        stab_mask(tid, n);
+          __syncthreads();
+          continue;
+        }
         if (rv >= 0) {   // a random record: its variable alone, constant 0
           add_var(q, px, pz, (uint32_t)rv);
           continue;
@@ -388,12 +466,12 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
         ++n_random;
         const uint32_t pw = p >> 6;
         const uint64_t pb = 1ull << (p & 63);
-        rows_to_lds(s_rows, 0, [&](uint32_t w) { return ld(xa + w) & ~(w == pw ? pb : 0ull); }, true);
+        if (!LOG) rows_to_lds(s_rows, 0, [&](uint32_t w) { return ld(xa + w) & ~(w == pw ? pb : 0ull); }, true);
         if (tid < RW) s_mask[tid] = ld(xa + tid) & ~(tid == pw ? pb : 0ull);
         const uint32_t cp = bit_of(s_C, p);
         // Row p's symbols move to Ecur, to be added to the rows below; row p
         // becomes the fresh variable alone.
-        {
+        if (!LOG) {
           uint64_t* pp = d.P + (size_t)(p - n) * W;
           for (uint32_t w = tid; w < Wt; w += kThreads) {
             Ecur[w] = pp[w];
@@ -457,8 +535,15 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
           if (tid == pw) cw &= ~pb;
           s_C[tid] = cw;
         }
-        // Symbols: every stabilizer row with x_a adds row p's old ones.
-        {
+        // Symbols: every stabilizer row with x_a adds row p's old ones (the
+        // logged pass logs those rows instead).
+        if (LOG) {
+          if (tid == 0) {
+            d.log[lp] = LOG_RAND | (op != D_M ? 1u : 0u) << 8 | (uint64_t)(p - n) << 32;
+            d.log[lp + 1] = (uint32_t)e_var;
+          }
+          log_mask(lp + 2, [&](uint32_t w) { return s_mask[w]; });
+        } else {
           const uint32_t nr = s_cnt[0];
           for (uint32_t i = tid; i < nr * Wt; i += kThreads) {
             const uint32_t r = s_rows[i / Wt], w = i % Wt;
@@ -493,11 +578,20 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
             d.rec_c[nrec] = 0;
             d.rec_off[nrec] = 0;
             d.rec_len[nrec] = 0;
+            if (LOG) d.rec_det[nrec] = -1;
           }
           ++nrec;
         }
         // Reset (R, MR): X^e on qubit a, e the fresh variable.
-        if (op != D_M) add_var(a, 1, 0, (uint32_t)e_var);
+        if (LOG) {
+          if (op != D_M) {
+            log_mask(lp + 2 + DW, [&](uint32_t w) { return Z[(size_t)a * RW + w]; });
+            __syncthreads();
+          }
+          lp += 2 + (op != D_M ? 2u : 1u) * DW;
+        } else if (op != D_M) {
+          add_var(a, 1, 0, (uint32_t)e_var);
+        }
       } else {
         // ---- determined outcome ----------------------------------------------
         // The product of the stabilizers n+i for the destabilizers i with
@@ -505,7 +599,21 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
         // its constant, and its symbols E (each thread a range of words).
         if (tid == 0) d.loc_var0[nloc] = -1;
         rows_to_lds(s_rows, 0, [&](uint32_t w) { return ld(xa + w); }, false);
-        if (op != D_M) rows_to_lds(s_rows2, 1, [&](uint32_t w) { return ld(Z + (size_t)a * RW + w); }, true);
+        if (LOG) {
+          // The selected rows (destabilizers i with x_a: phase row i) and the
+          // rows with z_a, logged while x_a and z_a cannot change.
+          const bool recorded = op != D_R, reset = op != D_M;
+          if (tid == 0) {
+            d.log[lp] = LOG_DET | (reset ? 1u : 0u) << 8 | (recorded ? 1u : 0u) << 9 |
+                        (uint64_t)(recorded ? n_det : 0u) << 32;
+            d.log[lp + 1] = 0;
+          }
+          for (uint32_t k = tid; k < DW; k += kThreads) d.log[lp + 2 + k] = xa[k] & destab_mask(k, n);
+          if (reset) log_mask(lp + 2 + DW, [&](uint32_t w) { return Z[(size_t)a * RW + w]; });
+          lp += 2 + (reset ? 2u : 1u) * DW;
+        } else if (op != D_M) {
+          rows_to_lds(s_rows2, 1, [&](uint32_t w) { return ld(Z + (size_t)a * RW + w); }, true);
+        }
         __syncthreads();
         const uint32_t ns = uni(s_cnt[0]);
         uint32_t g = 0, cpar = 0;
@@ -543,7 +651,7 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
         uint64_t e0 = 0, e1 = 0;
         auto e_word = [&](uint32_t w) { return w == w0 ? e0 : w == w0 + 1 ? e1 : Ecur[w]; };
         uint32_t mine = 0;
-        for (uint32_t w = w0; w < w1; ++w) {
+        for (uint32_t w = w0; !LOG && w < w1; ++w) {
           uint64_t e = 0;
           uint32_t j = 0;
           for (; j + 4 <= ns; j += 4) {   // four independent loads in flight
@@ -577,7 +685,18 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
         }
         e_c = cpar ^ ((G & 3u) == 2u ? 1u : 0u);
         total = uni(total);
-        if (op != D_R) {
+        if (LOG && op != D_R) {
+          // The list comes from the replay kernel's rows of E.
+          if (tid == 0) {
+            d.rec_var[nrec] = -1;
+            d.rec_c[nrec] = e_c;
+            d.rec_off[nrec] = 0;
+            d.rec_len[nrec] = 0;
+            d.rec_det[nrec] = (int32_t)n_det;
+          }
+          ++n_det;
+          ++nrec;
+        } else if (op != D_R) {
           // The ascending list of E's set bits (each thread its own words).
           const bool fits = (uint64_t)listu + total <= d.list_cap;
           if (fits) {
@@ -604,7 +723,7 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
         // Reset (R, MR): X^e on qubit a adds e to the stabilizer rows with z_a.
         if (op != D_M) {
           const uint32_t nr = s_cnt[1];
-          for (uint32_t w = w0; w < w1; ++w) {
+          for (uint32_t w = w0; !LOG && w < w1; ++w) {
             const uint64_t e = e_word(w);
             if (!e) continue;
             uint32_t j = 0;
@@ -635,6 +754,211 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
     d.status[3] = overflow;
     d.status[4] = nloc;
     d.status[5] = nrec;
+    d.status[6] = (uint32_t)lp;
+    d.status[7] = (uint32_t)(lp >> 32);
+    d.status[8] = (uint32_t)snp;
+    d.status[9] = (uint32_t)(snp >> 32);
+    d.status[10] = n_det;
+  }
+}
+
+// ---- Replay of the log over the phase rows ---------------------------------
+//
+// The tableau never depends on the phases (Fact 2), so the logged pass can
+// run ahead and the phase rows can be rebuilt afterwards from the log.  Each
+// workgroup owns K consecutive 64-bit words of every phase row (P is n x W
+// words; its slice, n x K words, lives in LDS) and applies the whole log to
+// its slice; slices never interact.  A determined recorded outcome's words
+// go to row `det` of E (n_det x W words) for the list kernels.
+struct ReplayArgs {
+  const uint64_t* log;
+  uint64_t log_words;
+  const uint64_t* snap;
+  uint64_t* E;          // [n_det][W]
+  uint32_t n, DW, K, W;
+};
+
+constexpr uint32_t kReplayThreads = 1024;
+constexpr size_t kReplayStaticLds = 20 * 1024;   // at least the replay kernel's static LDS
+
+__global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
+  extern __shared__ uint64_t s_P[];   // [n][K]
+  __shared__ uint32_t s_rows[kMaxQubits], s_rows2[kMaxQubits];
+  __shared__ uint32_t s_cnt[2];
+  __shared__ uint64_t s_part[kReplayThreads];
+  __shared__ uint64_t s_E[64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  const uint32_t n = r.n, DW = r.DW, K = r.K;
+  const uint32_t w_lo = blockIdx.x * K, Ks = min(K, r.W - w_lo);   // this slice: words [w_lo, w_lo + Ks)
+  for (uint32_t i = tid; i < n * K; i += kReplayThreads) s_P[i] = 0;
+
+  // Wave `wv` lists the set bits of a logged mask (DW words at m) into dst.
+  auto list = [&](uint32_t wv, const uint64_t* m, uint32_t* dst, uint32_t slot) {
+    if (wave == wv) {
+      const uint64_t mw = lane < DW ? m[lane] : 0ull;
+      uint32_t cnt = 0;
+      for (uint32_t k = 0; k < DW; ++k) {
+        const uint64_t x = readlane64(mw, k);
+        if ((x >> lane) & 1u) dst[cnt + (uint32_t)__builtin_popcountll(x & ((1ull << lane) - 1))] = k * 64 + lane;
+        cnt += (uint32_t)__builtin_popcountll(x);
+      }
+      if (lane == 0) s_cnt[slot] = cnt;
+    }
+  };
+  // Rows dst[0..nr) of the slice ^= v(k), over (row, word) pairs.
+  auto xor_rows = [&](const uint32_t* rows, uint32_t nr, auto v) {
+    for (uint32_t i = tid; i < nr * Ks; i += kReplayThreads) {
+      const uint32_t row = rows[i / Ks], k = i % Ks;
+      s_P[row * K + k] ^= v(k);
+    }
+  };
+  __syncthreads();
+
+  for (uint64_t lp = 0; lp < r.log_words;) {
+    const uint64_t h0 = r.log[lp], h1 = r.log[lp + 1];
+    const uint32_t kind = (uint32_t)h0 & 0xFFu;
+    const uint64_t* m = r.log + lp + 2;
+    if (kind == LOG_FAULT) {
+      const uint32_t fk = ((uint32_t)h0 >> 8) & 0xFu, lg = ((uint32_t)h0 >> 12) & 0xFu, nq = ((uint32_t)h0 >> 16) & 0xFu;
+      const uint32_t nv = (uint32_t)(h0 >> 32), v0 = (uint32_t)h1;
+      const uint64_t off = r.log[lp + 2];
+      lp += 3;
+      // One wave per variable word of the slice that the instruction covers;
+      // lane l takes variable 64 vw + l, builds its anticommuting-row mask
+      // from the snapshots, and the transpose gives each row's bits.
+      const uint32_t vw0 = max(v0 >> 6, w_lo), vw1 = min((v0 + nv - 1) >> 6, w_lo + Ks - 1);
+      for (uint32_t vw = vw0 + wave; vw <= vw1 && vw0 <= vw1; vw += kReplayThreads / 64) {
+        const uint32_t v = vw * 64 + lane;
+        bool xf = false, zf = false;
+        const uint64_t* sx = r.snap;
+        if (v >= v0 && v < v0 + nv) {
+          const uint32_t rel = v - v0, item = rel >> lg, b = rel & ((1u << lg) - 1u);
+          xf = fk == F_X || fk == F_Y || ((fk == F_DEP1 || fk == F_DEP2) && !(b & 1u));
+          zf = fk == F_Z || fk == F_Y || ((fk == F_DEP1 || fk == F_DEP2) && (b & 1u));
+          sx = r.snap + off + ((uint64_t)item * nq + (b >= 2 ? 1u : 0u)) * 2u * DW;
+        }
+        for (uint32_t k = 0; k < DW; ++k) {
+          uint64_t col = 0;
+          if (xf) col ^= sx[DW + k];   // an X fault flips the rows with z
+          if (zf) col ^= sx[k];        // a Z fault the rows with x
+          if (__ballot(col != 0) == 0) continue;
+          const uint64_t out = transpose64(col, lane);
+          const uint32_t row = k * 64 + lane;
+          if (out && row < n) s_P[row * K + (vw - w_lo)] |= out;
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+    const uint32_t flags = ((uint32_t)h0 >> 8) & 0xFFu, hi = (uint32_t)(h0 >> 32);
+    if (kind == LOG_RAND) {
+      const bool reset = flags & 1u;
+      const uint32_t p = hi, var = (uint32_t)h1;
+      list(0, m, s_rows, 0);
+      if (reset) list(1, m + DW, s_rows2, 1);
+      lp += 2 + (reset ? 2u : 1u) * DW;
+      __syncthreads();
+      xor_rows(s_rows, s_cnt[0], [&](uint32_t k) { return s_P[p * K + k]; });   // row p itself is not in the list
+      __syncthreads();
+      // Row p becomes the fresh variable (a reset then removes it again);
+      // a reset adds it to the other rows with z_a.
+      const bool in = (var >> 6) >= w_lo && (var >> 6) < w_lo + Ks;
+      const uint32_t vk = (var >> 6) - w_lo;
+      const uint64_t vb = 1ull << (var & 63);
+      for (uint32_t k = tid; k < Ks; k += kReplayThreads) s_P[p * K + k] = (!reset && in && k == vk) ? vb : 0ull;
+      if (reset && in)
+        for (uint32_t j = tid; j < s_cnt[1]; j += kReplayThreads)
+          if (s_rows2[j] != p) s_P[s_rows2[j] * K + vk] ^= vb;
+      __syncthreads();
+      continue;
+    }
+    if (kind == LOG_DET) {
+      const bool reset = flags & 1u, recorded = flags & 2u;
+      list(0, m, s_rows, 0);
+      if (reset) list(1, m + DW, s_rows2, 1);
+      lp += 2 + (reset ? 2u : 1u) * DW;
+      __syncthreads();
+      // E = XOR of the selected rows: per (row group, word) partial sums, then per word.
+      const uint32_t G = kReplayThreads / K, g = tid / K, k = tid % K, ns = s_cnt[0];
+      if (g < G) {
+        uint64_t e = 0;
+        if (k < Ks)
+          for (uint32_t j = g; j < ns; j += G) e ^= s_P[s_rows[j] * K + k];
+        s_part[tid] = e;
+      }
+      __syncthreads();
+      if (tid < Ks) {
+        uint64_t e = 0;
+        for (uint32_t gg = 0; gg < G; ++gg) e ^= s_part[gg * K + tid];
+        s_E[tid] = e;
+        if (recorded) r.E[(size_t)hi * r.W + w_lo + tid] = e;
+      }
+      __syncthreads();
+      if (reset) {
+        xor_rows(s_rows2, s_cnt[1], [&](uint32_t kk) { return s_E[kk]; });
+        __syncthreads();
+      }
+      continue;
+    }
+    // LOG_FB_RAND / LOG_FB_DET
+    list(0, m, s_rows, 0);
+    lp += 2 + DW;
+    if (kind == LOG_FB_DET && tid < Ks) s_E[tid] = r.E[(size_t)hi * r.W + w_lo + tid];
+    __syncthreads();
+    if (kind == LOG_FB_DET) {
+      xor_rows(s_rows, s_cnt[0], [&](uint32_t kk) { return s_E[kk]; });
+    } else if ((hi >> 6) >= w_lo && (hi >> 6) < w_lo + Ks) {
+      for (uint32_t j = tid; j < s_cnt[0]; j += kReplayThreads) s_P[s_rows[j] * K + ((hi >> 6) - w_lo)] ^= 1ull << (hi & 63);
+    }
+    __syncthreads();
+  }
+}
+
+// Index lists of the determined recorded outcomes from their rows of E:
+// one workgroup per outcome counts its bits, the host scans the counts, and
+// a second pass writes each row's set bits in ascending order.
+constexpr uint32_t kListThreads = 256;
+
+__global__ void __launch_bounds__(kListThreads) count_kernel(const uint64_t* E, uint32_t W, uint32_t* counts) {
+  __shared__ uint32_t s_sum[kListThreads / 64];
+  const uint64_t* row = E + (size_t)blockIdx.x * W;
+  uint32_t c = 0;
+  for (uint32_t w = threadIdx.x; w < W; w += kListThreads) c += (uint32_t)__builtin_popcountll(row[w]);
+  for (uint32_t off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63u) == 0) s_sum[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (uint32_t i = 0; i < kListThreads / 64; ++i) t += s_sum[i];
+    counts[blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kListThreads) write_lists_kernel(const uint64_t* E, uint32_t W, const uint32_t* offsets,
+                                                                   uint32_t* list) {
+  __shared__ uint32_t s_scan[kListThreads / 64];
+  const uint64_t* row = E + (size_t)blockIdx.x * W;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  const uint32_t per = (W + kListThreads - 1) / kListThreads;
+  const uint32_t w0 = min(W, tid * per), w1 = min(W, w0 + per);
+  uint32_t mine = 0;
+  for (uint32_t w = w0; w < w1; ++w) mine += (uint32_t)__builtin_popcountll(row[w]);
+  uint32_t incl = mine;
+  for (uint32_t off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) s_scan[wave] = incl;
+  __syncthreads();
+  uint32_t before = 0;
+  for (uint32_t i = 0; i < wave; ++i) before += s_scan[i];
+  uint32_t pos = offsets[blockIdx.x] + before + incl - mine;
+  for (uint32_t w = w0; w < w1; ++w) {
+    uint64_t e = row[w];
+    while (e) {
+      list[pos++] = w * 64 + (uint32_t)__builtin_ctzll(e);
+      e &= e - 1;
+    }
   }
 }
 
@@ -725,18 +1049,41 @@ DevProgram compile(const sp_circuit& c) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Log and snapshot words the logged pass can need at most (DW words per mask).
+void log_bounds(const DevProgram& P, uint32_t DW, uint64_t* log_words, uint64_t* snap_words) {
+  uint64_t lw = 0, sw = 0;
+  for (size_t pc = 0; pc < P.words.size();) {
+    const uint32_t hdr = P.words[pc], op = hdr & 0xFFu, cnt = hdr >> 8;
+    if (op == D_FAULT) {
+      const uint32_t kind = P.words[pc + 1] >> 28;
+      lw += 3;
+      sw += (uint64_t)cnt * (kind == F_DEP2 ? 2u : 1u) * 2u * DW;
+    } else if (op == D_M || op == D_R || op == D_MR) {
+      lw += (uint64_t)cnt * (2 + 2ull * DW);
+    } else if (op == D_FB) {
+      lw += (uint64_t)cnt * (2 + (uint64_t)DW);
+    }
+    pc += 1 + (size_t)cnt * (op == D_FB ? 2u : 1u);
+  }
+  *log_words = lw;
+  *snap_words = sw;
+}
+
 struct InitLayout {
-  size_t ops, X, Z, P, E, loc, rec_var, rec_off, rec_len, rec_c, status, list, total;
-  uint32_t RW, W, list_cap;
+  size_t ops, X, Z, P, E, loc, rec_var, rec_off, rec_len, rec_c, rec_det, status, log, snap, list, total;
+  uint32_t RW, W, DW, list_cap;
 };
 
-// The buffer layout; the index list takes whatever the buffer has left
-// (at least list_min entries).
-InitLayout layout(const sp_circuit& c, const DevProgram& P, size_t list_min, size_t budget) {
+// The buffer layout.  One pass: the index list takes whatever the buffer has
+// left (at least `tail` entries).  Two passes (no phase rows here): the log
+// and snapshots, then `tail` bytes for the rows of E, the list counts and
+// offsets and the lists, or whatever the buffer has left.
+InitLayout layout(const sp_circuit& c, const DevProgram& P, bool two_pass, size_t tail, size_t budget) {
   InitLayout L{};
   const uint32_t n = c.n_qubits;
   L.RW = std::max<uint32_t>(1, (2 * n + 63) / 64);
   L.W = (uint32_t)std::max<uint64_t>(1, (P.max_vars + 64) / 64);
+  L.DW = std::max<uint32_t>(1, (n + 63) / 64);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -746,24 +1093,51 @@ InitLayout layout(const sp_circuit& c, const DevProgram& P, size_t list_min, siz
   L.ops = take(4 * P.words.size());
   L.X = take(8ull * n * L.RW);
   L.Z = take(8ull * n * L.RW);
-  L.P = take(8ull * n * L.W);
-  L.E = take(16ull * L.W);
+  if (!two_pass) {
+    L.P = take(8ull * n * L.W);
+    L.E = take(16ull * L.W);
+  }
   L.loc = take(4ull * P.n_locs);
   L.rec_var = take(4ull * P.n_rec);
   L.rec_off = take(4ull * P.n_rec);
   L.rec_len = take(4ull * P.n_rec);
   L.rec_c = take(4ull * P.n_rec);
+  L.rec_det = take(4ull * P.n_rec);
   L.status = take(64);
-  L.list = off;
-  size_t cap = list_min;
-  if (budget > off + 4 * list_min) cap = std::min<size_t>((budget - off) / 4, 0xFFFFFFFFull);
-  L.list_cap = (uint32_t)cap;
-  L.total = align256(off + 4 * cap);
+  if (two_pass) {
+    uint64_t lw = 0, sw = 0;
+    log_bounds(P, L.DW, &lw, &sw);
+    L.log = take(8 * lw);
+    L.snap = take(8 * sw);
+  }
+  L.list = off;   // one pass: the lists; two passes: the rows of E and what follows them
+  const size_t unit = two_pass ? 1 : 4;
+  size_t room = tail;
+  if (budget > off + unit * tail) room = std::min<size_t>((budget - off) / unit, two_pass ? SIZE_MAX : 0xFFFFFFFFull);
+  L.list_cap = (uint32_t)std::min<size_t>(room, 0xFFFFFFFFull);
+  L.total = align256(off + unit * room);
   return L;
 }
 
-// Default index-list room: the bound, capped at 2^26 entries (256 MiB).
-size_t default_list(const DevProgram& P) { return (size_t)std::min<uint64_t>(P.list_bound, 1ull << 26); }
+// Default room after the fixed part.  One pass: index-list entries (the
+// bound, at most 2^26).  Two passes: bytes for the rows of E of every
+// recorded outcome and their lists, at most 1 GiB; a call that needs more
+// says how much.
+size_t default_tail(const DevProgram& P, bool two_pass) {
+  if (!two_pass) return (size_t)std::min<uint64_t>(P.list_bound, 1ull << 26);
+  const uint64_t W = std::max<uint64_t>(1, (P.max_vars + 64) / 64);
+  const uint64_t need = (uint64_t)P.n_rec * (8 * W + 8) + 4 * std::min<uint64_t>(P.list_bound, 1ull << 26) + 1024;
+  return (size_t)std::min<uint64_t>(need, 1ull << 30);
+}
+
+// Two passes pay when the phase rows are large: the one-pass kernel updates
+// them from one CU, the replay from every CU.
+bool pick_two_pass(const sp_circuit& c, const DevProgram& P, int mode) {
+  if (mode == SP_INIT_ONE_PASS) return false;
+  if (mode == SP_INIT_TWO_PASS) return true;
+  const uint64_t W = (P.max_vars + 64) / 64;
+  return (uint64_t)c.n_qubits * W * 8 > (32ull << 20);
+}
 
 #define HIP_TRY(expr)                                                                           \
   do {                                                                                          \
@@ -777,117 +1151,219 @@ int check_circuit(const sp_circuit* c) {
   return SP_OK;
 }
 
+// Launches the tableau pass (one or logged), the tableau in LDS when it fits.
+template <bool LOG>
+int launch_init(const InitDev& d, uint32_t n, uint32_t RW, hipStream_t s) {
+  int dev = 0, lds_max = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const size_t tab_bytes = 16ull * n * RW;
+  if (tab_bytes + kStaticLds <= (size_t)lds_max) {
+    if (tab_bytes > 64 * 1024)
+      HIP_TRY(hipFuncSetAttribute((const void*)init_kernel<true, LOG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)tab_bytes));
+    hipLaunchKernelGGL((init_kernel<true, LOG>), dim3(1), dim3(kThreads), tab_bytes, s, d);
+  } else {
+    hipLaunchKernelGGL((init_kernel<false, LOG>), dim3(1), dim3(kThreads), 0, s, d);
+  }
+  HIP_TRY(hipGetLastError());
+  return SP_OK;
+}
+
+int symbolize_device(const sp_circuit& c, int outputs, int mode, void* d_work, size_t work_bytes, hipStream_t s,
+                     sp_model** out) {
+  const DevProgram P = compile(c);
+  if (P.max_vars >= (1ull << 24)) return set_error(SP_E_LIMIT, "more than 2^24 variables");
+  if (P.n_locs != c.n_locs || P.n_rec != c.n_meas) return set_error(SP_E_INVALID, "inconsistent circuit");
+  const bool two = pick_two_pass(c, P, mode);
+  const InitLayout L = layout(c, P, two, 0, work_bytes);
+  if (L.total > work_bytes)
+    return set_error(SP_E_INVALID, "work buffer of " + std::to_string(work_bytes) + " bytes, need at least " +
+                                       std::to_string(L.total));
+  uint8_t* base = (uint8_t*)d_work;
+  HIP_TRY(hipMemsetAsync(base, 0, L.list, s));
+  if (!P.words.empty()) HIP_TRY(hipMemcpyAsync(base + L.ops, P.words.data(), 4 * P.words.size(), hipMemcpyHostToDevice, s));
+  InitDev d{};
+  d.ops = (const uint32_t*)(base + L.ops);
+  d.n_words = (uint32_t)P.words.size();
+  d.n = c.n_qubits;
+  d.RW = L.RW;
+  d.W = L.W;
+  d.X = (uint64_t*)(base + L.X);
+  d.Z = (uint64_t*)(base + L.Z);
+  d.loc_var0 = (int32_t*)(base + L.loc);
+  d.rec_var = (int32_t*)(base + L.rec_var);
+  d.rec_off = (uint32_t*)(base + L.rec_off);
+  d.rec_len = (uint32_t*)(base + L.rec_len);
+  d.rec_c = (uint32_t*)(base + L.rec_c);
+  d.rec_det = (int32_t*)(base + L.rec_det);
+  d.status = (uint32_t*)(base + L.status);
+  if (two) {
+    d.log = (uint64_t*)(base + L.log);
+    d.snap = (uint64_t*)(base + L.snap);
+    if (int rc = launch_init<true>(d, c.n_qubits, L.RW, s)) return rc;
+  } else {
+    d.P = (uint64_t*)(base + L.P);
+    d.E = (uint64_t*)(base + L.E);
+    d.list = (uint32_t*)(base + L.list);
+    d.list_cap = L.list_cap;
+    if (int rc = launch_init<false>(d, c.n_qubits, L.RW, s)) return rc;
+  }
+
+  uint32_t status[11] = {};
+  std::vector<int32_t> loc_var0(c.n_locs), rec_var(c.n_meas), rec_det(c.n_meas);
+  std::vector<uint32_t> rec_off(c.n_meas), rec_len(c.n_meas), rec_c(c.n_meas);
+  HIP_TRY(hipMemcpyAsync(status, d.status, sizeof status, hipMemcpyDeviceToHost, s));
+  if (c.n_locs) HIP_TRY(hipMemcpyAsync(loc_var0.data(), d.loc_var0, 4ull * c.n_locs, hipMemcpyDeviceToHost, s));
+  if (c.n_meas) {
+    HIP_TRY(hipMemcpyAsync(rec_var.data(), d.rec_var, 4ull * c.n_meas, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(rec_off.data(), d.rec_off, 4ull * c.n_meas, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(rec_len.data(), d.rec_len, 4ull * c.n_meas, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(rec_c.data(), d.rec_c, 4ull * c.n_meas, hipMemcpyDeviceToHost, s));
+    if (two) HIP_TRY(hipMemcpyAsync(rec_det.data(), d.rec_det, 4ull * c.n_meas, hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (status[4] != c.n_locs || status[5] != c.n_meas) return set_error(SP_E_DEVICE, "device Initialization incomplete");
+  std::vector<uint32_t> list;
+
+  if (!two) {
+    if (status[3])
+      return set_error(SP_E_LIMIT, "determined outcomes need more index-list room than the work buffer has (" +
+                                       std::to_string(L.list_cap) + " entries); at most " +
+                                       std::to_string(layout(c, P, false, (size_t)std::min<uint64_t>(P.list_bound, 0xFFFFFFFFull), 0).total) +
+                                       " bytes suffice");
+    list.resize(status[2]);
+    if (status[2]) {
+      HIP_TRY(hipMemcpyAsync(list.data(), base + L.list, 4ull * status[2], hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+  } else {
+    // Replay the log over the phase rows, a slice of K words per workgroup.
+    const uint64_t log_words = (uint64_t)status[6] | (uint64_t)status[7] << 32;
+    const uint32_t n_vars = status[0], n_det = status[10];
+    const uint32_t Wu = std::max<uint32_t>(1, (n_vars + 63) / 64);   // words of the phase rows in use
+    // After the fixed part: rows of E, then counts and offsets, then the lists.
+    const size_t e_off = L.list, cnt_off = align256(e_off + 8ull * n_det * Wu), ofs_off = align256(cnt_off + 4ull * n_det);
+    const size_t lst_off = align256(ofs_off + 4ull * n_det);
+    if (lst_off > work_bytes)
+      return set_error(SP_E_LIMIT, "the replay needs a work buffer of at least " + std::to_string(lst_off) +
+                                       " bytes plus room for the index lists");
+    uint64_t* E = (uint64_t*)(base + e_off);
+    if (log_words) {   // also with no variables: it writes every determined outcome's (empty) row
+      int dev = 0, lds_max = 0;
+      HIP_TRY(hipGetDevice(&dev));
+      HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+      const size_t n = std::max<uint32_t>(c.n_qubits, 1);
+      const uint32_t K = (uint32_t)std::max<size_t>(1, std::min<size_t>(64, ((size_t)lds_max - kReplayStaticLds) / (8 * n)));
+      ReplayArgs ra{};
+      ra.log = d.log;
+      ra.log_words = log_words;
+      ra.snap = d.snap;
+      ra.E = E;
+      ra.n = c.n_qubits;
+      ra.DW = L.DW;
+      ra.K = K;
+      ra.W = Wu;
+      const size_t lds = 8 * n * K;
+      if (lds > 64 * 1024)
+        HIP_TRY(hipFuncSetAttribute((const void*)replay_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      hipLaunchKernelGGL(replay_kernel, dim3((Wu + K - 1) / K), dim3(kReplayThreads), lds, s, ra);
+      HIP_TRY(hipGetLastError());
+    }
+    // Lists of the determined recorded outcomes.
+    std::vector<uint32_t> counts(n_det), offsets(n_det);
+    if (n_det) {
+      uint32_t* d_counts = (uint32_t*)(base + cnt_off);
+      uint32_t* d_offsets = (uint32_t*)(base + ofs_off);
+      hipLaunchKernelGGL(count_kernel, dim3(n_det), dim3(kListThreads), 0, s, (const uint64_t*)E, Wu, d_counts);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(counts.data(), d_counts, 4ull * n_det, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      uint64_t total = 0;
+      for (uint32_t i = 0; i < n_det; ++i) {
+        offsets[i] = (uint32_t)total;
+        total += counts[i];
+        if (total > 0xFFFFFFFFull) return set_error(SP_E_LIMIT, "more than 2^32 list entries");
+      }
+      if (lst_off + 4 * total > work_bytes)
+        return set_error(SP_E_LIMIT, "the replay needs a work buffer of at least " +
+                                         std::to_string(align256(lst_off + 4 * total)) + " bytes");
+      list.resize(total);
+      if (total) {
+        HIP_TRY(hipMemcpyAsync(d_offsets, offsets.data(), 4ull * n_det, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(write_lists_kernel, dim3(n_det), dim3(kListThreads), 0, s, (const uint64_t*)E, Wu,
+                           (const uint32_t*)d_offsets, (uint32_t*)(base + lst_off));
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(list.data(), base + lst_off, 4ull * total, hipMemcpyDeviceToHost, s));
+      }
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+    for (uint32_t k = 0; k < c.n_meas; ++k)
+      if (rec_var[k] < 0) {
+        if (rec_det[k] < 0 || (uint32_t)rec_det[k] >= n_det) return set_error(SP_E_DEVICE, "bad outcome record");
+        rec_off[k] = offsets[rec_det[k]];
+        rec_len[k] = counts[rec_det[k]];
+      }
+  }
+
+  std::vector<sp::Expr> outcomes(c.n_meas);
+  for (uint32_t k = 0; k < c.n_meas; ++k) {
+    sp::Expr& e = outcomes[k];
+    if (rec_var[k] >= 0) {
+      e.v.assign(1, (uint32_t)rec_var[k]);
+    } else {
+      e.c = (uint8_t)(rec_c[k] & 1u);
+      if ((uint64_t)rec_off[k] + rec_len[k] > list.size()) return set_error(SP_E_DEVICE, "bad outcome list");
+      e.v.assign(list.begin() + rec_off[k], list.begin() + rec_off[k] + rec_len[k]);
+    }
+  }
+  *out = sp::assemble_model(c, outputs, std::move(loc_var0), status[0], status[1], outcomes);
+  return SP_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int sp_symbolize_device_work_bytes(const sp_circuit* circuit, size_t* bytes) {
+int sp_symbolize_device_work_bytes_mode(const sp_circuit* circuit, int mode, size_t* bytes) {
   if (!circuit || !bytes) return set_error(SP_E_INVALID, "null argument");
+  if (mode < SP_INIT_AUTO || mode > SP_INIT_TWO_PASS) return set_error(SP_E_INVALID, "unknown mode");
   if (int rc = check_circuit(circuit)) return rc;
   try {
     const DevProgram P = compile(*circuit);
-    *bytes = layout(*circuit, P, default_list(P), 0).total;
+    const bool two = pick_two_pass(*circuit, P, mode);
+    *bytes = layout(*circuit, P, two, default_tail(P, two), 0).total;
   } catch (const std::bad_alloc&) {
     return set_error(SP_E_NOMEM, "out of host memory");
   }
   return SP_OK;
 }
 
-int sp_symbolize_device(const sp_circuit* circuit, int outputs, void* d_work, size_t work_bytes, void* stream,
-                        sp_model** out) {
+int sp_symbolize_device_work_bytes(const sp_circuit* circuit, size_t* bytes) {
+  return sp_symbolize_device_work_bytes_mode(circuit, SP_INIT_AUTO, bytes);
+}
+
+int sp_symbolize_device_mode(const sp_circuit* circuit, int outputs, int mode, void* d_work, size_t work_bytes,
+                             void* stream, sp_model** out) {
   if (!circuit || !out || !d_work) return set_error(SP_E_INVALID, "null argument");
   *out = nullptr;
   if (outputs != SP_OUT_MEASUREMENTS && outputs != SP_OUT_DETECTORS)
     return set_error(SP_E_INVALID, "unknown outputs " + std::to_string(outputs));
+  if (mode < SP_INIT_AUTO || mode > SP_INIT_TWO_PASS) return set_error(SP_E_INVALID, "unknown mode");
   if (((uintptr_t)d_work & 255u) != 0) return set_error(SP_E_INVALID, "work buffer must be 256-byte aligned");
   if (int rc = check_circuit(circuit)) return rc;
-  const sp_circuit& c = *circuit;
   try {
-    const DevProgram P = compile(c);
-    if (P.max_vars >= (1ull << 24)) return set_error(SP_E_LIMIT, "more than 2^24 variables");
-    if (P.n_locs != c.n_locs || P.n_rec != c.n_meas) return set_error(SP_E_INVALID, "inconsistent circuit");
-    const InitLayout L = layout(c, P, 0, work_bytes);
-    if (L.total > work_bytes)
-      return set_error(SP_E_INVALID, "work buffer of " + std::to_string(work_bytes) + " bytes, need at least " +
-                                         std::to_string(L.total));
-    hipStream_t s = (hipStream_t)stream;
-    uint8_t* base = (uint8_t*)d_work;
-    HIP_TRY(hipMemsetAsync(base, 0, L.list, s));
-    if (!P.words.empty()) HIP_TRY(hipMemcpyAsync(base + L.ops, P.words.data(), 4 * P.words.size(), hipMemcpyHostToDevice, s));
-    InitDev d{};
-    d.ops = (const uint32_t*)(base + L.ops);
-    d.n_words = (uint32_t)P.words.size();
-    d.n = c.n_qubits;
-    d.RW = L.RW;
-    d.W = L.W;
-    d.X = (uint64_t*)(base + L.X);
-    d.Z = (uint64_t*)(base + L.Z);
-    d.P = (uint64_t*)(base + L.P);
-    d.E = (uint64_t*)(base + L.E);
-    d.loc_var0 = (int32_t*)(base + L.loc);
-    d.rec_var = (int32_t*)(base + L.rec_var);
-    d.rec_off = (uint32_t*)(base + L.rec_off);
-    d.rec_len = (uint32_t*)(base + L.rec_len);
-    d.rec_c = (uint32_t*)(base + L.rec_c);
-    d.list = (uint32_t*)(base + L.list);
-    d.list_cap = L.list_cap;
-    d.status = (uint32_t*)(base + L.status);
-    // The tableau goes to LDS when it fits beside the kernel's own arrays.
-    int dev = 0, lds_max = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t tab_bytes = 16ull * c.n_qubits * L.RW;
-    if (tab_bytes + kStaticLds <= (size_t)lds_max) {
-      if (tab_bytes > 64 * 1024)
-        HIP_TRY(hipFuncSetAttribute((const void*)init_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)tab_bytes));
-      hipLaunchKernelGGL(init_kernel<true>, dim3(1), dim3(kThreads), tab_bytes, s, d);
-    } else {
-      hipLaunchKernelGGL(init_kernel<false>, dim3(1), dim3(kThreads), 0, s, d);
-    }
-    HIP_TRY(hipGetLastError());
-
-    uint32_t status[6];
-    std::vector<int32_t> loc_var0(c.n_locs), rec_var(c.n_meas);
-    std::vector<uint32_t> rec_off(c.n_meas), rec_len(c.n_meas), rec_c(c.n_meas);
-    HIP_TRY(hipMemcpyAsync(status, d.status, sizeof status, hipMemcpyDeviceToHost, s));
-    if (c.n_locs) HIP_TRY(hipMemcpyAsync(loc_var0.data(), d.loc_var0, 4ull * c.n_locs, hipMemcpyDeviceToHost, s));
-    if (c.n_meas) {
-      HIP_TRY(hipMemcpyAsync(rec_var.data(), d.rec_var, 4ull * c.n_meas, hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(rec_off.data(), d.rec_off, 4ull * c.n_meas, hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(rec_len.data(), d.rec_len, 4ull * c.n_meas, hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(rec_c.data(), d.rec_c, 4ull * c.n_meas, hipMemcpyDeviceToHost, s));
-    }
-    HIP_TRY(hipStreamSynchronize(s));
-    if (status[3])
-      return set_error(SP_E_LIMIT, "determined outcomes need more index-list room than the work buffer has (" +
-                                       std::to_string(L.list_cap) + " entries); at most " +
-                                       std::to_string(layout(c, P, (size_t)std::min<uint64_t>(P.list_bound, 0xFFFFFFFFull), 0).total) +
-                                       " bytes suffice");
-    if (status[4] != c.n_locs || status[5] != c.n_meas) return set_error(SP_E_DEVICE, "device Initialization incomplete");
-    std::vector<uint32_t> list(status[2]);
-    if (status[2]) {
-      HIP_TRY(hipMemcpyAsync(list.data(), d.list, 4ull * status[2], hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-    }
-    std::vector<sp::Expr> outcomes(c.n_meas);
-    for (uint32_t k = 0; k < c.n_meas; ++k) {
-      sp::Expr& e = outcomes[k];
-      if (rec_var[k] >= 0) {
-        e.v.assign(1, (uint32_t)rec_var[k]);
-      } else {
-        e.c = (uint8_t)(rec_c[k] & 1u);
-        if ((uint64_t)rec_off[k] + rec_len[k] > list.size()) return set_error(SP_E_DEVICE, "bad outcome list");
-        e.v.assign(list.begin() + rec_off[k], list.begin() + rec_off[k] + rec_len[k]);
-      }
-    }
-    *out = sp::assemble_model(c, outputs, std::move(loc_var0), status[0], status[1], outcomes);
+    return symbolize_device(*circuit, outputs, mode, d_work, work_bytes, (hipStream_t)stream, out);
   } catch (const sp::Error& e) {
     return set_error(e.code, e.what());
   } catch (const std::bad_alloc&) {
     return set_error(SP_E_NOMEM, "out of host memory");
   }
-  return SP_OK;
+}
+
+int sp_symbolize_device(const sp_circuit* circuit, int outputs, void* d_work, size_t work_bytes, void* stream,
+                        sp_model** out) {
+  return sp_symbolize_device_mode(circuit, outputs, SP_INIT_AUTO, d_work, work_bytes, stream, out);
 }
 
 }  // extern "C"

@@ -30,8 +30,11 @@ def _say(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def _device_model(text, outputs="measurements"):
-    return sp.Model(text, outputs=outputs, init="device")
+def _device_model(text, outputs="measurements", mode="auto"):
+    return sp.Model(text, outputs=outputs, init="device", init_mode=mode)
+
+
+MODES = ["one_pass", "two_pass"]
 
 
 def _same_model(a, b):
@@ -54,13 +57,14 @@ def _evaluate(M, c, b):
     return ((M.astype(np.int64) @ b.astype(np.int64)) + c) % 2
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("name", ["fig1.txt", "bell.txt"])
-def test_paper_examples_on_device(name):
+def test_paper_examples_on_device(name, mode):
     """The paper's printed outcome expressions (Fig. 1 and the Bell
     example), built on the GPU."""
     text, symbols, outcomes = example(name)
-    _say(f"device init {name}")
-    m = _device_model(text)
+    _say(f"device init {name} {mode}")
+    m = _device_model(text, mode=mode)
     M, c = m.export_dense()
     var_loc, var_bit = m.export_vars()
     col_of = {(int(l), int(b)): j for j, (l, b) in enumerate(zip(var_loc, var_bit))}
@@ -80,16 +84,17 @@ _SMALL = [("rep3", repetition_memory(3, 3, 1e-3, detectors=True)),
           ("random_feedback", random_clifford_circuit(11, 4, 40, feedback=True, detectors=True))]
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("outputs", ["measurements", "detectors"])
 @pytest.mark.parametrize("name,circ", _SMALL, ids=[n for n, _ in _SMALL])
-def test_device_model_equals_oracle_probing(name, circ, outputs):
+def test_device_model_equals_oracle_probing(name, circ, outputs, mode):
     """(M, c) of the device pass equal the oracle's outputs with one code
     bit set at a time (columns) and none set (c)."""
     if outputs == "detectors" and circ.n_detectors + circ.n_observables == 0:
         pytest.skip("no detectors")
     text = circ.text()
-    _say(f"device init probing {name} {outputs}")
-    m = _device_model(text, outputs)
+    _say(f"device init probing {name} {outputs} {mode}")
+    m = _device_model(text, outputs, mode)
     oc = oracle.Circuit(text, outputs=outputs)
     var_loc, var_bit = m.export_vars()
     zero = np.zeros(oc.n_locs, dtype=np.uint8)
@@ -105,8 +110,9 @@ def test_device_model_equals_oracle_probing(name, circ, outputs):
     assert np.array_equal(c, c0)
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("seed", range(40))
-def test_device_model_matches_oracle_on_random_circuits(seed):
+def test_device_model_matches_oracle_on_random_circuits(seed, mode):
     """Random noisy Clifford circuits with resets, feedback, detectors and
     observables: M b + c of the device model equals the oracle's outputs for
     random codes at every location (a location the device wrongly took as
@@ -117,7 +123,7 @@ def test_device_model_matches_oracle_on_random_circuits(seed):
     text = random_clifford_circuit(seed, n, n_ops, feedback=True, detectors=True).text()
     for outputs in ("measurements", "detectors"):
         oc = oracle.Circuit(text, outputs=outputs)
-        m = _device_model(text, outputs)
+        m = _device_model(text, outputs, mode)
         M, c = m.export_dense()
         mv = m.export_vars()
         kinds = oc.location_kinds()
@@ -137,9 +143,10 @@ _LARGE = [("surf5", lambda: surface_memory(5, 5, 1e-3, detectors=True)),
           ("random_feedback_64q", lambda: random_clifford_circuit(5, 64, 3000, feedback=True, detectors=True))]
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("outputs", ["measurements", "detectors"])
 @pytest.mark.parametrize("name,make", _LARGE, ids=[n for n, _ in _LARGE])
-def test_device_model_equals_host_model(name, make, outputs):
+def test_device_model_equals_host_model(name, make, outputs, mode):
     """Several tableau words per column, several phase words per row, many
     instructions split into runs: the device model is bit-identical to the
     host pass."""
@@ -147,19 +154,21 @@ def test_device_model_equals_host_model(name, make, outputs):
     if outputs == "detectors" and circ.n_detectors + circ.n_observables == 0:
         pytest.skip("no detectors")
     text = circ.text()
-    _say(f"device init vs host {name} {outputs}")
-    _same_model(_device_model(text, outputs), sp.Model(text, outputs=outputs))
+    _say(f"device init vs host {name} {outputs} {mode}")
+    _same_model(_device_model(text, outputs, mode), sp.Model(text, outputs=outputs))
 
 
-def test_surface_d15_detectors_device_model():
+@pytest.mark.parametrize("mode", MODES)
+def test_surface_d15_detectors_device_model(mode):
     """The served workload's circuit (surface d=15, 15 rounds, 449 qubits,
     p = 5e-3, detector outputs): device model equals the host model."""
     text = surface_memory(15, 15, "0.005", detectors=True).text()
     _say("device init surface d15 detectors")
-    _same_model(_device_model(text, "detectors"), sp.Model(text, outputs="detectors"))
+    _same_model(_device_model(text, "detectors", mode), sp.Model(text, outputs="detectors"))
 
 
-def test_max_qubits():
+@pytest.mark.parametrize("mode", MODES)
+def test_max_qubits(mode):
     """1024 qubits (the limit: 32 tableau words per column) with
     measurements, resets and faults on the highest qubits."""
     n = 1024
@@ -175,8 +184,8 @@ def test_max_qubits():
     lines.append("MR 1023 1022 0")
     lines.append("M " + " ".join(map(str, range(n))))
     text = "\n".join(lines) + "\n"
-    _say("device init 1024 qubits")
-    _same_model(_device_model(text), sp.Model(text))
+    _say(f"device init 1024 qubits {mode}")
+    _same_model(_device_model(text, mode=mode), sp.Model(text))
 
 
 def test_device_model_samples_equal_oracle():
@@ -193,11 +202,14 @@ def test_device_model_samples_equal_oracle():
     assert np.array_equal(got, want)
 
 
-def test_degenerate_circuits():
-    """No instructions, no measurements, only gates, only faults."""
-    for text in ["", "H 0\nS 1\nCX 0 1\n", "X_ERROR(0.1) 0 1 2\n", "M 0\n", "R 0 1\nM 1\n"]:
-        _say(f"device init degenerate {text!r}")
-        _same_model(_device_model(text), sp.Model(text))
+@pytest.mark.parametrize("mode", MODES)
+def test_degenerate_circuits(mode):
+    """No instructions, no measurements, only gates, only faults, determined
+    outcomes without any variable."""
+    for text in ["", "H 0\nS 1\nCX 0 1\n", "X_ERROR(0.1) 0 1 2\n", "M 0\n", "R 0 1\nM 1\n",
+                 "M 0 1\nM 0\nCX rec[-1] 1\nM 1\n"]:
+        _say(f"device init degenerate {text!r} {mode}")
+        _same_model(_device_model(text, mode=mode), sp.Model(text))
 
 
 def test_index_list_overflow_is_reported():
@@ -233,3 +245,13 @@ def test_index_list_overflow_is_reported():
         assert np.array_equal(cp, want_cp) and np.array_equal(ri[: d.nnz], want_ri)
     finally:
         L.sp_model_free(h)
+
+
+def test_two_pass_on_fig3c_n200():
+    """Fig. 3c at n = 200 (82,084 variables, phase rows of 1,283 words):
+    both passes give the host's model; the replay spans several workgroups."""
+    text = random_layered_circuit(200, seed=1, p_dep="0.001").text()
+    host = sp.Model(text)
+    for mode in MODES:
+        _say(f"fig3c n=200 device init {mode}")
+        _same_model(_device_model(text, mode=mode), host)
