@@ -40,8 +40,7 @@ def parse_args():
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
     ap.add_argument("--legs", default="rep,d15,outputs,init,fig3,mix,small,serving",
-                    help="comma list of the other workloads to run (rep, d15, outputs, init, fig3, mix, small, serving; "
-                         "fig3big, not in the default, runs Fig. 3c at n = 600 and 1000)")
+                    help="comma list of the other workloads to run (rep, d15, outputs, init, fig3, mix, small, serving)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -178,7 +177,7 @@ def main():
     legs = set() if args.no_extra else {x.strip() for x in args.legs.split(",") if x.strip()}
     if args.no_serving:
         legs.discard("serving")
-    unknown = legs - {"rep", "d15", "outputs", "init", "fig3", "fig3big", "mix", "small", "serving"}
+    unknown = legs - {"rep", "d15", "outputs", "init", "fig3", "mix", "small", "serving"}
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
         sys.exit(2)
@@ -188,8 +187,6 @@ def main():
             rec["extra"]["initialization_d15"] = init_leg(sp, torch, surface_memory)
         if "fig3" in legs:
             rec["extra"]["paper_fig3_layered_random"] = fig3_leg(sp, torch)
-        if "fig3big" in legs:
-            rec["extra"]["paper_fig3c_largest"] = fig3_big_leg(sp, torch)
         if "mix" in legs:
             rec["extra"]["batched_mix_64"] = batched_mix_leg(sp, torch)
         if "small" in legs:
@@ -281,24 +278,15 @@ def fig3_leg(sp, torch) -> dict:
     (the host pass grows about as n^3.5 on 3b/3c), then GPU time to generate
     10^4 samples (the paper's sampling metric) and 10^6 samples; circuits
     of more than 9,216 rows are sampled in row tiles.  n = 1000 is the
-    paper's largest size (3c there is in the 'fig3big' leg)."""
+    paper's largest size (3c: 2,000,000 fault variables)."""
     from workloads import random_layered_circuit
     res = {}
     sizes = [(100, ("3a", "3b", "3c")), (200, ("3a", "3b", "3c")), (400, ("3a", "3b", "3c")),
-             (700, ("3a", "3b")), (1000, ("3a", "3b"))]
+             (700, ("3a", "3b", "3c")), (1000, ("3a", "3b", "3c"))]
     for n, figs in sizes:
         for fig in figs:
             res[f"fig{fig}_n{n}"] = _fig3_case(sp, torch, random_layered_circuit, fig, n)
     return res
-
-
-def fig3_big_leg(sp, torch) -> dict:
-    """Fig. 3c at the paper's largest size, n = 1000 (2,000,000 fault
-    variables, 51,000 measurements): Initialization on the GPU only (about
-    a minute; the host pass would take hours), then sampling."""
-    from workloads import random_layered_circuit
-    return {"fig3c_n600": _fig3_case(sp, torch, random_layered_circuit, "3c", 600),
-            "fig3c_n1000": _fig3_case(sp, torch, random_layered_circuit, "3c", 1000)}
 
 
 _FIG3_KW = {"3a": {"cnot_pairs": 5}, "3b": {}, "3c": {"p_dep": "0.001"}}

@@ -210,7 +210,7 @@ int sp_symbolize_device(const sp_circuit* circuit, int outputs, void* d_work, si
  *                     LDS, and two small kernels turn the determined
  *                     outcomes' rows into index lists;
  *   SP_INIT_AUTO      two passes when the phase rows (n_qubits x
- *                     ceil((variables + 1)/64) words) exceed 32 MiB.
+ *                     ceil((variables + 1)/64) words) exceed 1 MiB.
  * The two-pass work buffer holds the log and, after it, the determined
  * recorded outcomes' rows and lists; sp_symbolize_device_work_bytes_mode
  * sizes that room for every recorded outcome, at most 1 GiB; when a call
