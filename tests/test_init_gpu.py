@@ -255,3 +255,43 @@ def test_two_pass_on_fig3c_n200():
     for mode in MODES:
         _say(f"fig3c n=200 device init {mode}")
         _same_model(_device_model(text, mode=mode), host)
+
+
+def test_two_pass_buffer_too_small_is_reported():
+    """Two passes with no room after the log for the determined outcomes'
+    rows: SP_E_LIMIT naming a size; with that size the call gives the host
+    pass's model (the same protocol the binding retries once)."""
+    text = surface_memory(5, 5, "0.01", detectors=True).text()
+    c = sp.Circuit(text)
+    L = _capi.lib()
+    two = _capi.SP_INIT_TWO_PASS
+    need = ctypes.c_size_t()
+    _capi.check(L.sp_symbolize_device_work_bytes_mode(c.handle, two, ctypes.byref(need)))
+    work = torch.zeros(need.value + 256, dtype=torch.uint8, device="cuda")
+    base = ctypes.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
+    h = ctypes.c_void_p()
+    assert L.sp_symbolize_device_mode(c.handle, 0, two, base, 256, None, ctypes.byref(h)) == _capi.SP_E_INVALID
+    fixed = int(re.search(r"need at least (\d+)", L.sp_last_error().decode()).group(1))
+    _say("two-pass buffer too small")
+    assert L.sp_symbolize_device_mode(c.handle, 0, two, base, fixed, None, ctypes.byref(h)) == _capi.SP_E_LIMIT
+    enough = int(re.search(r"at least (\d+) bytes", L.sp_last_error().decode()).group(1))
+    assert fixed < enough <= need.value
+    # the first figure covers the rows of E; the lists may name a larger one
+    rc = L.sp_symbolize_device_mode(c.handle, 0, two, base, enough, None, ctypes.byref(h))
+    if rc == _capi.SP_E_LIMIT:
+        enough = int(re.search(r"at least (\d+) bytes", L.sp_last_error().decode()).group(1))
+        assert enough <= need.value
+        rc = L.sp_symbolize_device_mode(c.handle, 0, two, base, enough, None, ctypes.byref(h))
+    _capi.check(rc)
+    try:
+        ref = sp.Model(text)
+        d = _capi.sp_dims()
+        _capi.check(L.sp_model_dims(h, ctypes.byref(d)))
+        assert (d.n_vars, d.nnz, d.n_meas) == (ref.dims.n_vars, ref.dims.nnz, ref.dims.n_meas)
+        cp = np.zeros(d.n_vars + 1, dtype=np.uint32)
+        ri = np.zeros(max(1, d.nnz), dtype=np.uint32)
+        _capi.check(L.sp_model_export_csc(h, cp.ctypes.data, ri.ctypes.data))
+        want_cp, want_ri = ref.export_csc()
+        assert np.array_equal(cp, want_cp) and np.array_equal(ri[: d.nnz], want_ri)
+    finally:
+        L.sp_model_free(h)
