@@ -84,3 +84,25 @@ def test_device_initialization_checks_arguments_before_device_work():
     assert L.sp_symbolize_device(big.handle, 0, fake, 1 << 30, None, ctypes.byref(h)) == E.SP_E_LIMIT
     assert b"1024 qubits" in L.sp_last_error()
     assert h.value is None
+
+
+def test_device_initialization_modes_checked_before_device_work():
+    import ctypes
+    import paper_2311_03906_amd as sp
+    L, E = sp.lib(), sp._capi
+    fake = ctypes.c_void_p(1 << 20)
+    h = ctypes.c_void_p()
+    c = sp.Circuit("H 0\nCX 0 1\nX_ERROR(0.1) 1\nM 0 1\n")
+    sizes = []
+    for mode in (E.SP_INIT_AUTO, E.SP_INIT_ONE_PASS, E.SP_INIT_TWO_PASS):
+        need = ctypes.c_size_t()
+        assert L.sp_symbolize_device_work_bytes_mode(c.handle, mode, ctypes.byref(need)) == 0
+        sizes.append(need.value)
+    assert sizes[0] == sizes[1]   # a tiny circuit runs in one pass
+    need = ctypes.c_size_t()
+    assert L.sp_symbolize_device_work_bytes_mode(c.handle, 3, ctypes.byref(need)) == E.SP_E_INVALID
+    assert L.sp_symbolize_device_mode(c.handle, 0, 3, fake, 1 << 30, None, ctypes.byref(h)) == E.SP_E_INVALID
+    assert L.sp_symbolize_device_mode(c.handle, 0, E.SP_INIT_TWO_PASS, fake, 256, None,
+                                      ctypes.byref(h)) == E.SP_E_INVALID
+    assert b"need at least" in L.sp_last_error()
+    assert h.value is None
