@@ -254,7 +254,8 @@ int sp_model_device_bytes(const sp_model* model, int path, size_t* bytes);
  * LDS slab (19,456 rows at most on gfx950 with room for 16 waves' event
  * queues).  A model of more than 9,216 rows (two workgroups' slabs per CU)
  * is stored as row tiles of 4,096 rows; each tile holds only the locations
- * that reach its rows, and sp_sample launches once per tile.  The draws are
+ * that reach its rows, and sp_sample samples every tile in one launch (the
+ * buffer then also holds a table of the tiles' descriptors).  The draws are
  * keyed by location, so the output is the same bit for bit whatever the
  * tiling.
  * Errors: SP_E_INVALID, SP_E_LIMIT (a tile does not fit the device's LDS,

@@ -35,6 +35,27 @@ struct LaunchArgs {
   uint32_t n_words, n_groups;
 };
 
+// One row tile of a model, as the tiled kernel reads it from device memory
+// (16-byte multiple, read with 16-byte scalar loads).
+struct alignas(16) TileRec {
+  DevModel m;
+  uint32_t row0;   // first output row of the tile
+  uint32_t pad[1];
+};
+
+// One launch over every row tile of a model: `tiles` is the model's tile
+// table, each tile gets n_groups groups of the same shot range.
+struct TiledArgs {
+  const TileRec* tiles;
+  uint64_t* out;
+  uint64_t ld;
+  uint64_t first_shot;
+  uint64_t shots;
+  uint32_t key0, key1;
+  uint32_t n_words, n_groups;
+  uint32_t n_tiles;
+};
+
 // A job inside a batched launch (device memory; 16-byte multiple so that
 // kernels read it with 16-byte scalar loads).
 struct alignas(16) BatchJob {
@@ -68,6 +89,8 @@ size_t lds_bytes(uint32_t n_meas, uint32_t words_per_group, uint32_t waves_per_g
 
 // Kernel launchers (sample.hip).
 int launch_sample(const LaunchArgs& a, int path, const sp_launch& L, hipStream_t s);
+// All row tiles in one launch; `rows_max` sizes the LDS slabs.
+int launch_sample_tiles(const TiledArgs& a, uint32_t rows_max, int path, const sp_launch& L, hipStream_t s);
 // Persistent schedule: `grid` workgroups take tasks from ctr until none is left.
 int launch_batch_persistent(const BatchJob* jobs, const BatchTask* tasks, uint32_t n_tasks, BatchCounters* ctr,
                             uint32_t n_meas_max, int path, const sp_launch& L, uint32_t grid, hipStream_t s);
@@ -87,6 +110,7 @@ int batch_grid(const sp_launch& L, uint32_t n_meas_max, int path, uint32_t* grid
 struct sp_dmodel {
   std::vector<sp::DevModel> tiles;
   std::vector<uint32_t> row0;
+  const sp::TileRec* d_tiles;   // the tile table in device memory (more than one tile), else null
   uint32_t n_meas;       // rows over all tiles
   uint32_t rows_max;     // rows of the largest tile
   uint32_t nb;           // Philox blocks per shot over all tiles

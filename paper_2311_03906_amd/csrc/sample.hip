@@ -35,6 +35,8 @@
 using sp::set_error;
 using sp::DevModel;
 using sp::LaunchArgs;
+using sp::TileRec;
+using sp::TiledArgs;
 using sp::BatchJob;
 using sp::BatchCounters;
 
@@ -495,6 +497,32 @@ __global__ void __launch_bounds__(1024) sample_kernel(LaunchArgs a) {
   process_group<R, DENSE>(a, slab, xcd_group(blockIdx.x, a.n_groups), tid, lane, wave, n_waves);
 }
 
+// Every row tile of one model in one launch.  The flat index group * n_tiles
+// + tile is spread over the XCDs like a single tile's groups, so each XCD
+// takes a run of consecutive words of every tile and all tiles advance
+// together (tiles of unequal cost then share every XCD); each workgroup
+// reads its tile's record from the table with scalar loads.
+template <int R, int DENSE>
+__global__ void __launch_bounds__(1024) sample_tiles_kernel(TiledArgs t) {
+  extern __shared__ uint64_t slab[];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  const uint32_t wave = uniform(tid >> 6), n_waves = blockDim.x >> 6;
+  const uint32_t f = xcd_group(blockIdx.x, t.n_tiles * t.n_groups);
+  const uint32_t ti = f % t.n_tiles;
+  const TileRec rec = load_uniform(t.tiles + ti);
+  LaunchArgs a;
+  a.m = rec.m;
+  a.out = t.out + (size_t)rec.row0 * t.ld;
+  a.ld = t.ld;
+  a.first_shot = t.first_shot;
+  a.shots = t.shots;
+  a.key0 = t.key0;
+  a.key1 = t.key1;
+  a.n_words = t.n_words;
+  a.n_groups = t.n_groups;
+  process_group<R, DENSE>(a, slab, f / t.n_tiles, tid, lane, wave, n_waves);
+}
+
 // Many jobs per launch, persistent schedule: workgroups take tasks (runs of
 // consecutive groups of one job) from a device counter until all are handed
 // out.  The workgroup that finishes last resets the counters, so the launch
@@ -658,9 +686,11 @@ struct TileLayout {
 struct Layout {
   std::vector<TileLayout> tiles;
   std::vector<HostBlocks> blocks;
-  size_t chans, total;
+  size_t chans, table, total;   // table: the TileRec array (more than one tile)
   uint32_t nch;
 };
+
+static_assert(sizeof(TileRec) % 16 == 0, "tile records are read with 16-byte loads");
 
 // tile_rows: 0 picks one tile up to kOneTileRowsMax rows, else tiles of
 // kTileRowsAuto rows; otherwise tiles of that many rows (a multiple of 64).
@@ -689,6 +719,8 @@ Layout plan(const sp_model& m, int path, uint32_t tile_rows) {
     if (path == SP_PATH_DENSE) off = align256(off + 8 * (size_t)m.n_vars * T.dense_words);
     L.tiles.push_back(T);
   }
+  L.table = off;
+  if (L.tiles.size() > 1) off = align256(off + sizeof(TileRec) * L.tiles.size());
   L.total = off;
   return L;
 }
@@ -700,6 +732,7 @@ Layout plan(const sp_model& m, int path, uint32_t tile_rows) {
   } while (0)
 
 using KernelFn = void (*)(LaunchArgs);
+using TilesFn = void (*)(TiledArgs);
 using PersistentFn = void (*)(const BatchJob*, const sp::BatchTask*, uint32_t, BatchCounters*);
 using FlatFn = void (*)(const BatchJob*, const uint32_t*, uint32_t);
 
@@ -709,6 +742,16 @@ KernelFn kernel_for(int path, uint32_t words_per_group) {
     case 1: return dense ? sample_kernel<1, 1> : sample_kernel<1, 0>;
     case 2: return dense ? sample_kernel<2, 1> : sample_kernel<2, 0>;
     case 4: return dense ? sample_kernel<4, 1> : sample_kernel<4, 0>;
+    default: return nullptr;
+  }
+}
+
+TilesFn tiles_for(int path, uint32_t words_per_group) {
+  const bool dense = path == SP_PATH_DENSE;
+  switch (words_per_group) {
+    case 1: return dense ? sample_tiles_kernel<1, 1> : sample_tiles_kernel<1, 0>;
+    case 2: return dense ? sample_tiles_kernel<2, 1> : sample_tiles_kernel<2, 0>;
+    case 4: return dense ? sample_tiles_kernel<4, 1> : sample_tiles_kernel<4, 0>;
     default: return nullptr;
   }
 }
@@ -748,6 +791,18 @@ int launch_sample(const LaunchArgs& a, int path, const sp_launch& L, hipStream_t
   if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
   if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k, dim3(a.n_groups), dim3(64 * L.waves_per_group), lds, s, a);
+  HIP_TRY(hipGetLastError());
+  return SP_OK;
+}
+
+int launch_sample_tiles(const TiledArgs& a, uint32_t rows_max, int path, const sp_launch& L, hipStream_t s) {
+  TilesFn k = tiles_for(path, L.words_per_group);
+  if (!k) return set_error(SP_E_INVALID, "words_per_group must be 1, 2 or 4");
+  const uint64_t grid = (uint64_t)a.n_tiles * a.n_groups;
+  if (grid > 0x7FFFFFFFull) return set_error(SP_E_LIMIT, "too many workgroups for one launch");
+  const size_t lds = lds_bytes(rows_max, L.words_per_group, L.waves_per_group, path);
+  if (lds > 64 * 1024) HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k, dim3((uint32_t)grid), dim3(64 * L.waves_per_group), lds, s, a);
   HIP_TRY(hipGetLastError());
   return SP_OK;
 }
@@ -897,10 +952,6 @@ int sp_model_upload_tiled(const sp_model* model, int path, uint32_t tile_rows, v
   } catch (const std::bad_alloc&) {
     return set_error(SP_E_NOMEM, "out of host memory");
   }
-  hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(hipMemcpyAsync(d_buf, host.data(), L.total, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));
-
   auto* dm = new (std::nothrow) sp_dmodel();
   if (!dm) return set_error(SP_E_NOMEM, "out of host memory");
   const uint8_t* base = (const uint8_t*)d_buf;
@@ -925,6 +976,23 @@ int sp_model_upload_tiled(const sp_model* model, int path, uint32_t tile_rows, v
   } catch (const std::bad_alloc&) {
     delete dm;
     return set_error(SP_E_NOMEM, "out of host memory");
+  }
+  dm->d_tiles = nullptr;
+  if (L.tiles.size() > 1) {
+    TileRec* rec = reinterpret_cast<TileRec*>(&host[L.table]);
+    for (size_t t = 0; t < L.tiles.size(); ++t) {
+      rec[t] = TileRec{};
+      rec[t].m = dm->tiles[t];
+      rec[t].row0 = dm->row0[t];
+    }
+    dm->d_tiles = (const TileRec*)(base + L.table);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(d_buf, host.data(), L.total, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete dm;
+    return set_error(SP_E_DEVICE, std::string("model upload: ") + hipGetErrorString(e));
   }
   dm->n_meas = model->n_meas;
   dm->rows_max = rows_max;
@@ -986,21 +1054,33 @@ int sp_sample(const sp_dmodel* dm, uint64_t seed, uint64_t first_shot, uint64_t 
   if (dev != dm->device) return set_error(SP_E_INVALID, "current device differs from the model's device");
   const sp_launch& L = dm->launch;
 
-  // One launch per row tile, each writing its own rows of the output.
-  for (size_t t = 0; t < dm->tiles.size(); ++t) {
+  const uint32_t n_groups = (uint32_t)((words + L.words_per_group - 1) / L.words_per_group);
+  if (dm->tiles.size() == 1) {
     LaunchArgs a;
-    a.m = dm->tiles[t];
-    a.out = d_out + (size_t)dm->row0[t] * ld_words;
+    a.m = dm->tiles[0];
+    a.out = d_out;
     a.ld = ld_words;
     a.first_shot = first_shot;
     a.shots = shots;
     a.key0 = (uint32_t)seed;
     a.key1 = (uint32_t)(seed >> 32);
     a.n_words = (uint32_t)words;
-    a.n_groups = (uint32_t)((words + L.words_per_group - 1) / L.words_per_group);
-    if (int rc = sp::launch_sample(a, dm->path, L, (hipStream_t)stream)) return rc;
+    a.n_groups = n_groups;
+    return sp::launch_sample(a, dm->path, L, (hipStream_t)stream);
   }
-  return SP_OK;
+  // Row tiles: one launch, each tile writing its own rows of the output.
+  TiledArgs a;
+  a.tiles = dm->d_tiles;
+  a.out = d_out;
+  a.ld = ld_words;
+  a.first_shot = first_shot;
+  a.shots = shots;
+  a.key0 = (uint32_t)seed;
+  a.key1 = (uint32_t)(seed >> 32);
+  a.n_words = (uint32_t)words;
+  a.n_groups = n_groups;
+  a.n_tiles = (uint32_t)dm->tiles.size();
+  return sp::launch_sample_tiles(a, dm->rows_max, dm->path, L, (hipStream_t)stream);
 }
 
 }  // extern "C"

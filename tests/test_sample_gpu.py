@@ -414,6 +414,30 @@ def test_row_tiles_equal_untiled_and_oracle(path, tile_rows):
         assert np.array_equal(got, oracle.Circuit(text, outputs=outputs).sample(seed=3, first_shot=640, shots=10_000))
 
 
+@pytest.mark.parametrize("path", ["sparse", "dense"])
+def test_row_tiles_one_launch_shapes_and_ragged_range(path):
+    """All row tiles are sampled by one launch: for every launch shape, a
+    ragged shot count, a padded output stride and a shot range that crosses
+    2^32, the tiled model (tiles of 64 rows, the last one partial) writes
+    exactly the one-tile model's words, and the padding stays untouched."""
+    text = surface_memory(5, 5, "0.005", detectors=True).text()
+    m = sp.Model(text, outputs="detectors")
+    dm = sp.DeviceModel(m, path=path, tile_rows=64)
+    assert dm.n_tiles == math.ceil(m.n_meas / 64) and m.n_meas % 64
+    ref = sp.DeviceModel(m, path=path)
+    shots, first, ld = 1000, 2**32 - 320, 19
+    want = _gpu(ref, shots, seed=11, first_shot=first)
+    for launch in [(1, 1), (4, 2), (8, 1), (8, 2), (16, 4)]:
+        _say(f"one-launch row tiles path={path} launch={launch}")
+        dm.launch = launch
+        out = torch.full((m.n_meas, ld), 0x5A5A, dtype=torch.int64, device="cuda")
+        dm.sample(shots, seed=11, first_shot=first, out=out)
+        torch.cuda.synchronize()
+        got = sp.to_numpy_bits(out)
+        assert np.array_equal(got[:, :16], want), launch
+        assert (got[:, 16:] == 0x5A5A).all(), launch
+
+
 def _many_rows_circuit(rounds=5000):
     """25,000 recorded measurements: qubit 0 (random at first, then repeated
     without reset, so its outcome's symbol and its sparse X faults reach
