@@ -399,9 +399,12 @@ int sp_server_work_bytes(const sp_server_config* cfg, size_t* bytes);
 int sp_server_create(const sp_server_config* cfg, void* d_arena, size_t arena_bytes, void* d_work, size_t work_bytes,
                      sp_server** out);
 /* Queues a request (thread-safe, does not block on the device).  Its output
- * is bit for bit what sp_sample(model, seed, first_shot, shots) writes.
- * Errors: SP_E_INVALID, SP_E_LIMIT, SP_E_BUDGET (can never fit the arena, or
- * the queue is full). */
+ * is bit for bit what sp_sample(model, seed, first_shot, shots) writes.  A
+ * row-tiled model is served whole: each word of its shot range costs one
+ * workgroup per tile.  Errors: SP_E_INVALID, SP_E_LIMIT (slabs exceed the
+ * LDS with the server's launch shape, or more row tiles than a tick's
+ * 65,536 workgroups), SP_E_BUDGET (can never fit the arena, or the queue is
+ * full). */
 int sp_server_submit(sp_server* server, const sp_dmodel* model, uint64_t seed, uint64_t first_shot, uint64_t shots,
                      uint64_t* ticket);
 int sp_server_status(sp_server* server, uint64_t ticket, sp_request_status* out);

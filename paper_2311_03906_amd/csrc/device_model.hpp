@@ -57,11 +57,15 @@ struct TiledArgs {
 };
 
 // A job inside a batched launch (device memory; 16-byte multiple so that
-// kernels read it with 16-byte scalar loads).
+// kernels read it with 16-byte scalar loads).  A job over a row-tiled model
+// (n_tiles > 1) numbers its groups group * n_tiles + tile: a.m and a.out
+// are then replaced per group by the tile's record (a.out points at row 0),
+// and a.n_groups counts the groups of one tile.
 struct alignas(16) BatchJob {
   LaunchArgs a;
   uint32_t group_base;   // global index of the job's first group
-  uint32_t pad[3];
+  uint32_t n_tiles;      // 0 or 1: a.m is the model; else the tiles in `tiles`
+  const TileRec* tiles;
 };
 
 // A unit of hand-out in the persistent schedule: `count` consecutive groups

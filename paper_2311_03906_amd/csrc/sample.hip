@@ -523,6 +523,22 @@ __global__ void __launch_bounds__(1024) sample_tiles_kernel(TiledArgs t) {
   process_group<R, DENSE>(a, slab, f / t.n_tiles, tid, lane, wave, n_waves);
 }
 
+// Group g of a batched job: the tile's model and output rows for a job over
+// row tiles, else the job itself.
+template <int R, int DENSE>
+__device__ __forceinline__ void process_job_group(const BatchJob& job, uint64_t* slab, uint32_t g, uint32_t tid,
+                                                  uint32_t lane, uint32_t wave, uint32_t n_waves) {
+  LaunchArgs a = job.a;
+  if (job.n_tiles > 1) {
+    const uint32_t ti = g % job.n_tiles;
+    const TileRec rec = load_uniform(job.tiles + ti);
+    a.m = rec.m;
+    a.out = job.a.out + (size_t)rec.row0 * job.a.ld;
+    g /= job.n_tiles;
+  }
+  process_group<R, DENSE>(a, slab, g, tid, lane, wave, n_waves);
+}
+
 // Many jobs per launch, persistent schedule: workgroups take tasks (runs of
 // consecutive groups of one job) from a device counter until all are handed
 // out.  The workgroup that finishes last resets the counters, so the launch
@@ -545,7 +561,7 @@ __global__ void __launch_bounds__(1024) batch_persistent_kernel(const BatchJob* 
     const sp::BatchTask task = load_uniform(tasks + t);
     const BatchJob job = load_uniform(jobs + task.job);
     for (uint32_t i = 0; i < task.count; ++i) {
-      process_group<R, DENSE>(job.a, slab, task.first + i, tid, lane, wave, n_waves);
+      process_job_group<R, DENSE>(job, slab, task.first + i, tid, lane, wave, n_waves);
       __syncthreads();
     }
     if (tid == 0) s_next = nxt;
@@ -582,7 +598,7 @@ __global__ void __launch_bounds__(1024) batch_flat_kernel(const BatchJob* __rest
   const uint32_t wave = uniform(tid >> 6), n_waves = blockDim.x >> 6;
   const uint32_t g = run_swizzle(blockIdx.x, total);
   const BatchJob job = load_uniform(jobs + ((cuint32_p)group_job)[g]);
-  process_group<R, DENSE>(job.a, slab, g - job.group_base, tid, lane, wave, n_waves);
+  process_job_group<R, DENSE>(job, slab, g - job.group_base, tid, lane, wave, n_waves);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -691,6 +707,7 @@ struct Layout {
 };
 
 static_assert(sizeof(TileRec) % 16 == 0, "tile records are read with 16-byte loads");
+static_assert(sizeof(BatchJob) % 16 == 0, "jobs are read with 16-byte loads");
 
 // tile_rows: 0 picks one tile up to kOneTileRowsMax rows, else tiles of
 // kTileRowsAuto rows; otherwise tiles of that many rows (a multiple of 64).

@@ -105,6 +105,8 @@ int stage_and_launch(sp_server* S, int si) {
       const sp_dmodel* dm = (const sp_dmodel*)r->model;
       sp::BatchJob J{};
       J.a.m = dm->tiles[0];
+      J.n_tiles = (uint32_t)dm->tiles.size();
+      J.tiles = dm->d_tiles;   // row tiles: the kernel takes each group's tile from the table
       J.a.ld = r->words;
       J.a.out = (uint64_t*)(S->arena + r->off) + c.w0;
       J.a.first_shot = r->first_shot + 64 * c.w0;
@@ -114,10 +116,11 @@ int stage_and_launch(sp_server* S, int si) {
       J.a.n_words = (uint32_t)(c.w1 - c.w0);
       J.a.n_groups = (J.a.n_words + R - 1) / R;
       J.group_base = groups[p];
-      for (uint32_t q = 0; q < J.a.n_groups; ++q) map[g + q] = n_jobs[p];
-      g += J.a.n_groups;
-      groups[p] += J.a.n_groups;
-      n_meas_max[p] = std::max(n_meas_max[p], dm->tiles[0].n_meas);
+      const uint32_t job_groups = J.a.n_groups * J.n_tiles;
+      for (uint32_t q = 0; q < job_groups; ++q) map[g + q] = n_jobs[p];
+      g += job_groups;
+      groups[p] += job_groups;
+      n_meas_max[p] = std::max(n_meas_max[p], dm->rows_max);
       jobs[j++] = J;
       ++n_jobs[p];
     }
@@ -265,15 +268,14 @@ int sp_server_submit(sp_server* S, const sp_dmodel* model, uint64_t seed, uint64
   if (model->device != S->device) return set_error(SP_E_INVALID, "model on another device");
   if (first_shot + shots < first_shot) return set_error(SP_E_INVALID, "shot range overflows 64 bits");
   if ((shots + 63) / 64 > 0x7FFFFFFFull) return set_error(SP_E_LIMIT, "too many shots for one request");
-  if (model->tiles.size() != 1)
-    return set_error(SP_E_LIMIT, "the server takes models of one row tile (at most one LDS slab of rows)");
-  if (sp::lds_bytes(model->tiles[0].n_meas, S->cfg.launch.words_per_group, S->cfg.launch.waves_per_group,
-                    model->path) > model->lds_max)
+  if (sp::lds_bytes(model->rows_max, S->cfg.launch.words_per_group, S->cfg.launch.waves_per_group, model->path) >
+      model->lds_max)
     return set_error(SP_E_LIMIT, "the model's slabs exceed the LDS of one workgroup with this launch shape");
   sp::serve::Request r;
   r.model = model;
-  r.n_meas = model->tiles[0].n_meas;
-  r.nb = model->tiles[0].nb;
+  r.n_meas = model->n_meas;
+  r.nb = model->nb;
+  r.tiles = (uint32_t)model->tiles.size();
   r.path = model->path;
   r.seed = seed;
   r.first_shot = first_shot;
@@ -283,6 +285,7 @@ int sp_server_submit(sp_server* S, const sp_dmodel* model, uint64_t seed, uint64
   const int rc = S->sched.submit(r, now_ns(), ticket);
   if (rc == 1) return set_error(SP_E_BUDGET, "request output exceeds the server's HBM arena");
   if (rc == 2) return set_error(SP_E_BUDGET, "request queue is full");
+  if (rc == 3) return set_error(SP_E_LIMIT, "the model has more row tiles than a tick has workgroups");
   S->gen++;
   S->cv_work.notify_one();
   return SP_OK;

@@ -73,7 +73,8 @@ class Arena {
 struct Request {
   uint64_t ticket = 0;
   const void* model = nullptr;   // opaque to the scheduler
-  uint32_t n_meas = 0, nb = 0;
+  uint32_t n_meas = 0, nb = 0;   // output rows and Philox blocks per shot, over all row tiles
+  uint32_t tiles = 1;            // row tiles: each word costs one group per tile
   int path = 0;
   uint64_t seed = 0, first_shot = 0, shots = 0;
   uint64_t words = 0;            // ceil(shots / 64) = ld of the output
@@ -103,11 +104,13 @@ class Scheduler {
         wpg_(std::max<uint32_t>(1, words_per_group)) {}
 
   // 0: queued (or done at once for zero shots); 1: refused because the
-  // output can never fit in the arena; 2: refused because the queue is full.
+  // output can never fit in the arena; 2: refused because the queue is full;
+  // 3: refused because one word of every row tile exceeds a tick's groups.
   int submit(Request r, uint64_t now, uint64_t* ticket) {
     r.words = (r.shots + 63) / 64;
     r.bytes = Arena::round((size_t)r.n_meas * r.words * 8);
     if (r.bytes > arena_.capacity()) return 1;
+    if (std::max<uint32_t>(1, r.tiles) > max_groups_) return 3;
     if (queue_.size() >= max_queued_) return 2;
     r.ticket = ++last_ticket_;
     r.t_submit = now;
@@ -143,8 +146,10 @@ class Scheduler {
   }
 
   // The next tick: every active request with words left gets a share of
-  // the tick's cost budget (at least one group), visiting requests in a
-  // rotating order so that no request waits for another to finish.
+  // the tick's cost budget (at least one group per row tile), visiting
+  // requests in a rotating order so that no request waits for another to
+  // finish.  A request whose tiles no longer fit the tick's groups waits for
+  // the next tick (the first request visited always fits).
   std::vector<Chunk> next_tick() {
     std::vector<Chunk> tick;
     std::vector<uint64_t> open;
@@ -160,13 +165,14 @@ class Scheduler {
     for (size_t i = 0; i < n && groups_left > 0; ++i) {
       Request& r = reqs_[open[(start + i) % n]];
       const uint64_t nb = std::max<uint32_t>(1, r.nb);
+      const uint64_t tiles = std::max<uint32_t>(1, r.tiles);
       uint64_t words = std::max<uint64_t>(wpg_, (std::min(share, cost_left) / nb) / wpg_ * wpg_);
-      words = std::min<uint64_t>(words, groups_left * wpg_);
+      words = std::min<uint64_t>(words, groups_left / tiles * wpg_);
       words = std::min<uint64_t>(words, r.words - r.next_word);
-      if (words == 0) break;
+      if (words == 0) continue;
       tick.push_back({r.ticket, r.next_word, r.next_word + words});
       r.next_word += words;
-      groups_left -= (words + wpg_ - 1) / wpg_;
+      groups_left -= tiles * ((words + wpg_ - 1) / wpg_);
       const uint64_t cost = words * nb;
       cost_left = cost_left > cost ? cost_left - cost : 0;
       if (cost_left == 0 && i + 1 < n) {

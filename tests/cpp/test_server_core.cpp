@@ -159,6 +159,40 @@ static void test_random_backpressure() {
   CHECK(written.size() <= tickets.size());
 }
 
+// Row-tiled requests: a word costs one group per tile, a tick never exceeds
+// its groups, a request whose tiles do not fit waits for a later tick, and
+// a request with more tiles than a tick's groups is refused.
+static void test_row_tiles() {
+  Scheduler s(1 << 30, 4, 100, 1 << 20, 16, 1);
+  uint64_t t;
+  Request big = req(100, 10, 64 * 40);
+  big.tiles = 17;
+  CHECK(s.submit(big, 0, &t) == 3);
+  Request a = req(100, 10, 64 * 40), b = req(10, 10, 64 * 40);
+  a.tiles = 5;
+  uint64_t ta, tb;
+  CHECK(s.submit(a, 0, &ta) == 0);
+  CHECK(s.submit(b, 0, &tb) == 0);
+  s.admit(0);
+  uint64_t now = 0, words_a = 0, words_b = 0;
+  int ticks = 0;
+  while (!s.idle() && ticks < 1000) {
+    auto tick = s.next_tick();
+    CHECK(!tick.empty());
+    uint64_t groups = 0;
+    for (const Chunk& c : tick) {
+      const uint64_t w = c.w1 - c.w0;
+      groups += (c.ticket == ta ? 5 : 1) * w;
+      (c.ticket == ta ? words_a : words_b) += w;
+    }
+    CHECK(groups <= 16);
+    for (uint64_t f : s.complete(tick, ++now, true)) s.release(f);
+    ++ticks;
+  }
+  CHECK(words_a == 40 && words_b == 40);
+  CHECK(s.idle() && s.arena().in_use() == 0);
+}
+
 static void test_fail_all() {
   Scheduler s(1 << 20, 1, 10, 100, 16, 1);
   uint64_t a, b;
@@ -178,6 +212,7 @@ int main() {
   test_fair_ticks();
   test_small_budget_keeps_everyone_moving();
   test_random_backpressure();
+  test_row_tiles();
   test_fail_all();
   if (failures) {
     std::printf("%d check(s) failed\n", failures);

@@ -144,14 +144,40 @@ def test_wait_timeout_and_unknown_ticket():
     srv.close()
 
 
-def test_refuses_row_tiled_models():
-    """The server serves models of one row tile; a tiled model is refused
-    with SP_E_LIMIT before anything is queued."""
-    m = sp.Model(surface_memory(5, 5, "0.001").text())
-    dm = sp.DeviceModel(m, tile_rows=64)
-    assert dm.n_tiles == 3
-    srv = sp.Server(arena_bytes=64 << 20, max_active=2)
-    with pytest.raises(sp.SymphaseError) as ei:
-        srv.submit(dm, 1000)
-    assert ei.value.code == sp._capi.SP_E_LIMIT
+def test_serves_row_tiled_models_in_a_mix():
+    """Row-tiled models (surface d=5 in 64-row tiles, the last one partial;
+    25,000 rows in automatic 4,096-row tiles) served together with one-tile
+    models, with a small tick budget so that requests are split over many
+    ticks: every output equals sp_sample's for the request alone, and one
+    tiled request equals the oracle's."""
+    text = surface_memory(5, 5, "0.004").text()
+    m = sp.Model(text)
+    tiled = sp.DeviceModel(m, tile_rows=64)
+    assert tiled.n_tiles == 3
+    big_text = "\n".join(["H 0", "CX 0 1"] + [l for k in range(5000) for l in
+                          (["X_ERROR(0.05) 0"] if k % 100 == 0 else []) +
+                          ["DEPOLARIZE1(0.002) 1 2 3 4", "CX 1 2", "M 0", "MR 1 2 3 4"]]) + "\n"
+    big = sp.DeviceModel(sp.Model(big_text))
+    assert big.n_tiles == 7
+    _, one = _model(surface_memory(3, 3, "0.01").text())
+    srv = sp.Server(arena_bytes=256 << 20, max_active=3, tick_cost=1 << 16)
+    reqs = []
+    rng = np.random.default_rng(4)
+    for i in range(12):
+        dm = (tiled, big, one)[i % 3]
+        shots = int(rng.integers(1, 40_000))
+        first = int(rng.integers(0, 1 << 36))
+        _say(f"server tiled mix request {i} tiles={dm.n_tiles} shots={shots}")
+        reqs.append((srv.submit(dm, shots, seed=100 + i, first_shot=first), dm, shots, 100 + i, first))
+    for t, dm, shots, seed, first in reqs:
+        st = srv.wait(t, timeout_ms=60_000)
+        assert st["state"] == "done"
+        assert st["n_meas"] == dm.n_meas
+        got = srv.output(st).clone()
+        if dm is tiled and seed == 100:
+            want = oracle.Circuit(text).sample(seed=seed, first_shot=first, shots=shots)
+            assert np.array_equal(sp.to_numpy_bits(got), want)
+        srv.release(t)
+        assert torch.equal(got, _alone(dm, shots, seed, first)), (seed, shots, dm.n_tiles)
+    assert srv.stats()["ticks"] > 12
     srv.close()
