@@ -53,8 +53,13 @@ using sp::OpKind;
 namespace {
 
 constexpr uint32_t kThreads = 1024;
+// Column words x selected rows up to which one wave computes a determined
+// outcome of a run in the logged pass.
+constexpr uint32_t kSoloWork = 64;
+constexpr uint32_t kTargetChunk = 1024;   // measurement targets staged in LDS at a time
 constexpr uint32_t kMaxQubits = 1024;
 constexpr uint32_t kMaxRW = 2 * kMaxQubits / 64;   // 32
+constexpr uint32_t kMaxDW = kMaxQubits / 64;       // words of a phase-row mask at most
 constexpr uint32_t kChunks = 32;                   // column chunks of the random-branch g sums
 constexpr size_t kStaticLds = 32 * 1024;           // at least the kernel's static LDS
 
@@ -186,6 +191,7 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
   __shared__ uint32_t s_cnt[2];
   __shared__ uint32_t s_red[kThreads / 64];
   __shared__ uint32_t s_scan[kThreads / 64];
+  __shared__ uint32_t s_tgt[kTargetChunk];   // targets of the current measurement instruction
   const uint32_t tid = threadIdx.x;
   const uint32_t n = d.n, RW = d.RW, W = d.W;
 
@@ -211,6 +217,15 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
   const uint32_t DW = (n + 63) >> 6, sh = n & 63u;
   uint64_t lp = 0, snp = 0;
   uint32_t n_det = 0;
+  // Logged pass: a determined outcome that selects few rows is done by one
+  // wave alone (the other waves walk past it), so a run of them costs no
+  // barrier; a barrier rejoins the waves before the next step that reads
+  // or writes shared state with every wave.
+  bool solo_wrote = false;   // uniform
+  auto join = [&]() {
+    if (solo_wrote) __syncthreads();
+    solo_wrote = false;
+  };
   // Word k of a mask over phase-row indices (bit i = stabilizer row n + i),
   // from word(w) of the same mask over tableau rows.
   auto pword = [&](auto word, uint32_t k) -> uint64_t {
@@ -273,6 +288,7 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
     const uint32_t op = hdr & 0xFFu, cnt = hdr >> 8;
     const uint32_t* it = d.ops + pc + 1;
     pc += 1 + cnt * (op == D_FB ? 2u : 1u);
+    join();
 
     if (op == D_H || op == D_S || op == D_PX || op == D_PY || op == D_PZ || op == D_CX) {
       for (uint32_t i = tid; i < cnt * RW; i += kThreads) {
@@ -436,9 +452,150 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
       continue;
     }
 
-    // D_M, D_R, D_MR: one location per target, in order.
+    // D_M, D_R, D_MR: one location per target, in order.  The targets are
+    // staged in LDS, a chunk at a time, so that the serial chain of
+    // measurements does not wait on a global load per target.
     for (uint32_t k = 0; k < cnt; ++k) {
-      const uint32_t a = uni(it[k]);
+      if (k % kTargetChunk == 0) {
+        __syncthreads();   // every wave is done with the previous chunk
+        solo_wrote = false;
+        for (uint32_t i = tid; i < min(cnt - k, kTargetChunk); i += kThreads) s_tgt[i] = it[k + i];
+        __syncthreads();
+      }
+      bool det0 = false;   // target k's outcome is determined (every wave checks, no barrier)
+      if (LOG && TAB_LDS) {
+        const uint32_t a0 = uni(s_tgt[k % kTargetChunk]);
+        const uint64_t x0 = lane < RW ? ld(X + (size_t)a0 * RW + lane) & stab_mask(lane, n) : 0ull;
+        det0 = __ballot(x0 != 0) == 0;
+      }
+      if (LOG && TAB_LDS && det0) {
+        // A run of determined outcomes that select few rows, one per wave:
+        // the tableau does not change along such a run, so every outcome's
+        // g sums are computed at once; only C changes (a reset with outcome
+        // 1 flips the rows with z_a), and wave 0 follows that chain in order
+        // in registers.
+        const uint32_t nb_max = min(min(cnt - k, kThreads / 64), kTargetChunk - k % kTargetChunk);
+        const bool recorded = op != D_R, reset = op != D_M;
+        uint64_t* const s_bsel = s_c0;         // [kMaxDW][kMaxDW]: selected rows (phase-row indices)
+        uint64_t* const s_bzp = s_c0 + 256;    // [kMaxDW][kMaxDW]: rows with z_a (phase-row indices)
+        join();   // the previous run's buffers are free
+        uint64_t dm = 0;
+        uint32_t aj = 0;
+        if (wave < nb_max) {
+          aj = uni(s_tgt[(k + wave) % kTargetChunk]);
+          const uint64_t xw = lane < RW ? ld(X + (size_t)aj * RW + lane) : 0ull;
+          const bool random = __ballot((lane < RW ? xw & stab_mask(lane, n) : 0ull) != 0) != 0;
+          dm = lane < DW ? xw & destab_mask(lane, n) : 0ull;
+          uint32_t ns = 0;
+          for (uint32_t kk = 0; kk < DW; ++kk) ns += (uint32_t)__builtin_popcountll(readlane64(dm, kk));
+          if (lane == 0) s_red[wave] = (!random && ns * DW <= kSoloWork) ? 1u : 0u;
+        }
+        __syncthreads();
+        uint32_t r = 0;
+        while (r < nb_max && s_red[r]) ++r;
+        r = uni(r);
+        if (r > 0) {
+          if (wave < r) {
+            // The product's g sums, bit-sliced: bit j of a lane's masks is
+            // column lane + 64 j.
+            uint32_t xs = 0, zs = 0, gs = 0;
+            uint64_t words = __ballot(dm != 0);
+            while (words) {
+              const uint32_t kk = (uint32_t)__builtin_ctzll(words);
+              words &= words - 1;
+              uint64_t x = readlane64(dm, kk);
+              while (x) {
+                const uint32_t row = n + kk * 64 + (uint32_t)__builtin_ctzll(x);
+                x &= x - 1;
+                const uint32_t rw = row >> 6, rb = row & 63u;
+                uint32_t xi = 0, zi = 0;
+                constexpr uint32_t kCols = 4;   // columns' loads in flight
+                for (uint32_t j = 0; j < DW; j += kCols) {
+                  uint64_t xv[kCols], zv[kCols];
+#pragma unroll
+                  for (uint32_t u = 0; u < kCols; ++u) {
+                    const uint32_t q = lane + 64 * (j + u);
+                    const bool ok = j + u < DW && q < n;
+                    xv[u] = ok ? X[(size_t)q * RW + rw] : 0ull;
+                    zv[u] = ok ? Z[(size_t)q * RW + rw] : 0ull;
+                  }
+#pragma unroll
+                  for (uint32_t u = 0; u < kCols; ++u) {
+                    xi |= (uint32_t)((xv[u] >> rb) & 1u) << (j + u);
+                    zi |= (uint32_t)((zv[u] >> rb) & 1u) << (j + u);
+                  }
+                }
+                uint64_t plus, minus;
+                g_masks(xi, zi, xs, zs, plus, minus);
+                gs += (uint32_t)__builtin_popcountll(plus) - (uint32_t)__builtin_popcountll(minus);
+                xs ^= xi;
+                zs ^= zi;
+              }
+            }
+            // The sum over lanes mod 4 (0 or 2), from the low bits' ballots.
+            const uint32_t gsum = (uint32_t)__builtin_popcountll(__ballot(gs & 1u)) +
+                                  2u * (uint32_t)__builtin_popcountll(__ballot(gs & 2u));
+            if (lane == 0) s_red[wave] = 1u | ((gsum & 3u) == 2u ? 2u : 0u);
+            if (lane < DW) {
+              s_bsel[wave * kMaxDW + lane] = dm;
+              if (reset) s_bzp[wave * kMaxDW + lane] = pword([&](uint32_t w) { return Z[(size_t)aj * RW + w]; }, lane);
+            }
+          }
+          __syncthreads();
+          if (wave == 0) {
+            // C over phase-row indices (bit i: row n + i), lane kk word kk.
+            uint64_t cp = lane < DW ? pword([&](uint32_t w) { return s_C[w]; }, lane) : 0ull;
+            uint64_t ecm = 0;   // outcomes with constant 1
+            for (uint32_t j = 0; j < r; ++j) {
+              const uint64_t sel = lane < DW ? s_bsel[j * kMaxDW + lane] : 0ull;
+              const uint32_t par = (uint32_t)__builtin_popcountll(__ballot(__builtin_popcountll(sel & cp) & 1u)) & 1u;
+              if (par ^ ((s_red[j] >> 1) & 1u)) {
+                ecm |= 1ull << j;
+                if (reset && lane < DW) cp ^= s_bzp[j * kMaxDW + lane];
+              }
+            }
+            const uint32_t ew = 2u + (reset ? 2u : 1u) * DW;   // log words per outcome
+            for (uint32_t i = lane; i < r * DW; i += 64) {
+              const uint32_t j = i / DW, kk = i % DW;
+              d.log[lp + j * ew + 2 + kk] = s_bsel[j * kMaxDW + kk];
+              if (reset) d.log[lp + j * ew + 2 + DW + kk] = s_bzp[j * kMaxDW + kk];
+            }
+            if (lane < r) {
+              const uint32_t j = lane;
+              d.loc_var0[nloc + j] = -1;
+              d.log[lp + j * ew] = LOG_DET | (reset ? 1u : 0u) << 8 | (recorded ? 1u : 0u) << 9 |
+                                   (uint64_t)(recorded ? n_det + j : 0u) << 32;
+              d.log[lp + j * ew + 1] = 0;
+              if (recorded) {
+                d.rec_var[nrec + j] = -1;
+                d.rec_c[nrec + j] = (uint32_t)(ecm >> j) & 1u;
+                d.rec_off[nrec + j] = 0;
+                d.rec_len[nrec + j] = 0;
+                d.rec_det[nrec + j] = (int32_t)(n_det + j);
+              }
+            }
+            // Resets with outcome 1: X on qubit a flips C of the rows with z_a.
+            if (reset && lane < RW) {
+              uint64_t acc = 0;
+              for (uint64_t em = uni64(ecm); em; em &= em - 1) {
+                const uint32_t at = uni(s_tgt[(k + (uint32_t)__builtin_ctzll(em)) % kTargetChunk]);
+                acc ^= Z[(size_t)at * RW + lane];
+              }
+              s_C[lane] ^= acc & stab_mask(lane, n);
+            }
+          }
+          lp += (uint64_t)r * (2u + (reset ? 2u : 1u) * DW);
+          if (recorded) {
+            n_det += r;
+            nrec += r;
+          }
+          nloc += r;
+          k += r - 1;
+          solo_wrote = true;
+          continue;
+        }
+      }
+      const uint32_t a = uni(s_tgt[k % kTargetChunk]);
       const uint64_t* xa = X + (size_t)a * RW;
       // Pivot: the first stabilizer row with x_a = 1, found by every wave.
       uint32_t p = 0xFFFFFFFFu;
@@ -451,6 +608,7 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
         }
         p = uni(p);
       }
+      join();
       int32_t e_var = -1;
       uint32_t e_c = 0;
       const uint32_t Wt = (vars + 1 + 63) >> 6;   // words holding every variable so far, and one more
@@ -770,6 +928,16 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
 // words; its slice, n x K words, lives in LDS) and applies the whole log to
 // its slice; slices never interact.  A determined recorded outcome's words
 // go to row `det` of E (n_det x W words) for the list kernels.
+//
+// The log is a chain of dependent steps, most of them small in a memory
+// experiment (a determined outcome there selects two rows on average) and
+// large in scrambling circuits (a random outcome's row list can hold half
+// the rows).  A step touching at most kShortRows rows is done by wave 0
+// alone: lane k owns word k of the slice, the rows come from scalar bit
+// scans of the logged masks, and no barrier is needed.  Longer steps use
+// every wave, with row lists in LDS and barriers.  All waves walk the log,
+// so they take the same barriers; a barrier precedes any step after wave 0
+// wrote alone.
 struct ReplayArgs {
   const uint64_t* log;
   uint64_t log_words;
@@ -779,7 +947,9 @@ struct ReplayArgs {
 };
 
 constexpr uint32_t kReplayThreads = 1024;
-constexpr size_t kReplayStaticLds = 20 * 1024;   // at least the replay kernel's static LDS
+constexpr uint32_t kLogWindow = 1024;             // log words staged in LDS at a time
+constexpr uint32_t kShortRows = 8;                // rows up to which one wave does a step
+constexpr size_t kReplayStaticLds = 28 * 1024;   // at least the replay kernel's static LDS
 
 __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
   extern __shared__ uint64_t s_P[];   // [n][K]
@@ -787,10 +957,15 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
   __shared__ uint32_t s_cnt[2];
   __shared__ uint64_t s_part[kReplayThreads];
   __shared__ uint64_t s_E[64];
+  __shared__ uint64_t s_log[kLogWindow];   // log words [win_lo, win_hi)
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint32_t n = r.n, DW = r.DW, K = r.K;
   const uint32_t w_lo = blockIdx.x * K, Ks = min(K, r.W - w_lo);   // this slice: words [w_lo, w_lo + Ks)
   for (uint32_t i = tid; i < n * K; i += kReplayThreads) s_P[i] = 0;
+  // Longest entry: a header of two words and two masks (a fault entry has three words).
+  const uint64_t max_entry = 2u + 2u * DW + 1u;
+  uint64_t win_lo = 0, win_hi = 0;
+  bool solo_wrote = false;   // wave 0 wrote alone since the last barrier (uniform)
 
   // Wave `wv` lists the set bits of a logged mask (DW words at m) into dst.
   auto list = [&](uint32_t wv, const uint64_t* m, uint32_t* dst, uint32_t slot) {
@@ -805,24 +980,76 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
       if (lane == 0) s_cnt[slot] = cnt;
     }
   };
-  // Rows dst[0..nr) of the slice ^= v(k), over (row, word) pairs.
-  auto xor_rows = [&](const uint32_t* rows, uint32_t nr, auto v) {
-    for (uint32_t i = tid; i < nr * Ks; i += kReplayThreads) {
-      const uint32_t row = rows[i / Ks], k = i % Ks;
-      s_P[row * K + k] ^= v(k);
+  // Set bits of a logged mask, counted by every wave (uniform).
+  auto bits = [&](const uint64_t* m) {
+    const uint64_t mw = lane < DW ? m[lane] : 0ull;
+    uint32_t c = 0;
+    for (uint32_t k = 0; k < DW; ++k) c += (uint32_t)__builtin_popcountll(readlane64(mw, k));
+    return c;
+  };
+  // Wave 0 alone: f(i) for every set bit i of a logged mask, ascending (the
+  // mask read once, lane k holding word k, and scanned with scalar ops).
+  auto for_bits = [&](const uint64_t* m, auto f) {
+    const uint64_t mw = lane < DW ? m[lane] : 0ull;
+    uint64_t words = __ballot(mw != 0);
+    while (words) {
+      const uint32_t k = (uint32_t)__builtin_ctzll(words);
+      words &= words - 1;
+      uint64_t x = readlane64(mw, k);
+      while (x) {
+        f(k * 64 + (uint32_t)__builtin_ctzll(x));
+        x &= x - 1;
+      }
     }
   };
+  // Row-parallel work: thread (rg, kw) takes word kw of the slice in rows
+  // rg, rg + G, ... of a list (G row groups of K threads).
+  const uint32_t G = kReplayThreads / K, rg = tid / K, kw = tid % K;
+  const bool rk = rg < G && kw < Ks;
+  // Rows dst[0..nr) of the slice ^= v(k).
+  auto xor_rows = [&](const uint32_t* rows, uint32_t nr, auto v) {
+    if (!rk) return;
+    const uint64_t x = v(kw);
+    uint32_t j = rg;
+    for (; j + 3 * G < nr; j += 4 * G) {
+      const uint32_t r0 = rows[j], r1 = rows[j + G], r2 = rows[j + 2 * G], r3 = rows[j + 3 * G];
+      s_P[r0 * K + kw] ^= x;
+      s_P[r1 * K + kw] ^= x;
+      s_P[r2 * K + kw] ^= x;
+      s_P[r3 * K + kw] ^= x;
+    }
+    for (; j < nr; j += G) s_P[rows[j] * K + kw] ^= x;
+  };
+  // Before a step that other waves take part in.
+  auto join = [&]() {
+    if (solo_wrote) __syncthreads();
+    solo_wrote = false;
+  };
+  const bool w0 = wave == 0, mine = w0 && lane < Ks;   // wave 0's lane = slice word
   __syncthreads();
 
+  // The log is read through a window in LDS, refilled by all threads with
+  // one coalesced load when the next entry may run past it (one load per
+  // window instead of a dependent global load per entry).
   for (uint64_t lp = 0; lp < r.log_words;) {
-    const uint64_t h0 = r.log[lp], h1 = r.log[lp + 1];
+    if (lp + max_entry > win_hi && win_hi < r.log_words) {
+      __syncthreads();   // every wave is done with the old window
+      solo_wrote = false;
+      win_lo = lp;
+      win_hi = min(lp + (uint64_t)kLogWindow, r.log_words);
+      for (uint32_t i = tid; i < win_hi - win_lo; i += kReplayThreads) s_log[i] = r.log[win_lo + i];
+      __syncthreads();
+    }
+    const uint64_t* e = s_log + (lp - win_lo);
+    const uint64_t h0 = uni64(e[0]), h1 = uni64(e[1]);
     const uint32_t kind = (uint32_t)h0 & 0xFFu;
-    const uint64_t* m = r.log + lp + 2;
+    const uint64_t* m = e + 2;
     if (kind == LOG_FAULT) {
       const uint32_t fk = ((uint32_t)h0 >> 8) & 0xFu, lg = ((uint32_t)h0 >> 12) & 0xFu, nq = ((uint32_t)h0 >> 16) & 0xFu;
       const uint32_t nv = (uint32_t)(h0 >> 32), v0 = (uint32_t)h1;
-      const uint64_t off = r.log[lp + 2];
+      const uint64_t off = uni64(e[2]);
       lp += 3;
+      join();
       // One wave per variable word of the slice that the instruction covers;
       // lane l takes variable 64 vw + l, builds its anticommuting-row mask
       // from the snapshots, and the transpose gives each row's bits.
@@ -854,17 +1081,34 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
     if (kind == LOG_RAND) {
       const bool reset = flags & 1u;
       const uint32_t p = hi, var = (uint32_t)h1;
-      list(0, m, s_rows, 0);
-      if (reset) list(1, m + DW, s_rows2, 1);
       lp += 2 + (reset ? 2u : 1u) * DW;
-      __syncthreads();
-      xor_rows(s_rows, s_cnt[0], [&](uint32_t k) { return s_P[p * K + k]; });   // row p itself is not in the list
-      __syncthreads();
-      // Row p becomes the fresh variable (a reset then removes it again);
-      // a reset adds it to the other rows with z_a.
       const bool in = (var >> 6) >= w_lo && (var >> 6) < w_lo + Ks;
       const uint32_t vk = (var >> 6) - w_lo;
       const uint64_t vb = 1ull << (var & 63);
+      // The listed rows (row p is not among them) take row p's symbols; row p
+      // becomes the fresh variable, which a reset then adds to the rows with
+      // z_a instead.
+      if (bits(m) + (reset ? bits(m + DW) : 0u) <= kShortRows) {
+        if (w0) {
+          const uint64_t vp = mine ? s_P[p * K + lane] : 0ull;
+          for_bits(m, [&](uint32_t i) {
+            if (mine) s_P[i * K + lane] ^= vp;
+          });
+          if (mine) s_P[p * K + lane] = (!reset && in && lane == vk) ? vb : 0ull;
+          if (reset && in)
+            for_bits(m + DW, [&](uint32_t i) {
+              if (i != p && lane == vk) s_P[i * K + vk] ^= vb;
+            });
+        }
+        solo_wrote = true;
+        continue;
+      }
+      join();
+      list(0, m, s_rows, 0);
+      if (reset) list(1, m + DW, s_rows2, 1);
+      __syncthreads();
+      xor_rows(s_rows, s_cnt[0], [&](uint32_t k) { return s_P[p * K + k]; });
+      __syncthreads();
       for (uint32_t k = tid; k < Ks; k += kReplayThreads) s_P[p * K + k] = (!reset && in && k == vk) ? vb : 0ull;
       if (reset && in)
         for (uint32_t j = tid; j < s_cnt[1]; j += kReplayThreads)
@@ -874,24 +1118,59 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
     }
     if (kind == LOG_DET) {
       const bool reset = flags & 1u, recorded = flags & 2u;
+      lp += 2 + (reset ? 2u : 1u) * DW;
+      // E = XOR of the selected rows; a reset adds it to the rows with z_a.
+      if (bits(m) + (reset ? bits(m + DW) : 0u) <= kShortRows) {
+        if (w0) {
+          uint64_t ev = 0;
+          for_bits(m, [&](uint32_t i) {
+            if (mine) ev ^= s_P[i * K + lane];
+          });
+          if (recorded && mine) r.E[(size_t)hi * r.W + w_lo + lane] = ev;
+          if (reset)
+            for_bits(m + DW, [&](uint32_t i) {
+              if (mine) s_P[i * K + lane] ^= ev;
+            });
+        }
+        solo_wrote = true;
+        continue;
+      }
+      join();
       list(0, m, s_rows, 0);
       if (reset) list(1, m + DW, s_rows2, 1);
-      lp += 2 + (reset ? 2u : 1u) * DW;
       __syncthreads();
-      // E = XOR of the selected rows: per (row group, word) partial sums, then per word.
-      const uint32_t G = kReplayThreads / K, g = tid / K, k = tid % K, ns = s_cnt[0];
-      if (g < G) {
-        uint64_t e = 0;
-        if (k < Ks)
-          for (uint32_t j = g; j < ns; j += G) e ^= s_P[s_rows[j] * K + k];
-        s_part[tid] = e;
+      // Per (row group, word) partial sums, then per word (four independent
+      // chains each, so the loads overlap).
+      const uint32_t ns = s_cnt[0];
+      if (rg < G) {
+        uint64_t e0 = 0, e1 = 0, e2 = 0, e3 = 0;
+        if (kw < Ks) {
+          uint32_t j = rg;
+          for (; j + 3 * G < ns; j += 4 * G) {
+            const uint32_t r0 = s_rows[j], r1 = s_rows[j + G], r2 = s_rows[j + 2 * G], r3 = s_rows[j + 3 * G];
+            e0 ^= s_P[r0 * K + kw];
+            e1 ^= s_P[r1 * K + kw];
+            e2 ^= s_P[r2 * K + kw];
+            e3 ^= s_P[r3 * K + kw];
+          }
+          for (; j < ns; j += G) e0 ^= s_P[s_rows[j] * K + kw];
+        }
+        s_part[tid] = e0 ^ e1 ^ e2 ^ e3;
       }
       __syncthreads();
       if (tid < Ks) {
-        uint64_t e = 0;
-        for (uint32_t gg = 0; gg < G; ++gg) e ^= s_part[gg * K + tid];
-        s_E[tid] = e;
-        if (recorded) r.E[(size_t)hi * r.W + w_lo + tid] = e;
+        uint64_t e0 = 0, e1 = 0, e2 = 0, e3 = 0;
+        uint32_t gg = 0;
+        for (; gg + 3 < G; gg += 4) {
+          e0 ^= s_part[gg * K + tid];
+          e1 ^= s_part[(gg + 1) * K + tid];
+          e2 ^= s_part[(gg + 2) * K + tid];
+          e3 ^= s_part[(gg + 3) * K + tid];
+        }
+        for (; gg < G; ++gg) e0 ^= s_part[gg * K + tid];
+        const uint64_t ev = e0 ^ e1 ^ e2 ^ e3;
+        s_E[tid] = ev;
+        if (recorded) r.E[(size_t)hi * r.W + w_lo + tid] = ev;
       }
       __syncthreads();
       if (reset) {
@@ -900,15 +1179,35 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
       }
       continue;
     }
-    // LOG_FB_RAND / LOG_FB_DET
-    list(0, m, s_rows, 0);
+    // LOG_FB_RAND / LOG_FB_DET: a Pauli conditioned on an earlier outcome.
     lp += 2 + DW;
+    const bool in = (hi >> 6) >= w_lo && (hi >> 6) < w_lo + Ks;
+    const uint32_t vk = (hi >> 6) - w_lo;
+    const uint64_t vb = 1ull << (hi & 63);
+    if (bits(m) <= kShortRows) {
+      if (w0) {
+        if (kind == LOG_FB_DET) {
+          const uint64_t ev = mine ? r.E[(size_t)hi * r.W + w_lo + lane] : 0ull;   // written by this lane
+          for_bits(m, [&](uint32_t i) {
+            if (mine) s_P[i * K + lane] ^= ev;
+          });
+        } else if (in) {
+          for_bits(m, [&](uint32_t i) {
+            if (lane == vk) s_P[i * K + vk] ^= vb;
+          });
+        }
+      }
+      solo_wrote = true;
+      continue;
+    }
+    join();
+    list(0, m, s_rows, 0);
     if (kind == LOG_FB_DET && tid < Ks) s_E[tid] = r.E[(size_t)hi * r.W + w_lo + tid];
     __syncthreads();
     if (kind == LOG_FB_DET) {
       xor_rows(s_rows, s_cnt[0], [&](uint32_t kk) { return s_E[kk]; });
-    } else if ((hi >> 6) >= w_lo && (hi >> 6) < w_lo + Ks) {
-      for (uint32_t j = tid; j < s_cnt[0]; j += kReplayThreads) s_P[s_rows[j] * K + ((hi >> 6) - w_lo)] ^= 1ull << (hi & 63);
+    } else if (in) {
+      for (uint32_t j = tid; j < s_cnt[0]; j += kReplayThreads) s_P[s_rows[j] * K + vk] ^= vb;
     }
     __syncthreads();
   }
