@@ -109,7 +109,10 @@ struct InitDev {
 //           selected rows (destabilizers with x_a), then (reset) the rows with z_a
 //   FB_RAND 2 words: kind | var << 32; 0; then the anticommuting rows
 //   FB_DET  2 words: kind | det << 32; 0; then the anticommuting rows
-enum LogKind : uint32_t { LOG_FAULT = 1, LOG_RAND, LOG_DET, LOG_FB_RAND, LOG_FB_DET };
+//   RUN     1 word:  kind | r << 8: the next r (2..16) entries are DET entries
+//           of one instruction computed together (along such a run the
+//           tableau does not change)
+enum LogKind : uint32_t { LOG_FAULT = 1, LOG_RAND, LOG_DET, LOG_FB_RAND, LOG_FB_DET, LOG_RUN };
 
 __device__ __forceinline__ uint32_t bit_of(const uint64_t* col, uint32_t r) { return (uint32_t)(col[r >> 6] >> (r & 63)) & 1u; }
 
@@ -554,18 +557,21 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
                 if (reset && lane < DW) cp ^= s_bzp[j * kMaxDW + lane];
               }
             }
+            // A run of two or more entries is announced by a RUN entry.
             const uint32_t ew = 2u + (reset ? 2u : 1u) * DW;   // log words per outcome
+            const uint64_t lb = lp + (r > 1 ? 1u : 0u);
+            if (r > 1 && lane == 0) d.log[lp] = LOG_RUN | r << 8;
             for (uint32_t i = lane; i < r * DW; i += 64) {
               const uint32_t j = i / DW, kk = i % DW;
-              d.log[lp + j * ew + 2 + kk] = s_bsel[j * kMaxDW + kk];
-              if (reset) d.log[lp + j * ew + 2 + DW + kk] = s_bzp[j * kMaxDW + kk];
+              d.log[lb + j * ew + 2 + kk] = s_bsel[j * kMaxDW + kk];
+              if (reset) d.log[lb + j * ew + 2 + DW + kk] = s_bzp[j * kMaxDW + kk];
             }
             if (lane < r) {
               const uint32_t j = lane;
               d.loc_var0[nloc + j] = -1;
-              d.log[lp + j * ew] = LOG_DET | (reset ? 1u : 0u) << 8 | (recorded ? 1u : 0u) << 9 |
+              d.log[lb + j * ew] = LOG_DET | (reset ? 1u : 0u) << 8 | (recorded ? 1u : 0u) << 9 |
                                    (uint64_t)(recorded ? n_det + j : 0u) << 32;
-              d.log[lp + j * ew + 1] = 0;
+              d.log[lb + j * ew + 1] = 0;
               if (recorded) {
                 d.rec_var[nrec + j] = -1;
                 d.rec_c[nrec + j] = (uint32_t)(ecm >> j) & 1u;
@@ -584,7 +590,7 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
               s_C[lane] ^= acc & stab_mask(lane, n);
             }
           }
-          lp += (uint64_t)r * (2u + (reset ? 2u : 1u) * DW);
+          lp += (r > 1 ? 1u : 0u) + (uint64_t)r * (2u + (reset ? 2u : 1u) * DW);
           if (recorded) {
             n_det += r;
             nrec += r;
@@ -958,12 +964,13 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
   __shared__ uint64_t s_part[kReplayThreads];
   __shared__ uint64_t s_E[64];
   __shared__ uint64_t s_log[kLogWindow];   // log words [win_lo, win_hi)
+  __shared__ uint32_t s_rdm[kReplayThreads / 64];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint32_t n = r.n, DW = r.DW, K = r.K;
   const uint32_t w_lo = blockIdx.x * K, Ks = min(K, r.W - w_lo);   // this slice: words [w_lo, w_lo + Ks)
   for (uint32_t i = tid; i < n * K; i += kReplayThreads) s_P[i] = 0;
-  // Longest entry: a header of two words and two masks (a fault entry has three words).
-  const uint64_t max_entry = 2u + 2u * DW + 1u;
+  // Longest entry: a RUN of 16 entries of two header words and two masks.
+  const uint64_t max_entry = 1u + 16u * (2u + 2u * DW);
   uint64_t win_lo = 0, win_hi = 0;
   bool solo_wrote = false;   // wave 0 wrote alone since the last barrier (uniform)
 
@@ -1075,6 +1082,62 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
         }
       }
       __syncthreads();
+      continue;
+    }
+    if (kind == LOG_RUN) {
+      // A run of DET entries of one instruction, one wave each: E of every
+      // outcome from the rows before the run's resets; the resets then
+      // follow in order on wave 0, where an outcome's E also takes the E of
+      // every earlier reset whose rows with z_a meet its selected rows an
+      // odd number of times.
+      const uint32_t nr = ((uint32_t)h0 >> 8) & 0xFFu;
+      const uint64_t lb = lp + 1;
+      const bool reset = (h1 >> 8) & 1u;   // h1 is the first entry's header
+      const uint32_t ew = 2u + (reset ? 2u : 1u) * DW;
+      const uint64_t* e0 = s_log + (lb - win_lo);
+      lp = lb + (uint64_t)nr * ew;
+      join();
+      uint64_t* const s_run = s_part;   // [16][64]: E of each outcome of the run
+      if (wave < nr) {
+        const uint64_t* ej = e0 + wave * ew;
+        const uint64_t hj = uni64(ej[0]);
+        uint64_t ev = 0;
+        for_bits(ej + 2, [&](uint32_t i) {
+          if (lane < Ks) ev ^= s_P[i * K + lane];
+        });
+        if (!reset) {
+          if (((hj >> 9) & 1u) && lane < Ks) r.E[(size_t)(hj >> 32) * r.W + w_lo + lane] = ev;
+        } else {
+          s_run[wave * 64 + lane] = ev;
+          const uint64_t sel = lane < DW ? ej[2 + lane] : 0ull;
+          uint32_t dmask = 0;
+          for (uint32_t j = 0; j < wave; ++j) {
+            const uint64_t zj = lane < DW ? e0[j * ew + 2 + DW + lane] : 0ull;
+            dmask |= ((uint32_t)__builtin_popcountll(__ballot(__builtin_popcountll(sel & zj) & 1u)) & 1u) << j;
+          }
+          if (lane == 0) s_rdm[wave] = dmask;
+        }
+      }
+      __syncthreads();   // every wave is done reading the rows
+      if (reset) {
+        if (w0) {
+          for (uint32_t j = 0; j < nr; ++j) {
+            const uint64_t* ej = e0 + j * ew;
+            const uint64_t hj = uni64(ej[0]);
+            uint64_t ev = s_run[j * 64 + lane];
+            const uint32_t dmask = uni(s_rdm[j]);
+            if (dmask) {
+              for (uint32_t dm = dmask; dm; dm &= dm - 1) ev ^= s_run[(uint32_t)__builtin_ctz(dm) * 64 + lane];
+              s_run[j * 64 + lane] = ev;
+            }
+            if (((hj >> 9) & 1u) && lane < Ks) r.E[(size_t)(hj >> 32) * r.W + w_lo + lane] = ev;
+            for_bits(ej + 2 + DW, [&](uint32_t i) {
+              if (lane < Ks) s_P[i * K + lane] ^= ev;
+            });
+          }
+        }
+        solo_wrote = true;
+      }
       continue;
     }
     const uint32_t flags = ((uint32_t)h0 >> 8) & 0xFFu, hi = (uint32_t)(h0 >> 32);
@@ -1358,7 +1421,7 @@ void log_bounds(const DevProgram& P, uint32_t DW, uint64_t* log_words, uint64_t*
       lw += 3;
       sw += (uint64_t)cnt * (kind == F_DEP2 ? 2u : 1u) * 2u * DW;
     } else if (op == D_M || op == D_R || op == D_MR) {
-      lw += (uint64_t)cnt * (2 + 2ull * DW);
+      lw += (uint64_t)cnt * (3 + 2ull * DW);   // an entry each, and at most one RUN entry each
     } else if (op == D_FB) {
       lw += (uint64_t)cnt * (2 + (uint64_t)DW);
     }

@@ -133,6 +133,54 @@ def test_device_model_matches_oracle_on_random_circuits(seed, mode):
             assert np.array_equal(_evaluate(M, c, _assignment(mv, codes)), want)
 
 
+def _repeated_target_circuit(seed):
+    """Noisy Clifford circuit whose M, R and MR instructions have several
+    targets with repeats, so that one instruction holds runs of determined
+    outcomes in which the same qubit is measured or reset again."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 7))
+    lines = []
+    for _ in range(int(rng.integers(5, 40))):
+        kind = rng.integers(7)
+        if kind == 0:
+            lines.append("H " + " ".join(str(q) for q in rng.choice(n, int(rng.integers(1, n + 1)), replace=False)))
+        elif kind == 1:
+            lines.append("S " + " ".join(str(q) for q in rng.choice(n, int(rng.integers(1, n + 1)), replace=False)))
+        elif kind == 2:
+            a, b = rng.choice(n, 2, replace=False)
+            lines.append(f"CX {a} {b}")
+        elif kind == 3:
+            lines.append(f"X_ERROR(0.25) {rng.integers(n)}")
+        elif kind == 4:
+            lines.append(f"DEPOLARIZE1(0.5) {rng.integers(n)}")
+        else:
+            op = ("M", "R", "MR")[int(rng.integers(3))]
+            lines.append(op + " " + " ".join(str(q) for q in rng.integers(0, n, int(rng.integers(2, 12)))))
+    lines.append("M " + " ".join(str(q) for q in range(n)))
+    return "\n".join(lines) + "\n"
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("seed", range(30))
+def test_repeated_targets_in_one_instruction(seed, mode):
+    """Measurements and resets of the same qubit again within one
+    instruction (a reset's X then flips rows that a later outcome of the
+    same instruction selects): the device model equals the host model and
+    reproduces the oracle's outputs for random codes."""
+    text = _repeated_target_circuit(seed)
+    rng = np.random.default_rng(1000 + seed)
+    oc = oracle.Circuit(text)
+    m = _device_model(text, "measurements", mode)
+    _same_model(m, sp.Model(text))
+    M, c = m.export_dense()
+    mv = m.export_vars()
+    kinds = oc.location_kinds()
+    for _ in range(4):
+        codes = np.array([rng.integers(0, 2 ** oracle.CODE_BITS[int(k)]) for k in kinds], dtype=np.uint8)
+        want = oc.rows_from_outcomes(oc.run_codes(codes)[0])
+        assert np.array_equal(_evaluate(M, c, _assignment(mv, codes)), want)
+
+
 _LARGE = [("surf5", lambda: surface_memory(5, 5, 1e-3, detectors=True)),
           ("surf7_feedback", lambda: surface_memory(7, 7, "0.005", detectors=True, reset="feedback")),
           ("rep25", lambda: repetition_memory(25, 25, "0.01", detectors=True)),
