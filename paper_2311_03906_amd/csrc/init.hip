@@ -688,16 +688,30 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
         __syncthreads();
         // Constants of the rows taking row p (the sums are even for
         // commuting rows: bit 1 says "2 mod 4"); row p's becomes 0.
-        if (tid < RW) {
+        // Four threads per word each add a quarter of the chunk counters (2-bit
+        // sums, bit-sliced), then two lane exchanges add the quarters.
+        if (tid < 4 * kMaxRW) {
+          const uint32_t w = tid / 4, qt = tid % 4;
           uint64_t c0 = 0, c1 = 0;
-          for (uint32_t ch = 0; ch < kChunks; ++ch) {
-            const uint64_t b0 = s_c0[tid * kChunks + ch], b1 = s_c1[tid * kChunks + ch];
+          if (w < RW) {
+#pragma unroll
+            for (uint32_t i = 0; i < kChunks / 4; ++i) {
+              const uint64_t b0 = s_c0[w * kChunks + qt * (kChunks / 4) + i];
+              const uint64_t b1 = s_c1[w * kChunks + qt * (kChunks / 4) + i];
+              c1 ^= b1 ^ (c0 & b0);
+              c0 ^= b0;
+            }
+          }
+          for (uint32_t off = 1; off < 4; off <<= 1) {
+            const uint64_t b0 = shfl_xor64(c0, off), b1 = shfl_xor64(c1, off);
             c1 ^= b1 ^ (c0 & b0);
             c0 ^= b0;
           }
-          uint64_t cw = s_C[tid] ^ (s_mask[tid] & stab_mask(tid, n) & (c1 ^ (cp ? ~0ull : 0ull)));
-          if (tid == pw) cw &= ~pb;
-          s_C[tid] = cw;
+          if (qt == 0 && w < RW) {
+            uint64_t cw = s_C[w] ^ (s_mask[w] & stab_mask(w, n) & (c1 ^ (cp ? ~0ull : 0ull)));
+            if (w == pw) cw &= ~pb;
+            s_C[w] = cw;
+          }
         }
         // Symbols: every stabilizer row with x_a adds row p's old ones (the
         // logged pass logs those rows instead).
