@@ -60,7 +60,8 @@ constexpr uint32_t kTargetChunk = 1024;   // measurement targets staged in LDS a
 constexpr uint32_t kMaxQubits = 1024;
 constexpr uint32_t kMaxRW = 2 * kMaxQubits / 64;   // 32
 constexpr uint32_t kMaxDW = kMaxQubits / 64;       // words of a phase-row mask at most
-constexpr uint32_t kChunks = 32;                   // column chunks of the random-branch g sums
+constexpr uint32_t kChunks = 32;                   // kMaxRW x kChunks: the random branch's chunk counters
+constexpr uint32_t kMaxChunks = 64;                // column chunks of the random-branch g sums, at most
 constexpr size_t kStaticLds = 32 * 1024;           // at least the kernel's static LDS
 
 // Device instruction stream: a header word (opcode | count << 8), then
@@ -642,10 +643,13 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
             pp[w] = w == ((uint32_t)e_var >> 6) ? 1ull << ((uint32_t)e_var & 63) : 0ull;
           }
         }
-        // g sums of every row against row p, bit-sliced mod 4, per (word, column chunk).
+        // g sums of every row against row p, bit-sliced mod 4, per (word, column
+        // chunk): thread tid takes word tid % RW of chunk tid / RW, so a
+        // wave's loads cover consecutive words and every lane works.
+        const uint32_t nch = min(kMaxChunks, kThreads / RW);   // column chunks
         {
-          const uint32_t w = tid % kMaxRW, chunk = tid / kMaxRW;
-          if (w < RW) {
+          const uint32_t w = tid % RW, chunk = tid / RW;
+          if (chunk < nch) {
             uint64_t c0 = 0, c1 = 0;
             const uint64_t mw = ld(xa + w) & ~(w == pw ? pb : 0ull);
             if (mw) {
@@ -661,12 +665,12 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
                 c0 ^= minus;
               };
               uint32_t q = chunk;
-              for (; q + kChunks < n; q += 2 * kChunks) {   // two columns' loads in flight
+              for (; q + nch < n; q += 2 * nch) {   // two columns' loads in flight
                 uint64_t px[2], pz[2], vx[2], vz[2];
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                  const uint64_t* xq = X + (size_t)(q + i * kChunks) * RW;
-                  const uint64_t* zq = Z + (size_t)(q + i * kChunks) * RW;
+                  const uint64_t* xq = X + (size_t)(q + i * nch) * RW;
+                  const uint64_t* zq = Z + (size_t)(q + i * nch) * RW;
                   px[i] = xq[pw];
                   pz[i] = zq[pw];
                   vx[i] = xq[w];
@@ -675,29 +679,27 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
 #pragma unroll
                 for (int i = 0; i < 2; ++i) add(px[i], pz[i], vx[i], vz[i]);
               }
-              for (; q < n; q += kChunks) {
+              for (; q < n; q += nch) {
                 const uint64_t* xq = X + (size_t)q * RW;
                 const uint64_t* zq = Z + (size_t)q * RW;
                 add(xq[pw], zq[pw], xq[w], zq[w]);
               }
             }
-            s_c0[w * kChunks + chunk] = c0;
-            s_c1[w * kChunks + chunk] = c1;
+            s_c0[w * nch + chunk] = c0;
+            s_c1[w * nch + chunk] = c1;
           }
         }
         __syncthreads();
         // Constants of the rows taking row p (the sums are even for
-        // commuting rows: bit 1 says "2 mod 4"); row p's becomes 0.
-        // Four threads per word each add a quarter of the chunk counters (2-bit
+        // commuting rows: bit 1 says "2 mod 4"); row p's becomes 0.  Four
+        // threads per word each add a quarter of the chunk counters (2-bit
         // sums, bit-sliced), then two lane exchanges add the quarters.
         if (tid < 4 * kMaxRW) {
           const uint32_t w = tid / 4, qt = tid % 4;
           uint64_t c0 = 0, c1 = 0;
           if (w < RW) {
-#pragma unroll
-            for (uint32_t i = 0; i < kChunks / 4; ++i) {
-              const uint64_t b0 = s_c0[w * kChunks + qt * (kChunks / 4) + i];
-              const uint64_t b1 = s_c1[w * kChunks + qt * (kChunks / 4) + i];
+            for (uint32_t ch = qt; ch < nch; ch += 4) {
+              const uint64_t b0 = s_c0[w * nch + ch], b1 = s_c1[w * nch + ch];
               c1 ^= b1 ^ (c0 & b0);
               c0 ^= b0;
             }
