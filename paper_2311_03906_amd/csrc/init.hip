@@ -738,12 +738,32 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
           uint64_t* zq = Z + (size_t)q * RW;
           const uint64_t bx = xq[pw] & pb, bz = zq[pw] & pb;
           const uint64_t lx = bx ? ~0ull : 0ull, lz = bz ? ~0ull : 0ull;
-          if (bx | bz)   // otherwise the column keeps its words
+          if ((bx | bz) && TAB_LDS) {   // otherwise the column keeps its words
             for (uint32_t w = 0; w < RW; ++w) {
               const uint64_t m = s_mask[w];
               xq[w] ^= m & lx;
               zq[w] ^= m & lz;
             }
+          } else if (bx | bz) {
+            // A tableau in global memory: eight words' loads are issued before
+            // any store (X and Z may alias as far as the compiler knows, so it
+            // would not hoist them), and words the mask leaves alone are not
+            // written.
+            for (uint32_t w0 = 0; w0 < RW; w0 += 8) {
+              uint64_t xv[8], zv[8];
+#pragma unroll
+              for (uint32_t u = 0; u < 8; ++u) {
+                xv[u] = w0 + u < RW ? xq[w0 + u] : 0ull;
+                zv[u] = w0 + u < RW ? zq[w0 + u] : 0ull;
+              }
+#pragma unroll
+              for (uint32_t u = 0; u < 8; ++u) {
+                const uint64_t m = w0 + u < RW ? s_mask[w0 + u] : 0ull;
+                if (m & lx) xq[w0 + u] = xv[u] ^ m;
+                if (m & lz) zq[w0 + u] = zv[u] ^ m;
+              }
+            }
+          }
           const uint32_t dr = p - n, dw = dr >> 6;
           const uint64_t db = 1ull << (dr & 63);
           xq[dw] = (xq[dw] & ~db) | (bx ? db : 0ull);
