@@ -188,6 +188,7 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
   extern __shared__ uint64_t s_tab[];
   __shared__ uint64_t s_C[kMaxRW];      // constant phase bit of every row
   __shared__ uint64_t s_mask[kMaxRW];   // x_a of every row but p, before a random measurement's update
+  __shared__ uint64_t s_rpx[kMaxQubits / 64], s_rpz[kMaxQubits / 64];   // row p's x and z, bit q = column q
   __shared__ uint64_t s_c0[kMaxRW * kChunks];
   __shared__ uint64_t s_c1[kMaxRW * kChunks];
   __shared__ uint32_t s_rows[kMaxQubits];    // rows of the current measurement's row operations
@@ -643,6 +644,21 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
             pp[w] = w == ((uint32_t)e_var >> 6) ? 1ull << ((uint32_t)e_var & 63) : 0ull;
           }
         }
+        // Row p's x and z in every column, one thread per column: only the
+        // columns where row p has x or z add to the g sums below.
+        {
+          uint64_t bxq = 0, bzq = 0;
+          if (tid < n) {
+            bxq = X[(size_t)tid * RW + pw] & pb;
+            bzq = Z[(size_t)tid * RW + pw] & pb;
+          }
+          const uint64_t mx = __ballot(bxq != 0), mz = __ballot(bzq != 0);
+          if (lane == 0) {
+            s_rpx[wave] = mx;
+            s_rpz[wave] = mz;
+          }
+        }
+        __syncthreads();
         // g sums of every row against row p, bit-sliced mod 4, per (word, column
         // chunk): thread tid takes word tid % RW of chunk tid / RW, so a
         // wave's loads cover consecutive words and every lane works.
@@ -653,10 +669,9 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
             uint64_t c0 = 0, c1 = 0;
             const uint64_t mw = ld(xa + w) & ~(w == pw ? pb : 0ull);
             if (mw) {
-              // c += plus; c -= minus (mod 4, per bit), for column q whose row-p
-              // bits are (px, pz) and whose word w is (vx, vz)
-              auto add = [&](uint64_t px, uint64_t pz, uint64_t vx, uint64_t vz) {
-                const uint64_t lx = (px & pb) ? ~0ull : 0ull, lz = (pz & pb) ? ~0ull : 0ull;
+              // c += plus; c -= minus (mod 4, per bit), for a column whose row-p
+              // bits are (lx, lz) (all ones or zero) and whose word w is (vx, vz)
+              auto add = [&](uint64_t lx, uint64_t lz, uint64_t vx, uint64_t vz) {
                 uint64_t plus, minus;
                 g_masks(lx, lz, vx, vz, plus, minus);
                 c1 ^= c0 & plus;
@@ -664,25 +679,30 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
                 c1 ^= ~c0 & minus;
                 c0 ^= minus;
               };
+              auto rp = [&](uint32_t q, uint64_t& lx, uint64_t& lz) {
+                lx = ((s_rpx[q >> 6] >> (q & 63)) & 1u) ? ~0ull : 0ull;
+                lz = ((s_rpz[q >> 6] >> (q & 63)) & 1u) ? ~0ull : 0ull;
+              };
               uint32_t q = chunk;
               for (; q + nch < n; q += 2 * nch) {   // two columns' loads in flight
-                uint64_t px[2], pz[2], vx[2], vz[2];
+                uint64_t lx[2], lz[2], vx[2] = {0, 0}, vz[2] = {0, 0};
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                  const uint64_t* xq = X + (size_t)(q + i * nch) * RW;
-                  const uint64_t* zq = Z + (size_t)(q + i * nch) * RW;
-                  px[i] = xq[pw];
-                  pz[i] = zq[pw];
-                  vx[i] = xq[w];
-                  vz[i] = zq[w];
+                  const uint32_t qi = q + i * nch;
+                  rp(qi, lx[i], lz[i]);
+                  if (lx[i] | lz[i]) {
+                    vx[i] = X[(size_t)qi * RW + w];
+                    vz[i] = Z[(size_t)qi * RW + w];
+                  }
                 }
 #pragma unroll
-                for (int i = 0; i < 2; ++i) add(px[i], pz[i], vx[i], vz[i]);
+                for (int i = 0; i < 2; ++i)
+                  if (lx[i] | lz[i]) add(lx[i], lz[i], vx[i], vz[i]);
               }
               for (; q < n; q += nch) {
-                const uint64_t* xq = X + (size_t)q * RW;
-                const uint64_t* zq = Z + (size_t)q * RW;
-                add(xq[pw], zq[pw], xq[w], zq[w]);
+                uint64_t lx, lz;
+                rp(q, lx, lz);
+                if (lx | lz) add(lx, lz, X[(size_t)q * RW + w], Z[(size_t)q * RW + w]);
               }
             }
             s_c0[w * nch + chunk] = c0;
@@ -736,7 +756,8 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
         for (uint32_t q = tid; q < n; q += kThreads) {
           uint64_t* xq = X + (size_t)q * RW;
           uint64_t* zq = Z + (size_t)q * RW;
-          const uint64_t bx = xq[pw] & pb, bz = zq[pw] & pb;
+          const uint64_t bx = ((s_rpx[q >> 6] >> (q & 63)) & 1u) ? pb : 0ull;
+          const uint64_t bz = ((s_rpz[q >> 6] >> (q & 63)) & 1u) ? pb : 0ull;
           const uint64_t lx = bx ? ~0ull : 0ull, lz = bz ? ~0ull : 0ull;
           if ((bx | bz) && TAB_LDS) {   // otherwise the column keeps its words
             for (uint32_t w = 0; w < RW; ++w) {
