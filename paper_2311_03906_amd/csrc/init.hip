@@ -95,6 +95,7 @@ struct InitDev {
   // Logged pass only (the phase rows are left to the replay kernel):
   uint64_t* log;        // row-operation log, see LogKind
   uint64_t* snap;       // per fault location and qubit: its x and z stabilizer-row masks
+  uint64_t* first;      // per 64-variable word: 1 + the log position of the entry that introduces its first variable
   int32_t* rec_det;     // determined recorded outcome: its index among those, else -1
 };
 
@@ -362,6 +363,8 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
           d.log[lp + 1] = vars;
           d.log[lp + 2] = snp;
         }
+        for (uint32_t w = (vars + 63) >> 6; nv && w <= (vars + nv - 1) >> 6; w += kThreads)
+          if (w + tid <= (vars + nv - 1) >> 6) d.first[w + tid] = lp + 1;
         lp += 3;
         snp += (uint64_t)cnt * per_item;
         nloc += cnt;
@@ -741,6 +744,7 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
           if (tid == 0) {
             d.log[lp] = LOG_RAND | (op != D_M ? 1u : 0u) << 8 | (uint64_t)(p - n) << 32;
             d.log[lp + 1] = (uint32_t)e_var;
+            if ((e_var & 63) == 0) d.first[e_var >> 6] = lp + 1;
           }
           log_mask(lp + 2, [&](uint32_t w) { return s_mask[w]; });
         } else {
@@ -1005,7 +1009,8 @@ struct ReplayArgs {
   const uint64_t* log;
   uint64_t log_words;
   const uint64_t* snap;
-  uint64_t* E;          // [n_det][W]
+  const uint64_t* first;   // per variable word: 1 + the log position introducing its first variable
+  uint64_t* E;             // [n_det][W], zero on entry
   uint32_t n, DW, K, W;
 };
 
@@ -1028,7 +1033,13 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
   for (uint32_t i = tid; i < n * K; i += kReplayThreads) s_P[i] = 0;
   // Longest entry: a RUN of 16 entries of two header words and two masks.
   const uint64_t max_entry = 1u + 16u * (2u + 2u * DW);
-  uint64_t win_lo = 0, win_hi = 0;
+  // Variables are numbered in the order the log introduces them, so before
+  // the entry that introduces this slice's first variable every row is zero
+  // in the slice and every entry leaves it so (its E words stay the zeros
+  // E starts with): the walk starts there.
+  const uint64_t f0 = r.first[w_lo];
+  const uint64_t start = f0 ? min(f0 - 1, r.log_words) : 0;
+  uint64_t win_lo = start, win_hi = start;
   bool solo_wrote = false;   // wave 0 wrote alone since the last barrier (uniform)
 
   // Wave `wv` lists the set bits of a logged mask (DW words at m) into dst.
@@ -1095,7 +1106,7 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
   // The log is read through a window in LDS, refilled by all threads with
   // one coalesced load when the next entry may run past it (one load per
   // window instead of a dependent global load per entry).
-  for (uint64_t lp = 0; lp < r.log_words;) {
+  for (uint64_t lp = start; lp < r.log_words;) {
     if (lp + max_entry > win_hi && win_hi < r.log_words) {
       __syncthreads();   // every wave is done with the old window
       solo_wrote = false;
@@ -1489,14 +1500,15 @@ void log_bounds(const DevProgram& P, uint32_t DW, uint64_t* log_words, uint64_t*
 }
 
 struct InitLayout {
-  size_t ops, X, Z, P, E, loc, rec_var, rec_off, rec_len, rec_c, rec_det, status, log, snap, list, total;
+  size_t ops, X, Z, P, E, loc, rec_var, rec_off, rec_len, rec_c, rec_det, status, log, snap, first, list, total;
   uint32_t RW, W, DW, list_cap;
 };
 
 // The buffer layout.  One pass: the index list takes whatever the buffer has
-// left (at least `tail` entries).  Two passes (no phase rows here): the log
-// and snapshots, then `tail` bytes for the rows of E, the list counts and
-// offsets and the lists, or whatever the buffer has left.
+// left (at least `tail` entries).  Two passes (no phase rows here): the log,
+// the snapshots and the first-entry table of the variable words, then
+// `tail` bytes for the rows of E, the list counts and offsets and the
+// lists, or whatever the buffer has left.
 InitLayout layout(const sp_circuit& c, const DevProgram& P, bool two_pass, size_t tail, size_t budget) {
   InitLayout L{};
   const uint32_t n = c.n_qubits;
@@ -1528,6 +1540,7 @@ InitLayout layout(const sp_circuit& c, const DevProgram& P, bool two_pass, size_
     log_bounds(P, L.DW, &lw, &sw);
     L.log = take(8 * lw);
     L.snap = take(8 * sw);
+    L.first = take(8ull * L.W);   // zeroed with the rest of the fixed part
   }
   L.list = off;   // one pass: the lists; two passes: the rows of E and what follows them
   const size_t unit = two_pass ? 1 : 4;
@@ -1621,6 +1634,7 @@ int symbolize_device(const sp_circuit& c, int outputs, int mode, void* d_work, s
   if (two) {
     d.log = (uint64_t*)(base + L.log);
     d.snap = (uint64_t*)(base + L.snap);
+    d.first = (uint64_t*)(base + L.first);
     if (int rc = launch_init<true>(d, c.n_qubits, L.RW, s)) return rc;
   } else {
     d.P = (uint64_t*)(base + L.P);
@@ -1669,7 +1683,8 @@ int symbolize_device(const sp_circuit& c, int outputs, int mode, void* d_work, s
       return set_error(SP_E_LIMIT, "the replay needs a work buffer of at least " + std::to_string(lst_off) +
                                        " bytes plus room for the index lists");
     uint64_t* E = (uint64_t*)(base + e_off);
-    if (log_words) {   // also with no variables: it writes every determined outcome's (empty) row
+    if (n_det) HIP_TRY(hipMemsetAsync(E, 0, 8ull * n_det * Wu, s));   // slices skip the entries before their variables
+    if (log_words) {
       int dev = 0, lds_max = 0;
       HIP_TRY(hipGetDevice(&dev));
       HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -1679,6 +1694,7 @@ int symbolize_device(const sp_circuit& c, int outputs, int mode, void* d_work, s
       ra.log = d.log;
       ra.log_words = log_words;
       ra.snap = d.snap;
+      ra.first = d.first;
       ra.E = E;
       ra.n = c.n_qubits;
       ra.DW = L.DW;
