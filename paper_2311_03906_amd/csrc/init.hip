@@ -1235,6 +1235,12 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
         continue;
       }
       join();
+      {
+        // Row p zero in the slice and the variable elsewhere: nothing here
+        // changes (every wave reads the same words, so all skip alike).
+        const uint64_t vp = lane < Ks ? s_P[p * K + lane] : 0ull;
+        if (!in && __ballot(vp != 0) == 0) continue;
+      }
       list(0, m, s_rows, 0);
       if (reset) list(1, m + DW, s_rows2, 1);
       __syncthreads();
