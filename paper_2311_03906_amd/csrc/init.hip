@@ -1124,11 +1124,12 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
       const uint32_t nv = (uint32_t)(h0 >> 32), v0 = (uint32_t)h1;
       const uint64_t off = uni64(e[2]);
       lp += 3;
-      join();
       // One wave per variable word of the slice that the instruction covers;
       // lane l takes variable 64 vw + l, builds its anticommuting-row mask
       // from the snapshots, and the transpose gives each row's bits.
       const uint32_t vw0 = max(v0 >> 6, w_lo), vw1 = min((v0 + nv - 1) >> 6, w_lo + Ks - 1);
+      if (nv == 0 || vw0 > vw1) continue;   // no variable of this slice
+      join();
       for (uint32_t vw = vw0 + wave; vw <= vw1 && vw0 <= vw1; vw += kReplayThreads / 64) {
         const uint32_t v = vw * 64 + lane;
         bool xf = false, zf = false;
