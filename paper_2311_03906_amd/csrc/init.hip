@@ -33,6 +33,13 @@
 // for its own column, a reduction adds the g sums mod 4, and E is the XOR of
 // the selected P rows; recorded outcomes are written as sorted index lists.
 // Reset is measure then X^e; a Pauli controlled by record k is P^{e_k}.
+//
+// Two passes (large phase rows): the tableau never depends on the phases
+// (Fact 2), so a logged pass runs the tableau alone and logs each row
+// operation, and a replay kernel rebuilds the phase rows, each workgroup a
+// slice of their words.  The logged pass takes runs of determined outcomes
+// of one instruction together (the tableau does not change along them),
+// one per wave.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
