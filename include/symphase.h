@@ -211,8 +211,10 @@ int sp_symbolize_device(const sp_circuit* circuit, int outputs, void* d_work, si
  *                     outcomes' rows into index lists;
  *   SP_INIT_AUTO      two passes when the phase rows (n_qubits x
  *                     ceil((variables + 1)/64) words) exceed 1 MiB.
- * The two-pass work buffer holds the log and, after it, the determined
- * recorded outcomes' rows and lists; sp_symbolize_device_work_bytes_mode
+ * The two-pass work buffer holds the log (with the fault snapshots and, per
+ * 64 variables, where the log introduces them, so that each replay slice
+ * starts there) and, after it, the determined recorded outcomes' rows and
+ * lists; sp_symbolize_device_work_bytes_mode
  * sizes that room for every recorded outcome, at most 1 GiB; when a call
  * needs more it fails with SP_E_LIMIT and a message naming a size that
  * suffices ("at least N bytes"). */
