@@ -210,7 +210,7 @@ int sp_symbolize_device(const sp_circuit* circuit, int outputs, void* d_work, si
  *                     LDS, and two small kernels turn the determined
  *                     outcomes' rows into index lists;
  *   SP_INIT_AUTO      two passes when the phase rows (n_qubits x
- *                     ceil((variables + 1)/64) words) exceed 1 MiB.
+ *                     ceil((variables + 1)/64) words) exceed 64 KiB.
  * The two-pass work buffer holds the log (with the fault snapshots and, per
  * 64 variables, where the log introduces them, so that each replay slice
  * starts there) and, after it, the determined recorded outcomes' rows and

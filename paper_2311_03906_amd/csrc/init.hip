@@ -1577,13 +1577,17 @@ size_t default_tail(const DevProgram& P, bool two_pass) {
 }
 
 // Two passes pay unless the phase rows are small: the one-pass kernel
-// updates them from one CU, the replay from every CU (measured: even at
-// surface d=15, 5.7 MB of rows, the two are even; 3c n=400, 7.7x).
+// updates them from one CU, the replay from every CU, and the logged pass
+// takes runs of determined outcomes together.  Measured end to end: surface
+// d=7 (122 KB of rows) 2.6 ms one pass, 1.4 ms two; d=15 (5.7 MB) 31 and 10
+// ms; layered random 3c n=100 (252 KB) 3.9 and 3.5 ms; below 64 KB the
+// random-outcome-heavy circuits (3a/3b n = 60-200, 2-52 KB) are 5-25%
+// faster in one pass.
 bool pick_two_pass(const sp_circuit& c, const DevProgram& P, int mode) {
   if (mode == SP_INIT_ONE_PASS) return false;
   if (mode == SP_INIT_TWO_PASS) return true;
   const uint64_t W = (P.max_vars + 64) / 64;
-  return (uint64_t)c.n_qubits * W * 8 > (1ull << 20);
+  return (uint64_t)c.n_qubits * W * 8 > (64ull << 10);
 }
 
 #define HIP_TRY(expr)                                                                           \
