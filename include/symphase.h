@@ -14,6 +14,7 @@
  *   sp_symbolize_device               the same Initialization on the GPU
  *   sp_model_upload                   make (M, c, P_C) resident on the GPU
  *   sp_sample                         Sampling, on the GPU (Section 3.2.3, Eq. 4)
+ *   sp_sample_host                    the same Sampling on the host CPU
  *
  * Conventions
  *   - Every function returns SP_OK (0) or a negative SP_E_* code; the message
@@ -215,13 +216,19 @@ int sp_symbolize_device(const sp_circuit* circuit, int outputs, void* d_work, si
  * 64 variables, where the log introduces them, so that each replay slice
  * starts there) and, after it, the determined recorded outcomes' rows and
  * lists; sp_symbolize_device_work_bytes_mode
- * sizes that room for every recorded outcome, at most 1 GiB; when a call
- * needs more it fails with SP_E_LIMIT and a message naming a size that
- * suffices ("at least N bytes"). */
+ * sizes that room for every recorded outcome, at most 1 GiB; a call that
+ * needs more fails with SP_E_LIMIT.
+ *
+ * need_bytes (nullable, host): set on every return.  When the call fails
+ * because work_bytes is too small -- SP_E_INVALID for the fixed part,
+ * SP_E_LIMIT for the rows and lists of determined outcomes -- it holds a
+ * work-buffer size that suffices for the failed step (a second call with
+ * that size may still name a larger one once the lists' length is known);
+ * otherwise 0. */
 enum { SP_INIT_AUTO = 0, SP_INIT_ONE_PASS = 1, SP_INIT_TWO_PASS = 2 };
 int sp_symbolize_device_work_bytes_mode(const sp_circuit* circuit, int mode, size_t* bytes);
 int sp_symbolize_device_mode(const sp_circuit* circuit, int outputs, int mode, void* d_work, size_t work_bytes,
-                             void* stream, sp_model** out);
+                             void* stream, sp_model** out, size_t* need_bytes);
 
 int sp_model_dims(const sp_model* model, sp_dims* out);
 
@@ -285,6 +292,22 @@ int sp_dmodel_tiles(const sp_dmodel* dmodel, uint32_t* n_tiles, uint32_t* rows_m
  * Errors: SP_E_INVALID, SP_E_LIMIT, SP_E_DEVICE. */
 int sp_sample(const sp_dmodel* dmodel, uint64_t seed, uint64_t first_shot, uint64_t shots,
               uint64_t* d_out, size_t ld_words, void* stream);
+
+/* Algorithm 1, Sampling, on the host CPU: the same draws, the same product
+ * out = M s + c over GF(2) (Section 3.2.3, Eq. 4) and the same output as
+ * sp_sample, computed from the host model's column lists by n_threads
+ * threads (<= 0: one per hardware thread), 64 shots per word at a time (the
+ * paper's own sampler is a sparse product on a CPU, Section 5).  h_out is
+ * host memory of n_meas rows of ld_words uint64 words, laid out as for
+ * sp_sample (ld_words >= ceil(shots/64); bits of shots >= `shots` written as
+ * 0, words past the last one untouched).  Synchronous.  The result is a pure
+ * function of (model, seed, first_shot, shots): bit for bit what sp_sample
+ * writes for the same arguments.  shots = 0 is a no-op.  It is a separate
+ * entry point, never a fallback: sp_sample does not call it.
+ * Errors: SP_E_INVALID (null, ld_words too small, shot range past 2^64),
+ * SP_E_LIMIT, SP_E_NOMEM. */
+int sp_sample_host(const sp_model* model, uint64_t seed, uint64_t first_shot, uint64_t shots, uint64_t* h_out,
+                   size_t ld_words, int n_threads);
 
 /* Launch shape of the sampling kernel: a workgroup of waves_per_group
  * wave64s (1..16) owns words_per_group (1, 2 or 4) consecutive 64-shot words,

@@ -10,7 +10,6 @@ fallback: without the built library, importing the binding raises.
 from __future__ import annotations
 
 import ctypes
-import re
 
 import numpy as np
 import torch
@@ -121,21 +120,24 @@ class Model:
             n = ctypes.c_size_t()
             check(lib().sp_symbolize_device_work_bytes_mode(circuit.handle, mode, ctypes.byref(n)))
             size = n.value
+            need = ctypes.c_size_t()
             with torch.cuda.device(device):
-                for attempt in range(2):   # the two-pass mode may name a larger buffer once
+                # A too-small buffer fails with the size that suffices for the
+                # failed step; the lists' length is known only after the
+                # replay, so a second retry may be needed.
+                for attempt in range(3):
                     work = torch.empty(size + 256, dtype=torch.uint8, device=device)
                     base = work.data_ptr()
                     off = (-base) % 256
                     rc = lib().sp_symbolize_device_mode(circuit.handle, _OUTPUTS[outputs], mode,
                                                         ctypes.c_void_p(base + off), size,
-                                                        ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h))
+                                                        ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h),
+                                                        ctypes.byref(need))
                     del work
-                    msg = lib().sp_last_error().decode(errors="replace") if rc else ""
-                    need = re.search(r"at least (\d+) bytes", msg) if rc == _capi.SP_E_LIMIT else None
-                    if need is None or attempt == 1:
+                    if rc == _capi.SP_OK or need.value <= size or attempt == 2:
                         check(rc)
                         break
-                    size = int(need.group(1)) + (1 << 20)
+                    size = need.value
         self._h = h
         d = sp_dims()
         check(lib().sp_model_dims(h, ctypes.byref(d)))
@@ -176,6 +178,16 @@ class Model:
         vb = np.zeros(max(1, self.n_vars), dtype=np.uint8)
         check(lib().sp_model_export_vars(self._h, vl.ctypes.data, vb.ctypes.data))
         return vl[: self.n_vars], vb[: self.n_vars]
+
+    def sample_host(self, shots: int, seed: int = 0, first_shot: int = 0, ld: int | None = None,
+                    n_threads: int = 0) -> np.ndarray:
+        """Sampling on the host CPU (sp_sample_host): packed outcomes
+        (n_meas, ld) uint64, bit for bit what DeviceModel.sample writes."""
+        words = (shots + 63) // 64
+        ld = max(words, 1) if ld is None else ld
+        out = np.zeros((max(self.n_meas, 1), ld), dtype=np.uint64)
+        check(lib().sp_sample_host(self._h, seed, first_shot, shots, out.ctypes.data, ld, n_threads))
+        return out[: self.n_meas]
 
     def device_bytes(self, path: str = "auto", tile_rows: int = 0) -> int:
         n = ctypes.c_size_t()

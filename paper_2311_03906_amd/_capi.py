@@ -30,7 +30,7 @@ EXPORTS = (
     "sp_model_export_dense", "sp_model_export_csc", "sp_model_export_vars", "sp_model_device_bytes",
     "sp_model_upload", "sp_model_device_bytes_tiled", "sp_model_upload_tiled", "sp_dmodel_free", "sp_dmodel_dims",
     "sp_dmodel_tiles", "sp_dmodel_get_launch", "sp_dmodel_set_launch",
-    "sp_sample", "sp_batch_work_bytes", "sp_batch_create", "sp_batch_info", "sp_batch_launch", "sp_batch_free",
+    "sp_sample", "sp_sample_host", "sp_batch_work_bytes", "sp_batch_create", "sp_batch_info", "sp_batch_launch", "sp_batch_free",
     "sp_graph_capture_batch", "sp_graph_capture_plain", "sp_graph_launch", "sp_graph_free",
     "sp_server_work_bytes", "sp_server_create", "sp_server_submit", "sp_server_status", "sp_server_wait",
     "sp_server_release", "sp_server_stats", "sp_server_destroy", "sp_last_error",
@@ -101,7 +101,7 @@ def lib():
         "sp_symbolize_device_work_bytes": ([vp, P(sz)], ctypes.c_int),
         "sp_symbolize_device": ([vp, ctypes.c_int, vp, sz, vp, P(vp)], ctypes.c_int),
         "sp_symbolize_device_work_bytes_mode": ([vp, ctypes.c_int, P(sz)], ctypes.c_int),
-        "sp_symbolize_device_mode": ([vp, ctypes.c_int, ctypes.c_int, vp, sz, vp, P(vp)], ctypes.c_int),
+        "sp_symbolize_device_mode": ([vp, ctypes.c_int, ctypes.c_int, vp, sz, vp, P(vp), P(sz)], ctypes.c_int),
         "sp_circuit_counts": ([vp, P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32)],
                               ctypes.c_int),
         "sp_model_free": ([vp], None),
@@ -120,6 +120,7 @@ def lib():
         "sp_dmodel_get_launch": ([vp, P(sp_launch)], ctypes.c_int),
         "sp_dmodel_set_launch": ([vp, P(sp_launch)], ctypes.c_int),
         "sp_sample": ([vp, u64, u64, u64, vp, sz, vp], ctypes.c_int),
+        "sp_sample_host": ([vp, u64, u64, u64, vp, sz, ctypes.c_int], ctypes.c_int),
         "sp_batch_work_bytes": ([vp, sz, vp, ctypes.c_int, P(sz)], ctypes.c_int),
         "sp_batch_create": ([vp, sz, vp, ctypes.c_int, vp, sz, vp, P(vp)], ctypes.c_int),
         "sp_batch_info": ([vp, P(u32), P(u32), P(u32), P(sp_launch)], ctypes.c_int),

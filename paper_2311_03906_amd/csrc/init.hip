@@ -1048,6 +1048,11 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
   const uint64_t start = f0 ? min(f0 - 1, r.log_words) : 0;
   uint64_t win_lo = start, win_hi = start;
   bool solo_wrote = false;   // wave 0 wrote alone since the last barrier (uniform)
+  // Every wave read row p of the slice to decide a skip since the last
+  // barrier (uniform).  Any write to the slice must wait until all waves are
+  // past that read: a wave that saw the row already changed would not skip,
+  // and the waves would no longer meet the same barriers.
+  bool read_pending = false;
 
   // Wave `wv` lists the set bits of a logged mask (DW words at m) into dst.
   auto list = [&](uint32_t wv, const uint64_t* m, uint32_t* dst, uint32_t slot) {
@@ -1104,8 +1109,15 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
   };
   // Before a step that other waves take part in.
   auto join = [&]() {
-    if (solo_wrote) __syncthreads();
+    if (solo_wrote || read_pending) __syncthreads();
     solo_wrote = false;
+    read_pending = false;
+  };
+  // Before wave 0 writes alone: every wave takes this barrier or none does,
+  // since the skip that set read_pending was taken by all of them.
+  auto settle = [&]() {
+    if (read_pending) __syncthreads();
+    read_pending = false;
   };
   const bool w0 = wave == 0, mine = w0 && lane < Ks;   // wave 0's lane = slice word
   __syncthreads();
@@ -1117,6 +1129,7 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
     if (lp + max_entry > win_hi && win_hi < r.log_words) {
       __syncthreads();   // every wave is done with the old window
       solo_wrote = false;
+      read_pending = false;
       win_lo = lp;
       win_hi = min(lp + (uint64_t)kLogWindow, r.log_words);
       for (uint32_t i = tid; i < win_hi - win_lo; i += kReplayThreads) s_log[i] = r.log[win_lo + i];
@@ -1228,6 +1241,7 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
       // becomes the fresh variable, which a reset then adds to the rows with
       // z_a instead.
       if (bits(m) + (reset ? bits(m + DW) : 0u) <= kShortRows) {
+        settle();
         if (w0) {
           const uint64_t vp = mine ? s_P[p * K + lane] : 0ull;
           for_bits(m, [&](uint32_t i) {
@@ -1247,7 +1261,10 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
         // Row p zero in the slice and the variable elsewhere: nothing here
         // changes (every wave reads the same words, so all skip alike).
         const uint64_t vp = lane < Ks ? s_P[p * K + lane] : 0ull;
-        if (!in && __ballot(vp != 0) == 0) continue;
+        if (!in && __ballot(vp != 0) == 0) {
+          read_pending = true;
+          continue;
+        }
       }
       list(0, m, s_rows, 0);
       if (reset) list(1, m + DW, s_rows2, 1);
@@ -1266,6 +1283,7 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
       lp += 2 + (reset ? 2u : 1u) * DW;
       // E = XOR of the selected rows; a reset adds it to the rows with z_a.
       if (bits(m) + (reset ? bits(m + DW) : 0u) <= kShortRows) {
+        settle();
         if (w0) {
           uint64_t ev = 0;
           for_bits(m, [&](uint32_t i) {
@@ -1330,6 +1348,7 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
     const uint32_t vk = (hi >> 6) - w_lo;
     const uint64_t vb = 1ull << (hi & 63);
     if (bits(m) <= kShortRows) {
+      settle();
       if (w0) {
         if (kind == LOG_FB_DET) {
           const uint64_t ev = mine ? r.E[(size_t)hi * r.W + w_lo + lane] : 0ull;   // written by this lane
@@ -1621,16 +1640,21 @@ int launch_init(const InitDev& d, uint32_t n, uint32_t RW, hipStream_t s) {
   return SP_OK;
 }
 
+// *need: a work-buffer size that suffices, when the call fails because the
+// buffer is too small (SP_E_INVALID for the fixed part, SP_E_LIMIT for the
+// lists); left 0 otherwise.
 int symbolize_device(const sp_circuit& c, int outputs, int mode, void* d_work, size_t work_bytes, hipStream_t s,
-                     sp_model** out) {
+                     sp_model** out, size_t* need) {
   const DevProgram P = compile(c);
   if (P.max_vars >= (1ull << 24)) return set_error(SP_E_LIMIT, "more than 2^24 variables");
   if (P.n_locs != c.n_locs || P.n_rec != c.n_meas) return set_error(SP_E_INVALID, "inconsistent circuit");
   const bool two = pick_two_pass(c, P, mode);
   const InitLayout L = layout(c, P, two, 0, work_bytes);
-  if (L.total > work_bytes)
+  if (L.total > work_bytes) {
+    *need = L.total;
     return set_error(SP_E_INVALID, "work buffer of " + std::to_string(work_bytes) + " bytes, need at least " +
                                        std::to_string(L.total));
+  }
   uint8_t* base = (uint8_t*)d_work;
   HIP_TRY(hipMemsetAsync(base, 0, L.list, s));
   if (!P.words.empty()) HIP_TRY(hipMemcpyAsync(base + L.ops, P.words.data(), 4 * P.words.size(), hipMemcpyHostToDevice, s));
@@ -1679,11 +1703,12 @@ int symbolize_device(const sp_circuit& c, int outputs, int mode, void* d_work, s
   std::vector<uint32_t> list;
 
   if (!two) {
-    if (status[3])
+    if (status[3]) {
+      *need = layout(c, P, false, (size_t)std::min<uint64_t>(P.list_bound, 0xFFFFFFFFull), 0).total;
       return set_error(SP_E_LIMIT, "determined outcomes need more index-list room than the work buffer has (" +
-                                       std::to_string(L.list_cap) + " entries); at most " +
-                                       std::to_string(layout(c, P, false, (size_t)std::min<uint64_t>(P.list_bound, 0xFFFFFFFFull), 0).total) +
+                                       std::to_string(L.list_cap) + " entries); at most " + std::to_string(*need) +
                                        " bytes suffice");
+    }
     list.resize(status[2]);
     if (status[2]) {
       HIP_TRY(hipMemcpyAsync(list.data(), base + L.list, 4ull * status[2], hipMemcpyDeviceToHost, s));
@@ -1697,9 +1722,14 @@ int symbolize_device(const sp_circuit& c, int outputs, int mode, void* d_work, s
     // After the fixed part: rows of E, then counts and offsets, then the lists.
     const size_t e_off = L.list, cnt_off = align256(e_off + 8ull * n_det * Wu), ofs_off = align256(cnt_off + 4ull * n_det);
     const size_t lst_off = align256(ofs_off + 4ull * n_det);
-    if (lst_off > work_bytes)
+    if (lst_off > work_bytes) {
+      // The lists' length is known only after the replay; their bound is
+      // every determined outcome holding every variable.
+      *need = align256(lst_off + 4 * std::min<uint64_t>(P.list_bound, (uint64_t)n_det * n_vars));
       return set_error(SP_E_LIMIT, "the replay needs a work buffer of at least " + std::to_string(lst_off) +
-                                       " bytes plus room for the index lists");
+                                       " bytes plus room for the index lists; " + std::to_string(*need) +
+                                       " bytes suffice");
+    }
     uint64_t* E = (uint64_t*)(base + e_off);
     if (n_det) HIP_TRY(hipMemsetAsync(E, 0, 8ull * n_det * Wu, s));   // slices skip the entries before their variables
     if (log_words) {
@@ -1739,9 +1769,11 @@ int symbolize_device(const sp_circuit& c, int outputs, int mode, void* d_work, s
         total += counts[i];
         if (total > 0xFFFFFFFFull) return set_error(SP_E_LIMIT, "more than 2^32 list entries");
       }
-      if (lst_off + 4 * total > work_bytes)
-        return set_error(SP_E_LIMIT, "the replay needs a work buffer of at least " +
-                                         std::to_string(align256(lst_off + 4 * total)) + " bytes");
+      if (lst_off + 4 * total > work_bytes) {
+        *need = align256(lst_off + 4 * total);
+        return set_error(SP_E_LIMIT, "the replay needs a work buffer of at least " + std::to_string(*need) +
+                                         " bytes");
+      }
       list.resize(total);
       if (total) {
         HIP_TRY(hipMemcpyAsync(d_offsets, offsets.data(), 4ull * n_det, hipMemcpyHostToDevice, s));
@@ -1798,7 +1830,9 @@ int sp_symbolize_device_work_bytes(const sp_circuit* circuit, size_t* bytes) {
 }
 
 int sp_symbolize_device_mode(const sp_circuit* circuit, int outputs, int mode, void* d_work, size_t work_bytes,
-                             void* stream, sp_model** out) {
+                             void* stream, sp_model** out, size_t* need_bytes) {
+  size_t need = 0;
+  if (need_bytes) *need_bytes = 0;
   if (!circuit || !out || !d_work) return set_error(SP_E_INVALID, "null argument");
   *out = nullptr;
   if (outputs != SP_OUT_MEASUREMENTS && outputs != SP_OUT_DETECTORS)
@@ -1807,7 +1841,9 @@ int sp_symbolize_device_mode(const sp_circuit* circuit, int outputs, int mode, v
   if (((uintptr_t)d_work & 255u) != 0) return set_error(SP_E_INVALID, "work buffer must be 256-byte aligned");
   if (int rc = check_circuit(circuit)) return rc;
   try {
-    return symbolize_device(*circuit, outputs, mode, d_work, work_bytes, (hipStream_t)stream, out);
+    const int rc = symbolize_device(*circuit, outputs, mode, d_work, work_bytes, (hipStream_t)stream, out, &need);
+    if (need_bytes) *need_bytes = need;
+    return rc;
   } catch (const sp::Error& e) {
     return set_error(e.code, e.what());
   } catch (const std::bad_alloc&) {
@@ -1817,7 +1853,7 @@ int sp_symbolize_device_mode(const sp_circuit* circuit, int outputs, int mode, v
 
 int sp_symbolize_device(const sp_circuit* circuit, int outputs, void* d_work, size_t work_bytes, void* stream,
                         sp_model** out) {
-  return sp_symbolize_device_mode(circuit, outputs, SP_INIT_AUTO, d_work, work_bytes, stream, out);
+  return sp_symbolize_device_mode(circuit, outputs, SP_INIT_AUTO, d_work, work_bytes, stream, out, nullptr);
 }
 
 }  // extern "C"

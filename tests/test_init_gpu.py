@@ -10,7 +10,6 @@ sampling the device-built model on the GPU against the oracle."""
 from __future__ import annotations
 
 import ctypes
-import re
 import sys
 
 import numpy as np
@@ -272,15 +271,24 @@ def test_index_list_overflow_is_reported():
     work = torch.zeros(need.value + 256, dtype=torch.uint8, device="cuda")
     base = ctypes.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
     h = ctypes.c_void_p()
-    # too small for the fixed part: rejected before any device work
-    assert L.sp_symbolize_device(c.handle, 0, base, 256, None, ctypes.byref(h)) == _capi.SP_E_INVALID
-    fixed = int(re.search(r"need at least (\d+)", L.sp_last_error().decode()).group(1))
+    one = _capi.SP_INIT_ONE_PASS
+    got = ctypes.c_size_t(12345)
+    # too small for the fixed part: rejected before any device work, with
+    # the size that suffices in the out-parameter and the message
+    assert L.sp_symbolize_device_mode(c.handle, 0, one, base, 256, None, ctypes.byref(h),
+                                      ctypes.byref(got)) == _capi.SP_E_INVALID
+    fixed = got.value
+    assert str(fixed).encode() in L.sp_last_error()
     assert 256 < fixed < need.value
     _say("device init list overflow")
-    assert L.sp_symbolize_device(c.handle, 0, base, fixed, None, ctypes.byref(h)) == _capi.SP_E_LIMIT
-    enough = int(re.search(r"at most (\d+) bytes suffice", L.sp_last_error().decode()).group(1))
-    assert enough <= need.value
-    _capi.check(L.sp_symbolize_device(c.handle, 0, base, enough, None, ctypes.byref(h)))
+    assert L.sp_symbolize_device_mode(c.handle, 0, one, base, fixed, None, ctypes.byref(h),
+                                      ctypes.byref(got)) == _capi.SP_E_LIMIT
+    enough = got.value
+    assert str(enough).encode() + b" bytes suffice" in L.sp_last_error()
+    assert fixed < enough <= need.value
+    _capi.check(L.sp_symbolize_device_mode(c.handle, 0, one, base, enough, None, ctypes.byref(h),
+                                           ctypes.byref(got)))
+    assert got.value == 0
     try:
         ref = sp.Model(text)
         d = _capi.sp_dims()
@@ -318,19 +326,26 @@ def test_two_pass_buffer_too_small_is_reported():
     work = torch.zeros(need.value + 256, dtype=torch.uint8, device="cuda")
     base = ctypes.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
     h = ctypes.c_void_p()
-    assert L.sp_symbolize_device_mode(c.handle, 0, two, base, 256, None, ctypes.byref(h)) == _capi.SP_E_INVALID
-    fixed = int(re.search(r"need at least (\d+)", L.sp_last_error().decode()).group(1))
+    got = ctypes.c_size_t()
+    assert L.sp_symbolize_device_mode(c.handle, 0, two, base, 256, None, ctypes.byref(h),
+                                      ctypes.byref(got)) == _capi.SP_E_INVALID
+    fixed = got.value
+    assert b"need at least %d" % fixed in L.sp_last_error()
     _say("two-pass buffer too small")
-    assert L.sp_symbolize_device_mode(c.handle, 0, two, base, fixed, None, ctypes.byref(h)) == _capi.SP_E_LIMIT
-    enough = int(re.search(r"at least (\d+) bytes", L.sp_last_error().decode()).group(1))
+    assert L.sp_symbolize_device_mode(c.handle, 0, two, base, fixed, None, ctypes.byref(h),
+                                      ctypes.byref(got)) == _capi.SP_E_LIMIT
+    enough = got.value
+    assert b"%d bytes" % enough in L.sp_last_error()
     assert fixed < enough <= need.value
-    # the first figure covers the rows of E; the lists may name a larger one
-    rc = L.sp_symbolize_device_mode(c.handle, 0, two, base, enough, None, ctypes.byref(h))
+    # the figure covers the rows of E and a bound on the lists; a size that
+    # fits the lists' bound but not their real length would name that length
+    rc = L.sp_symbolize_device_mode(c.handle, 0, two, base, enough, None, ctypes.byref(h), ctypes.byref(got))
     if rc == _capi.SP_E_LIMIT:
-        enough = int(re.search(r"at least (\d+) bytes", L.sp_last_error().decode()).group(1))
-        assert enough <= need.value
-        rc = L.sp_symbolize_device_mode(c.handle, 0, two, base, enough, None, ctypes.byref(h))
+        assert enough < got.value <= need.value
+        enough = got.value
+        rc = L.sp_symbolize_device_mode(c.handle, 0, two, base, enough, None, ctypes.byref(h), ctypes.byref(got))
     _capi.check(rc)
+    assert got.value == 0
     try:
         ref = sp.Model(text)
         d = _capi.sp_dims()

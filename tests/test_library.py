@@ -101,8 +101,15 @@ def test_device_initialization_modes_checked_before_device_work():
     assert sizes[0] == sizes[1]   # a tiny circuit runs in one pass
     need = ctypes.c_size_t()
     assert L.sp_symbolize_device_work_bytes_mode(c.handle, 3, ctypes.byref(need)) == E.SP_E_INVALID
-    assert L.sp_symbolize_device_mode(c.handle, 0, 3, fake, 1 << 30, None, ctypes.byref(h)) == E.SP_E_INVALID
+    got = ctypes.c_size_t(7)
+    assert L.sp_symbolize_device_mode(c.handle, 0, 3, fake, 1 << 30, None, ctypes.byref(h),
+                                      ctypes.byref(got)) == E.SP_E_INVALID
+    assert got.value == 0   # not a size error
     assert L.sp_symbolize_device_mode(c.handle, 0, E.SP_INIT_TWO_PASS, fake, 256, None,
-                                      ctypes.byref(h)) == E.SP_E_INVALID
-    assert b"need at least" in L.sp_last_error()
+                                      ctypes.byref(h), ctypes.byref(got)) == E.SP_E_INVALID
+    # the size that suffices comes back in the out-parameter (and the message)
+    assert 256 < got.value <= sizes[2]
+    assert b"need at least %d" % got.value in L.sp_last_error()
+    assert L.sp_symbolize_device_mode(c.handle, 0, E.SP_INIT_TWO_PASS, fake, 256, None,
+                                      ctypes.byref(h), None) == E.SP_E_INVALID
     assert h.value is None
