@@ -17,10 +17,11 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsymphase_hip.so")
 
 ARCH = os.environ.get("SYMPHASE_ARCH", "gfx950")
-HOST_SRCS = ["circuit.cpp", "symbolize.cpp", "api.cpp"]
+HOST_SRCS = ["circuit.cpp", "symbolize.cpp", "api.cpp", "sample_host.cpp"]
 HIP_SRCS = ["sample.hip", "batch.hip", "server.hip", "init.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include")]
+HOST_FLAGS = ["-pthread"]
 # Packed FP32 instructions are disabled for all device code.
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]
@@ -38,7 +39,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     cmds, objs = [], []
     for s in HOST_SRCS:
         o = os.path.join(BUILD, s + ".o")
-        cmds.append(["g++"] + COMMON + ["-c", os.path.join(CSRC, s), "-o", o])
+        cmds.append(["g++"] + COMMON + HOST_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
     for s in HIP_SRCS:
         o = os.path.join(BUILD, s + ".o")
@@ -49,7 +50,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             if verbose:
                 print(" ".join(c))
     tmp = LIB + ".tmp"
-    _run(["hipcc", "-shared", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-Wl,-rpath,/opt/rocm/lib"])
+    _run(["hipcc", "-shared", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-pthread", "-Wl,-rpath,/opt/rocm/lib"])
     os.replace(tmp, LIB)
     return LIB
 
