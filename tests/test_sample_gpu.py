@@ -165,35 +165,70 @@ def test_surface_d5_million_shots_sampled():
     assert got.shape[1] == 15625
 
 
+def _d15_oracle_ids(shots, n_words_run, total, seed):
+    """Shots of a 2^20-shot d=15 batch for the oracle: every lane of the
+    first and last word, lanes 0, 31 and 63 of the first and last word of
+    every run of consecutive words one XCD takes (default launch: one word
+    per workgroup, runs of n_words_run words), then seeded-random shots up to
+    `total`."""
+    words = (shots + 63) // 64
+    fixed = set(range(64)) | set(range(64 * (words - 1), shots))
+    for w0 in range(0, words, n_words_run):
+        for w in (w0, min(words, w0 + n_words_run) - 1):
+            fixed |= {64 * w + 0, 64 * w + 31, min(shots - 1, 64 * w + 63)}
+    rng = np.random.default_rng(seed)
+    ids = set(fixed)
+    while len(ids) < total:
+        ids |= set(int(x) for x in rng.choice(shots, total - len(ids), replace=False))
+    return np.array(sorted(ids), dtype=np.int64)
+
+
+
 @pytest.mark.parametrize("p", ["0.001", "0.005"])
-def test_surface_d15_batch_sampled(p):
-    """Surface d=15, 15 rounds: one 2^20-shot batch at first_shot = 3 * 2^20;
-    sampled shots (first, last, random) equal the oracle."""
+def test_surface_d15_full_batch_both_paths(p):
+    """Surface d=15, 15 rounds (3,585 rows, 101,489 variables), one whole
+    2^20-shot batch at first_shot = 3 * 2^20, on the sparse (column-list)
+    and the dense (bit-mask) path: every word of both equals the host
+    sampler's (sp_sample_host, the same Eq. 4 from the host model), and 4,096
+    shots spread over every XCD's run of words equal the oracle's."""
     text = surface_memory(15, 15, p).text()
-    _say(f"surface d15 p={p} 2^20 shots sampled")
-    m, dm, oc = _models(text)
+    m = sp.Model(text)
     shots, first = 1 << 20, 3 << 20
-    got = _gpu(dm, shots, seed=0, first_shot=first)
-    assert got.shape == (3585, 16384)
-    rng = np.random.default_rng(1)
-    idx = np.concatenate([[0, 1, 63, 64], [shots - 1, shots - 64], rng.choice(shots, 58, replace=False)])
-    want = oc.sample_shots(0, first + idx)
-    for i, s in enumerate(idx):
-        assert np.array_equal(_column(got, int(s)), want[i]), int(s)
+    _say(f"surface d15 p={p} 2^20 shots: host sampler")
+    host = m.sample_host(shots, seed=0, first_shot=first)
+    assert host.shape == (3585, 16384)
+    for path in ("sparse", "dense"):
+        _say(f"surface d15 p={p} 2^20 shots: GPU {path}")
+        dm = sp.DeviceModel(m, path=path)
+        assert dm.launch == (8, 1) and dm.n_tiles == 1
+        got = _gpu(dm, shots, seed=0, first_shot=first)
+        bad = np.nonzero((got != host).any(axis=0))[0]
+        assert bad.size == 0, (path, bad[:10])
+        del dm, got
+    ids = _d15_oracle_ids(shots, 16384 // 8, 4096, seed=int(float(p) * 1e4))
+    _say(f"surface d15 p={p}: oracle on {len(ids)} shots")
+    want = oracle.Circuit(text).sample_shots(0, first + ids)
+    for i, s in enumerate(ids):
+        assert np.array_equal(_column(host, int(s)), want[i]), int(s)
 
 
-def test_surface_d15_last_partial_batch_sampled():
-    """The last batch of 10^7 shots: 562,816 shots at first_shot = 9 * 2^20."""
-    text = surface_memory(15, 15, 1e-3).text()
-    _say("surface d15 tail batch sampled")
-    m, dm, oc = _models(text)
+def test_surface_d15_last_partial_batch():
+    """The last batch of 10^7 shots, 562,816 shots at first_shot = 9 * 2^20:
+    every word equals the host sampler's, and 512 of its shots (the first and
+    last 64, and random ones) equal the oracle's."""
+    text = surface_memory(15, 15, "0.001").text()
+    _say("surface d15 tail batch")
+    m, dm, oc = _models(text, "sparse")
     shots, first = 10_000_000 - 9 * (1 << 20), 9 << 20
     got = _gpu(dm, shots, seed=0, first_shot=first)
-    idx = np.array([0, shots // 2, shots - 1, shots - 2, shots - 64])
+    assert shots % 64 == 0 and got.shape[1] == shots // 64
+    assert np.array_equal(got, m.sample_host(shots, seed=0, first_shot=first))
+    rng = np.random.default_rng(9)
+    idx = np.unique(np.concatenate([np.arange(64), np.arange(shots - 64, shots),
+                                    rng.choice(shots, 384, replace=False)]))
     want = oc.sample_shots(0, first + idx)
     for i, s in enumerate(idx):
         assert np.array_equal(_column(got, int(s)), want[i]), int(s)
-    assert shots % 64 == 0 and got.shape[1] == shots // 64
 
 
 def test_surface_d7_ragged_batch():

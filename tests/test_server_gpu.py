@@ -65,6 +65,53 @@ def test_results_identical_alone_and_in_mix():
     srv.close()
 
 
+def test_d15_pool_alone_and_in_mix():
+    """The serving pool's own circuits (rotated surface code d=15, 15 rounds,
+    3,585 rows): five of them, one uploaded as two row tiles, serve 16
+    requests of 10^3 to 10^5 shots with a small tick budget, so that the
+    larger requests span several ticks while others are admitted.  Each
+    output equals the same request sampled alone, word for word, and 16
+    shots of each of four requests equal the oracle's."""
+    from workloads.circuits import serving_pool
+    pool = serving_pool(0)[:5]
+    _say("server: d15 pool, 5 models")
+    models = []
+    for i, c in enumerate(pool):
+        m = sp.Model(c["circuit"].text())
+        dm = sp.DeviceModel(m, path="sparse", tile_rows=2048 if i == 4 else 0)
+        models.append((c, m, dm))
+    assert models[4][2].n_tiles == 2 and all(x[2].n_tiles == 1 for x in models[:4])
+    rng = np.random.default_rng(3)
+    srv = sp.Server(arena_bytes=2 << 30, max_active=6, tick_cost=1 << 22)
+    reqs = []
+    for i in range(16):
+        k = i % len(models)
+        shots = 100_000 if i == 0 else int(10 ** rng.uniform(3, 5))
+        first = int(rng.integers(0, 1 << 36))
+        reqs.append((srv.submit(models[k][2], shots, seed=1000 + i, first_shot=first), k, shots, 1000 + i, first))
+    for n, (t, k, shots, seed, first) in enumerate(reqs):
+        st = srv.wait(t, timeout_ms=120_000)
+        assert st["state"] == "done"
+        got = srv.output(st).clone()
+        srv.release(t)
+        c, m, dm = models[k]
+        assert torch.equal(got, _alone(dm, shots, seed, first)), (k, seed, shots)
+        if n < 4:
+            _say(f"server: d15 request {n} (model {k}, {shots} shots) vs oracle, 16 shots")
+            ids = np.concatenate([[0, shots - 1], np.random.default_rng(n).choice(shots, 14, replace=False)])
+            want = oracle.Circuit(c["circuit"].text()).sample_shots(seed, first + ids)
+            packed = sp.to_numpy_bits(got)
+            for j, s in enumerate(ids):
+                col = ((packed[:, int(s) // 64] >> np.uint64(int(s) % 64)) & np.uint64(1)).astype(np.uint8)
+                assert np.array_equal(col, want[j]), (n, int(s))
+    stats = srv.stats()
+    # the 10^5-shot request alone needs 1,563 words x 10,502 blocks, four
+    # ticks' budget and more
+    assert stats["ticks"] >= 4
+    assert stats["queued"] == 0 and stats["active"] == 0 and stats["arena_in_use"] == 0
+    srv.close()
+
+
 def test_small_request_against_oracle():
     text = surface_memory(3, 3, "0.03").text()
     _, dm = _model(text)
