@@ -14,14 +14,14 @@ namespace sp {
 
 // Device model: every section lives in the caller's buffer.
 struct DevModel {
-  const uint4* hot;          // [nb][2]: tm1[4] | (blk, 0, 0, 0), read for every block
+  const uint4* hot;          // [nb + kHotPad][2]: tm1[4] | (blk, 0, 0, 0), read for every block
   const uint4* cold;         // [nb][4]: meta[4] | lst[0..3] | (lst[4], 0, 0, 0) | 0, read when a block fires
   const uint32_t* entries;   // merged (row << 5 | bit) lists, one per drawn location
   const uint32_t* chans;     // [nch][16]: kind | m << 8, T_1..T_{m-1}, then 0xFFFFFFFF
   const uint64_t* c_mask;    // [ceil(n_meas/64)]
   const uint64_t* dense;     // [n_vars][dense_words] (dense path only)
   uint32_t nb, n_meas, dense_words, nch;
-  uint32_t defer_max;        // fired lanes up to which a location is queued rather than evaluated at once
+  uint32_t nb_lazy;          // blocks [0, nb_lazy) are lazy, [nb_lazy, nb) eager (sparse path)
 };
 
 // One sampling job: a model, an output and a shot range.
@@ -84,11 +84,18 @@ struct BatchCounters {
 
 int set_error(int code, const std::string& msg);
 
-// Events a wave queues before it evaluates them (sparse path).
+// Records a wave queues before it evaluates them (sparse path): one per
+// (block, word, lane) with a fired location, 16 bytes of draws and a 4-byte
+// tag.
 constexpr uint32_t kQueueCap = 64;
+constexpr uint32_t kQueueRecBytes = 20;
 
-// LDS bytes of one workgroup: its slabs, then (sparse path) one event
-// queue of kQueueCap 8-byte records per wave.
+// Hot records past the last block, so that a wave may load the record one
+// stride ahead of its last block (at most 16 waves) without a bounds test.
+constexpr uint32_t kHotPad = 16;
+
+// LDS bytes of one workgroup: its slabs, then (sparse path) one record
+// queue of kQueueCap records per wave.
 size_t lds_bytes(uint32_t n_meas, uint32_t words_per_group, uint32_t waves_per_group, int path);
 
 // Kernel launchers (sample.hip).

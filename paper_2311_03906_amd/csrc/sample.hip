@@ -232,63 +232,82 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// A fired location with few fired lanes is not evaluated at once: each of
-// its fired lanes queues one 8-byte event {u, block << 10 | slot << 8 |
-// lane << 2 | word} in the wave's LDS queue.  The queue is evaluated with
-// one event per lane: the lane reads its location's channel and list from
-// the block's cold record, finds its code from u, then walks the list and
-// flips its shot's bit in the rows of the code's set bits.  Queueing costs a
-// few instructions per fired location; everything else is shared by up to
-// 64 events.
-__device__ __forceinline__ void flush_events(const DevModel& m, uint64_t* slab, const uint2* q, uint32_t qn,
-                                             uint32_t lane) {
+// Walks the entry list [lo, hi) of one fired location for one shot: flips
+// the shot's bit (`bit`) in the slab rows of the entries whose code bit is
+// set in `code`.  Eight entry loads are kept in flight.
+__device__ __forceinline__ void walk_list(const DevModel& m, uint64_t* sl, uint32_t lo, uint32_t hi, uint32_t code,
+                                          uint64_t bit) {
+  const guint32_p p1 = (guint32_p)m.entries + hi;
+  guint32_p p = (guint32_p)m.entries + lo;
+  for (; p + 8 <= p1; p += 8) {
+    uint32_t e[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) e[i] = p[i];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (__builtin_amdgcn_ubfe(code, e[i], 1)) atomicXor((unsigned long long*)&row_of(sl, e[i]), (unsigned long long)bit);
+  }
+  for (; p + 4 <= p1; p += 4) {
+    const uint32_t e0 = p[0], e1 = p[1], e2 = p[2], e3 = p[3];
+    if (__builtin_amdgcn_ubfe(code, e0, 1)) atomicXor((unsigned long long*)&row_of(sl, e0), (unsigned long long)bit);
+    if (__builtin_amdgcn_ubfe(code, e1, 1)) atomicXor((unsigned long long*)&row_of(sl, e1), (unsigned long long)bit);
+    if (__builtin_amdgcn_ubfe(code, e2, 1)) atomicXor((unsigned long long*)&row_of(sl, e2), (unsigned long long)bit);
+    if (__builtin_amdgcn_ubfe(code, e3, 1)) atomicXor((unsigned long long*)&row_of(sl, e3), (unsigned long long)bit);
+  }
+  for (; p < p1; ++p) {
+    const uint32_t e = *p;
+    if (__builtin_amdgcn_ubfe(code, e, 1)) atomicXor((unsigned long long*)&row_of(sl, e), (unsigned long long)bit);
+  }
+}
+
+// A wave's record queue (sparse path): record i is the four draws of one
+// lane in one block and word, u[i], and its tag t[i] = block << 8 | lane << 2
+// | word.  A lane appends a record when any location of the block fired in
+// its shot; the four draws say which ones did (u <= T_m - 1, with T_m from
+// the block's hot record).
+struct Queue {
+  uint4* u;
+  uint32_t* t;
+};
+
+// Evaluates the queued records, one per lane: the lane reloads its block's
+// thresholds and list bounds, and for every location that fired in its shot
+// finds the Pauli code from the draw (lane_code) and walks the location's
+// list, flipping its shot's bit in the rows of the code's set bits.  A lane
+// with several fired locations takes them one after another.  Everything
+// but the queueing is shared by up to 64 records.
+__device__ __forceinline__ void flush_records(const DevModel& m, uint64_t* slab, const Queue& q, uint32_t qn,
+                                              uint32_t lane) {
   wave_sync();
   if (lane < qn) {
-    const uint2 ev = q[lane];
-    const uint32_t u = ev.x, info = ev.y;
-    const guint32_p cw = (guint32_p)m.cold + (size_t)(info >> 10) * 16u;   // meta[4] | lst[4] | end
-    const uint32_t s = (info >> 8) & 3u;
-    const uint32_t meta = cw[s], lo = cw[4 + s], hi = cw[5 + s];
-    const uint32_t code = lane_code(m.chans, meta & 0xFFu, u);
-    const uint64_t bit = 1ull << ((info >> 2) & 63u);
-    uint64_t* sl = slab + (size_t)(info & 3u) * m.n_meas;
-    const guint32_p p1 = (guint32_p)m.entries + hi;
-    guint32_p p = (guint32_p)m.entries + lo;
-    for (; p + 8 <= p1; p += 8) {   // eight loads in flight
-      uint32_t e[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) e[i] = p[i];
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (__builtin_amdgcn_ubfe(code, e[i], 1)) atomicXor((unsigned long long*)&row_of(sl, e[i]), (unsigned long long)bit);
-    }
-    for (; p + 4 <= p1; p += 4) {   // four loads in flight
-      const uint32_t e0 = p[0], e1 = p[1], e2 = p[2], e3 = p[3];
-      if (__builtin_amdgcn_ubfe(code, e0, 1)) atomicXor((unsigned long long*)&row_of(sl, e0), (unsigned long long)bit);
-      if (__builtin_amdgcn_ubfe(code, e1, 1)) atomicXor((unsigned long long*)&row_of(sl, e1), (unsigned long long)bit);
-      if (__builtin_amdgcn_ubfe(code, e2, 1)) atomicXor((unsigned long long*)&row_of(sl, e2), (unsigned long long)bit);
-      if (__builtin_amdgcn_ubfe(code, e3, 1)) atomicXor((unsigned long long*)&row_of(sl, e3), (unsigned long long)bit);
-    }
-    for (; p < p1; ++p) {
-      const uint32_t e = *p;
-      if (__builtin_amdgcn_ubfe(code, e, 1)) atomicXor((unsigned long long*)&row_of(sl, e), (unsigned long long)bit);
+    const uint4 u = q.u[lane];
+    const uint32_t tag = q.t[lane];
+    const uint32_t b = tag >> 8;
+    const uint4 tm1 = ((guint4_p)m.hot)[(size_t)b * 2u];
+    const guint4_p cw = (guint4_p)m.cold + (size_t)b * 4u;   // meta[4] | lst[4] | end
+    const uint4 meta = cw[0], lst = cw[1];
+    const uint32_t end = ((guint32_p)cw)[8];
+    uint32_t fired = (uint32_t)(u.x <= tm1.x) | (uint32_t)(u.y <= tm1.y) << 1 | (uint32_t)(u.z <= tm1.z) << 2 |
+                     (uint32_t)(u.w <= tm1.w) << 3;
+    const uint64_t bit = 1ull << ((tag >> 2) & 63u);
+    uint64_t* sl = slab + (size_t)(tag & 3u) * m.n_meas;
+    while (fired) {
+      const uint32_t s = (uint32_t)__builtin_ctz(fired);
+      fired &= fired - 1u;
+      const uint32_t us = s == 0 ? u.x : s == 1 ? u.y : s == 2 ? u.z : u.w;
+      const uint32_t mt = s == 0 ? meta.x : s == 1 ? meta.y : s == 2 ? meta.z : meta.w;
+      const uint32_t lo = s == 0 ? lst.x : s == 1 ? lst.y : s == 2 ? lst.z : lst.w;
+      const uint32_t hi = s == 0 ? lst.y : s == 1 ? lst.z : s == 2 ? lst.w : end;
+      // A slot without a drawn location (threshold 0) fires at u = 0 only,
+      // and its list is empty.
+      if (lo != hi) walk_list(m, sl, lo, hi, lane_code(m.chans, mt & 0xFFu, us), bit);
     }
   }
   wave_sync();
 }
 
-// Queues the fired lanes of slot s of word r of block b (fired: this lane
-// drew u <= T_m - 1 there; f: the slot's 64-lane fire mask).
-__device__ __forceinline__ void enqueue(uint2* q, uint32_t qn, uint64_t f, bool fired, uint32_t u, uint32_t tag,
-                                        uint32_t lane4) {
-  if (fired) {
-    const uint32_t pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(f >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)f, 0u));
-    q[pos] = make_uint2(u, tag | lane4);
-  }
-}
-
-// A block's descriptor: the part every block needs (thresholds and the
-// Philox block index, 32 bytes) and the part only fired blocks need
+// A block's descriptor: the part every block needs (thresholds, the Philox
+// block index and flags, 32 bytes) and the part only evaluated blocks need
 // (channels, variables and list bounds, 64 bytes).
 struct Hot {
   uint4 tm1;    // T_m - 1 per slot; 0 for a slot without a drawn location
@@ -301,14 +320,13 @@ struct Cold {
   uint4 pad;
 };
 
-// The draw-select-evaluate loop of one wave over its share of the blocks.
-// UHI: the high word of every lane's shot index is the same (the usual case),
-// which lets the first Philox rounds run on the scalar unit.
-template <int R, int DENSE, bool UHI>
-__device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, uint2* queue, uint32_t g,
-                                           uint32_t wave, uint32_t n_waves, uint32_t lane) {
-  const DevModel& m = a.m;
-  uint32_t s_lo[R], s_hi[R];
+// Shot-index words of the R words of group g: lane t of word r stands for
+// shot first_shot + 64 (g R + r) + t.  UHI: every lane's shot index has the
+// same high word (the usual case), which lets the first Philox rounds run on
+// the scalar unit.
+template <int R, bool UHI>
+__device__ __forceinline__ void shot_words(const LaunchArgs& a, uint32_t g, uint32_t lane, uint32_t (&s_lo)[R],
+                                           uint32_t (&s_hi)[R]) {
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const uint64_t base = a.first_shot + (uint64_t)(g * R + r) * 64u;
@@ -321,129 +339,149 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
       s_hi[r] = (uint32_t)(shot >> 32);
     }
   }
-  uint32_t b = wave;
-  if (b >= m.nb) return;
-  const RoundKeys keys = round_keys(a.key0, a.key1);
-  const Hot* hot = reinterpret_cast<const Hot*>(m.hot);
-  const Cold* cold = reinterpret_cast<const Cold*>(m.cold);
-  const guint32_p entries = (guint32_p)m.entries;
-  Hot cur = load_uniform(hot + b);
-  uint32_t qn = 0;   // queued events (wave-uniform)
-  for (;;) {
-    const uint32_t bn = b + n_waves;
-    Hot nx = cur;
-    if (bn < m.nb) nx = load_uniform(hot + bn);   // in flight while this block computes
-    uint4 u[R];
+}
+
+// Evaluates every fired location of block b now (lane = entry of the
+// location's list): eager blocks, whose locations fire in many
+// lanes, and every fired block on the dense path.
+template <int R, int DENSE>
+__device__ __forceinline__ void evaluate_block(const DevModel& m, uint64_t* slab, const Cold* cold, uint32_t b,
+                                               const uint4 (&u)[R], const uint64_t (&f)[R][4], uint32_t lane) {
+  const Cold c = load_uniform(cold + b);
+  const uint4 d1 = c.meta, d2 = c.lst, d3 = c.end;
+  // Issue the first entry load of every fired location before decoding, so
+  // that their latencies overlap.
+  uint32_t first[4] = {kNoEntry, kNoEntry, kNoEntry, kNoEntry};
+  if (!DENSE) {
+    const guint32_p entries = (guint32_p)m.entries;
 #pragma unroll
-    for (int r = 0; r < R; ++r) u[r] = philox4x32_10(cur.blk.x, s_lo[r], s_hi[r], 0u, keys);
-    // A slot without a drawn location has threshold 0: it "fires" only at
-    // u = 0, and its empty list makes that a no-op.
-    uint64_t f[R][4];
-    uint64_t any = 0;
+    for (int s = 0; s < 4; ++s) {
+      uint64_t any_s = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      f[r][0] = ballot(u[r].x <= cur.tm1.x);
-      f[r][1] = ballot(u[r].y <= cur.tm1.y);
-      f[r][2] = ballot(u[r].z <= cur.tm1.z);
-      f[r][3] = ballot(u[r].w <= cur.tm1.w);
-      any |= f[r][0] | f[r][1] | f[r][2] | f[r][3];
+      for (int r = 0; r < R; ++r) any_s |= f[r][s];
+      const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
+      if (any_s && lo + lane < hi) first[s] = entries[lo + lane];
     }
-    if (any) {
-      // Locations fired in more than dmax lanes are evaluated now (one pass
-      // over the location's list, lane = entry); the others queue their
-      // fired lanes.  dmax <= kQueueCap / (4R), so that one block's events
-      // always fit in an emptied queue.  A slot without a drawn location
-      // has an empty list (and the coin channel), so its spurious fires at
-      // u = 0 change nothing.
-      const uint32_t dmax = min(m.defer_max, sp::kQueueCap / (4u * R));
-      uint32_t need = 0;   // fired lanes of the block
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) need += (uint32_t)__builtin_popcountll(f[r][s]);
-      bool big = DENSE;    // some location is evaluated now
-      if (!DENSE && need > dmax) {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-          for (int s = 0; s < 4; ++s) big |= (uint32_t)__builtin_popcountll(f[r][s]) > dmax;
-      }
-      if (!big) {
-        // The usual case: every fired location of the block is queued.
-        if (qn + need > sp::kQueueCap) {
-          flush_events(m, slab, queue, qn, lane);
-          qn = 0;
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            if (!f[r][s]) continue;
-            enqueue(queue, qn, f[r][s], pick(u[r], s) <= pick(cur.tm1, s), pick(u[r], s),
-                    (b << 10) | ((uint32_t)s << 8) | (uint32_t)r, lane << 2);
-            qn += (uint32_t)__builtin_popcountll(f[r][s]);
-          }
-      } else {
-        const Cold c = load_uniform(cold + b);
-        const uint4 d1 = c.meta, d2 = c.lst, d3 = c.end;
-        uint32_t defer = 0;   // events this block queues
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const uint32_t n = (uint32_t)__builtin_popcountll(f[r][s]);
-            if (!DENSE && n <= dmax) defer += n;
-          }
-        if (!DENSE && qn + defer > sp::kQueueCap) {
-          flush_events(m, slab, queue, qn, lane);
-          qn = 0;
-        }
-        // Issue the entry loads of every location evaluated now first, so
-        // their latencies overlap, then decode and XOR.
-        uint32_t first[4] = {kNoEntry, kNoEntry, kNoEntry, kNoEntry};
-        if (!DENSE) {
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            bool now_s = false;
-#pragma unroll
-            for (int r = 0; r < R; ++r) now_s |= (uint32_t)__builtin_popcountll(f[r][s]) > dmax;
-            const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
-            if (now_s && lo + lane < hi) first[s] = entries[lo + lane];
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            if (!f[r][s]) continue;
-            const uint32_t meta = pick(d1, s);
-            const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
-            if (lo == hi) continue;   // no measurement depends on it (or no drawn location)
-            const uint32_t n = (uint32_t)__builtin_popcountll(f[r][s]);
-            if (!DENSE && n <= dmax) {
-              enqueue(queue, qn, f[r][s], pick(u[r], s) <= pick(cur.tm1, s), pick(u[r], s),
-                      (b << 10) | ((uint32_t)s << 8) | (uint32_t)r, lane << 2);
-              qn += n;
-              continue;
-            }
-            const Masks k = decode(m.chans, meta, pick(u[r], s), f[r][s], lane);
-            uint64_t* sl = slab + (size_t)r * m.n_meas;
-            if (DENSE) {
-              evaluate_dense(m, sl, meta, k, lane);
-            } else {
-              if (k.nbits == 1) evaluate_sparse<1>(m, sl, lo, hi, first[s], k, lane);
-              else if (k.nbits == 2) evaluate_sparse<2>(m, sl, lo, hi, first[s], k, lane);
-              else evaluate_sparse<4>(m, sl, lo, hi, first[s], k, lane);
-            }
-          }
-        }
-      }
-    }
-    if (bn >= m.nb) break;
-    b = bn;
-    cur = nx;
   }
-  if (!DENSE && qn) flush_events(m, slab, queue, qn, lane);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (!f[r][s]) continue;
+      const uint32_t meta = pick(d1, s);
+      const uint32_t lo = pick(d2, s), hi = s < 3 ? pick(d2, s + 1) : d3.x;
+      if (lo == hi) continue;   // no output depends on it (or no drawn location)
+      const Masks k = decode(m.chans, meta, pick(u[r], s), f[r][s], lane);
+      uint64_t* sl = slab + (size_t)r * m.n_meas;
+      if (DENSE) {
+        evaluate_dense(m, sl, meta, k, lane);
+      } else {
+        if (k.nbits == 1) evaluate_sparse<1>(m, sl, lo, hi, first[s], k, lane);
+        else if (k.nbits == 2) evaluate_sparse<2>(m, sl, lo, hi, first[s], k, lane);
+        else evaluate_sparse<4>(m, sl, lo, hi, first[s], k, lane);
+      }
+    }
+  }
+}
+
+// One block of the draw loop: draw, fire test, then either queue the fired
+// lanes' records (QUEUE: the sparse path's lazy blocks) or evaluate every
+// fired location at once (eager blocks, and every block on the dense path).
+// Returns the hot record at `next`, whose load is issued once the current
+// record has been used (scalar loads complete out of order, so a wait for
+// the current record would otherwise also wait for the next one).
+template <int R, int DENSE, bool QUEUE, bool UHI>
+__device__ __forceinline__ Hot draw_block(const LaunchArgs& a, uint64_t* slab, const Queue& q, uint32_t& qn,
+                                          const Hot& cur, const Hot* next, uint32_t b, const RoundKeys& keys,
+                                          const uint32_t (&s_lo)[R], const uint32_t (&s_hi)[R], uint32_t lane) {
+  const DevModel& m = a.m;
+  uint4 u[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) u[r] = philox4x32_10(cur.blk.x, s_lo[r], s_hi[r], 0u, keys);
+  // Every word of `cur` is in registers here; keep the next load below.
+  asm volatile("" ::"s"(cur.tm1.x), "s"(cur.tm1.y), "s"(cur.tm1.z), "s"(cur.tm1.w) : "memory");
+  const Hot nx = load_uniform(next);
+  // A slot without a drawn location has threshold 0: it "fires" only at
+  // u = 0, and its empty list makes that a no-op.
+  uint64_t f[R][4], fr[R];
+  uint64_t any = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    f[r][0] = ballot(u[r].x <= cur.tm1.x);
+    f[r][1] = ballot(u[r].y <= cur.tm1.y);
+    f[r][2] = ballot(u[r].z <= cur.tm1.z);
+    f[r][3] = ballot(u[r].w <= cur.tm1.w);
+    fr[r] = f[r][0] | f[r][1] | f[r][2] | f[r][3];
+    any |= fr[r];
+  }
+  if (!any) return nx;   // the usual case at p ~ 1e-3: nothing fired in this block
+  if (!QUEUE) {
+    evaluate_block<R, DENSE>(m, slab, reinterpret_cast<const Cold*>(m.cold), b, u, f, lane);
+    return nx;
+  }
+  // Queue one record per fired lane and word.  A word's records always fit
+  // an emptied queue: it has at most 64 fired lanes.
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (R > 1 && !fr[r]) continue;
+    const uint32_t n = (uint32_t)__builtin_popcountll(fr[r]);
+    if (qn + n > sp::kQueueCap) {
+      flush_records(m, slab, q, qn, lane);
+      qn = 0;
+    }
+    if ((fr[r] >> lane) & 1ull) {
+      const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(fr[r] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fr[r], qn));
+      q.u[pos] = u[r];
+      q.t[pos] = (b << 8) | (lane << 2) | (uint32_t)r;
+    }
+    qn += n;
+  }
+  return nx;
+}
+
+// The blocks [b0, b1) of the hot table that one wave draws: b0 + wave,
+// b0 + wave + n_waves, ...  Two blocks per iteration, so that the record
+// loaded one block ahead lands in the registers of the block after next and
+// no record is copied; the hot table's padding makes the load past the last
+// block safe.
+template <int R, int DENSE, bool QUEUE, bool UHI>
+__device__ __forceinline__ void draw_range(const LaunchArgs& a, uint64_t* slab, const Queue& q, uint32_t& qn,
+                                           uint32_t b0, uint32_t b1, const RoundKeys& keys, const uint32_t (&s_lo)[R],
+                                           const uint32_t (&s_hi)[R], uint32_t wave, uint32_t n_waves, uint32_t lane) {
+  uint32_t b = b0 + wave;
+  if (b >= b1) return;
+  const Hot* hot = reinterpret_cast<const Hot*>(a.m.hot);
+  Hot h0 = load_uniform(hot + b);
+  for (;;) {
+    const Hot h1 = draw_block<R, DENSE, QUEUE, UHI>(a, slab, q, qn, h0, hot + b + n_waves, b, keys, s_lo, s_hi, lane);
+    b += n_waves;
+    if (b >= b1) break;
+    h0 = draw_block<R, DENSE, QUEUE, UHI>(a, slab, q, qn, h1, hot + b + n_waves, b, keys, s_lo, s_hi, lane);
+    b += n_waves;
+    if (b >= b1) break;
+  }
+}
+
+// The draw-select-evaluate loop of one wave over its share of the blocks:
+// the lazy blocks [0, nb_lazy) queue their fired lanes (sparse path), the
+// eager ones [nb_lazy, nb) are evaluated at once; on the dense path every
+// block is evaluated at once.
+template <int R, int DENSE, bool UHI>
+__device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, const Queue& q, uint32_t g,
+                                           uint32_t wave, uint32_t n_waves, uint32_t lane) {
+  const DevModel& m = a.m;
+  if (wave >= m.nb) return;
+  uint32_t s_lo[R], s_hi[R];
+  shot_words<R, UHI>(a, g, lane, s_lo, s_hi);
+  const RoundKeys keys = round_keys(a.key0, a.key1);
+  uint32_t qn = 0;   // queued records (wave-uniform)
+  if (DENSE) {
+    draw_range<R, DENSE, false, UHI>(a, slab, q, qn, 0, m.nb, keys, s_lo, s_hi, wave, n_waves, lane);
+    return;
+  }
+  draw_range<R, DENSE, true, UHI>(a, slab, q, qn, 0, m.nb_lazy, keys, s_lo, s_hi, wave, n_waves, lane);
+  if (qn) flush_records(m, slab, q, qn, lane);
+  draw_range<R, DENSE, false, UHI>(a, slab, q, qn, m.nb_lazy, m.nb, keys, s_lo, s_hi, wave, n_waves, lane);
 }
 
 // blockIdx -> group, keeping consecutive groups on one XCD (workgroups are
@@ -471,8 +509,11 @@ __device__ __forceinline__ void process_group(const LaunchArgs& a, uint64_t* sla
   // Do the R words' shot indices share one high word?
   const uint64_t first = a.first_shot + (uint64_t)g * R * 64u;
   const uint64_t last = first + (uint64_t)R * 64u - 1u;
-  // The wave's event queue follows the slabs (16-byte aligned).
-  uint2* queue = reinterpret_cast<uint2*>(slab + (((size_t)R * m.n_meas + 1u) & ~(size_t)1)) + wave * sp::kQueueCap;
+  // The waves' record queues follow the slabs (16-byte aligned): per wave,
+  // kQueueCap 16-byte draw records, then their 4-byte tags.
+  char* qbase = reinterpret_cast<char*>(slab + (((size_t)R * m.n_meas + 1u) & ~(size_t)1)) +
+                (size_t)wave * sp::kQueueCap * sp::kQueueRecBytes;
+  const Queue queue{reinterpret_cast<uint4*>(qbase), reinterpret_cast<uint32_t*>(qbase + sp::kQueueCap * 16u)};
   if ((first >> 32) == (last >> 32)) run_blocks<R, DENSE, true>(a, slab, queue, g, wave, n_waves, lane);
   else run_blocks<R, DENSE, false>(a, slab, queue, g, wave, n_waves, lane);
   __syncthreads();
@@ -603,14 +644,20 @@ __global__ void __launch_bounds__(1024) batch_flat_kernel(const BatchJob* __rest
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Fired lanes up to which a location's lanes are queued (sparse path).
-constexpr uint32_t kDeferMax = 8;
+// Locations that fire in at least an eighth of the shots (T_m >= 2^29) make
+// their block eager: evaluated at once, lane = list entry, which costs less
+// than queueing their many fired lanes one record each.
+constexpr uint64_t kEagerTm = 1ull << 29;
 
 // Drawn locations grouped by Philox block (l/4); blocks without a drawn
-// location are left out.  Per block, a hot record of 8 words:
+// location are left out.  The lazy blocks come first, then the eager ones
+// (nb_lazy counts the former), each part in block order; the order of blocks
+// changes no output, since every draw is keyed by its block index.  Per
+// block, a hot record of 8 words:
 //   [0..3]  T_m - 1 per slot (fire when u <= T_m - 1, i.e. u < T_m); 0 for
 //           a slot without a drawn location
 //   [4]     the Philox block index l/4
+// followed, after the last block, by kHotPad zero records (read, never used),
 // and a cold record of 16 words:
 //   [0..3]  meta per slot: var0 << 8 | (channel + 1); 1 (channel 0, with an
 //           empty list) for a slot without a drawn location
@@ -621,6 +668,7 @@ constexpr uint32_t kDeferMax = 8;
 struct HostBlocks {
   std::vector<uint32_t> hot, cold;
   std::vector<uint32_t> entries;
+  uint32_t nb_lazy = 0;
 };
 
 // Output rows [r0, r1) only (a row tile): a location is kept when some row of
@@ -642,6 +690,7 @@ HostBlocks build_blocks(const sp_model& m, uint32_t r0, uint32_t r1) {
   if (m.n_locs >= (1u << 24)) throw sp::Error(SP_E_LIMIT, "more than 2^24 locations");
   const bool whole = r0 == 0 && r1 >= m.n_meas;
   int64_t cur = -1;
+  std::vector<uint8_t> eager;   // per block
   for (uint32_t l = 0; l < m.n_locs; ++l) {
     if (!sp::loc_drawn(m, l)) continue;   // never fires, or reaches no output row
     if (!whole && !loc_reaches(m, l, r0, r1)) continue;
@@ -656,12 +705,14 @@ HostBlocks build_blocks(const sp_model& m, uint32_t r0, uint32_t r1) {
       for (int i = 0; i < 4; ++i) w[i] = 1u;   // empty slot: the coin channel, empty list
       for (int i = 4; i <= 8; ++i) w[i] = (uint32_t)H.entries.size();
       H.hot[H.hot.size() - 8 + 4] = (uint32_t)blk;
+      eager.push_back(0);
       cur = blk;
     }
     uint32_t* h = &H.hot[H.hot.size() - 8];
     uint32_t* w = &H.cold[H.cold.size() - 16];
     const uint32_t s = l & 3u, var0 = (uint32_t)m.loc_var0[l];
     h[s] = (uint32_t)(Tm - 1);
+    if (Tm >= kEagerTm) eager.back() = 1;
     w[s] = (var0 << 8) | (uint32_t)(ch + 1);
     w[4 + s] = (uint32_t)H.entries.size();
     for (uint32_t b = 0; b < sp::loc_bits(m.loc_kind[l]); ++b)
@@ -672,6 +723,19 @@ HostBlocks build_blocks(const sp_model& m, uint32_t r0, uint32_t r1) {
     if (H.entries.size() >= (1ull << 32)) throw sp::Error(SP_E_LIMIT, "more than 2^32 entries in M");
     for (uint32_t t = s + 1; t <= 4; ++t) w[4 + t] = (uint32_t)H.entries.size();
   }
+  // Lazy blocks first, then eager ones, each part keeping its order.
+  std::vector<uint32_t> hot, cold;
+  hot.reserve(H.hot.size());
+  cold.reserve(H.cold.size());
+  for (int pass = 0; pass < 2; ++pass)
+    for (size_t i = 0; i < eager.size(); ++i) {
+      if (eager[i] != pass) continue;
+      hot.insert(hot.end(), H.hot.begin() + 8 * i, H.hot.begin() + 8 * (i + 1));
+      cold.insert(cold.end(), H.cold.begin() + 16 * i, H.cold.begin() + 16 * (i + 1));
+      if (pass == 0) ++H.nb_lazy;
+    }
+  H.hot.swap(hot);
+  H.cold.swap(cold);
   return H;
 }
 
@@ -684,19 +748,19 @@ int choose_path(const sp_model& m, int path) {
   return (avg * 4.0 > (double)m.n_meas) ? SP_PATH_DENSE : SP_PATH_SPARSE;
 }
 
-// Rows of one LDS slab that leave room for the event queues of 16 waves
+// Rows of one LDS slab that leave room for the record queues of 16 waves
 // (160 KB of LDS per workgroup on gfx950): the largest tile.  The automatic
-// choice keeps one tile while two workgroups' slabs fit a CU (9,216 rows);
-// past that, a single slab leaves too few waves per SIMD to hide the draw's
-// latency, and tiles of 4,096 rows sample faster despite the draws that
-// several tiles repeat.
-constexpr uint32_t kSlabRowsMax = (160u * 1024u - 16u * sp::kQueueCap * 8u) / 8u;
-constexpr uint32_t kOneTileRowsMax = 9216;
+// choice keeps one tile while two 8-wave workgroups' slabs and queues fit a
+// CU (8,960 rows); past that, a single slab leaves too few waves per SIMD to
+// hide the draw's latency, and tiles of 4,096 rows sample faster despite the
+// draws that several tiles repeat.
+constexpr uint32_t kSlabRowsMax = (160u * 1024u - 16u * sp::kQueueCap * sp::kQueueRecBytes) / 8u;
+constexpr uint32_t kOneTileRowsMax = (80u * 1024u - 8u * sp::kQueueCap * sp::kQueueRecBytes) / 8u;
 constexpr uint32_t kTileRowsAuto = 4096;
 
 struct TileLayout {
   size_t hot, cold, entries, c_mask, dense;
-  uint32_t r0, rows, nb, dense_words;
+  uint32_t r0, rows, nb, nb_lazy, dense_words;
 };
 
 struct Layout {
@@ -727,8 +791,9 @@ Layout plan(const sp_model& m, int path, uint32_t tile_rows) {
     T.r0 = r0;
     T.rows = m.n_meas ? r1 - r0 : 0;
     T.nb = (uint32_t)(H.hot.size() / 8);
+    T.nb_lazy = H.nb_lazy;
     T.dense_words = (T.rows + 63) / 64;
-    T.hot = off;     off = align256(off + 32 * std::max<size_t>(T.nb, 1));
+    T.hot = off;     off = align256(off + 32 * ((size_t)T.nb + sp::kHotPad));
     T.cold = off;    off = align256(off + 64 * std::max<size_t>(T.nb, 1));
     T.entries = off; off = align256(off + 4 * std::max<size_t>(H.entries.size(), 1));
     T.c_mask = off;  off = align256(off + 8 * std::max<size_t>(T.dense_words, 1));
@@ -799,7 +864,7 @@ namespace sp {
 
 size_t lds_bytes(uint32_t n_meas, uint32_t words_per_group, uint32_t waves_per_group, int path) {
   const size_t slabs = ((size_t)n_meas * words_per_group + 1u) / 2u * 16u;
-  return path == SP_PATH_DENSE ? slabs : slabs + (size_t)waves_per_group * kQueueCap * 8u;
+  return path == SP_PATH_DENSE ? slabs : slabs + (size_t)waves_per_group * kQueueCap * kQueueRecBytes;
 }
 
 int launch_sample(const LaunchArgs& a, int path, const sp_launch& L, hipStream_t s) {
@@ -982,8 +1047,8 @@ int sp_model_upload_tiled(const sp_model* model, int path, uint32_t tile_rows, v
       m.c_mask = (const uint64_t*)(base + T.c_mask);
       m.dense = p == SP_PATH_DENSE ? (const uint64_t*)(base + T.dense) : nullptr;
       m.nb = T.nb;
+      m.nb_lazy = T.nb_lazy;
       m.nch = L.nch;
-      m.defer_max = kDeferMax;
       m.n_meas = T.rows;
       m.dense_words = T.dense_words;
       dm->tiles.push_back(m);
