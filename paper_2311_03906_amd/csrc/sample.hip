@@ -121,9 +121,94 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
   return make_uint4(c0, c1, c2, c3);
 }
 
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+// Scalar-unit arithmetic on wave-uniform words.  The compiler moves a
+// uniform computation to the vector unit as soon as one operand sits in a
+// vector register; these keep each step on the scalar unit (operands are
+// read into scalar registers first when needed).
+__device__ __forceinline__ uint32_t s_mulhi(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("s_mul_hi_u32 %0, %1, %2" : "=s"(r) : "s"(a), "s"(b));
+  return r;
+}
+__device__ __forceinline__ uint32_t s_mullo(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("s_mul_i32 %0, %1, %2" : "=s"(r) : "s"(a), "s"(b));
+  return r;
+}
+__device__ __forceinline__ uint32_t s_xor(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("s_xor_b32 %0, %1, %2" : "=s"(r) : "s"(a), "s"(b) : "scc");
+  return r;
+}
+
+// The draws of one 64-shot word.  Lane t's counter is (l/4, shot lo, shot
+// hi, 0): within a wave the block index l/4, the key and (UHI: when the 64
+// shots share it) the high word are uniform, so of the cipher's first rounds
+// only part depends on the lane, and of that part some does not depend on
+// the block.  Per word, before the block loop:
+//   a   = hi(M1 * hi) ^ lo ^ k0[0]     round 1's first output word (lane)
+//   b   = M0 * a                       round 2's first product (lane)
+//   p1l = lo(M1 * hi)                  round 1's second output word (uniform)
+// Per block, round 1 and the uniform halves of rounds 2-4 run on the scalar
+// unit, leaving 15 products and 17 XORs per lane instead of 20 and 20.
+struct ShotWord {
+  uint32_t lo, hi;       // the shot index's words (hi uniform when UHI)
+  uint32_t a, bhi, blo;  // lane-invariant words of rounds 1-2 (UHI)
+  uint32_t p1l;          // uniform (UHI)
+};
+
+template <bool UHI>
+__device__ __forceinline__ ShotWord shot_word(uint64_t shot0, uint32_t lane, const RoundKeys& k) {
+  ShotWord w{};
+  if (UHI) {
+    w.lo = (uint32_t)shot0 + lane;
+    w.hi = s_xor((uint32_t)(shot0 >> 32), 0u);
+    w.p1l = s_mullo(w.hi, kM1);
+    w.a = s_xor(s_mulhi(w.hi, kM1), k.k0[0]) ^ w.lo;
+    const uint64_t b = (uint64_t)kM0 * w.a;
+    w.bhi = (uint32_t)(b >> 32);
+    w.blo = (uint32_t)b;
+  } else {
+    const uint64_t shot = shot0 + lane;
+    w.lo = (uint32_t)shot;
+    w.hi = (uint32_t)(shot >> 32);
+  }
+  return w;
+}
+
+// Philox4x32-10 of counter (blk, w.lo, w.hi, 0): the same value as
+// philox4x32_10, with the UHI split above.
+template <bool UHI>
+__device__ __forceinline__ uint4 draw4(uint32_t blk, const ShotWord& w, const RoundKeys& k) {
+  if (!UHI) return philox4x32_10(blk, w.lo, w.hi, 0u, k);
+  // round 1: (a, p1l, hi(M0 blk) ^ k1[0], lo(M0 blk))
+  const uint32_t c2 = s_xor(s_mulhi(blk, kM0), k.k1[0]);
+  const uint32_t c3 = s_mullo(blk, kM0);
+  // round 2: (hi(M1 c2) ^ p1l ^ k0[1], lo(M1 c2), bhi ^ c3 ^ k1[1], blo)
+  const uint32_t d0 = s_xor(s_xor(s_mulhi(c2, kM1), w.p1l), k.k0[1]);
+  const uint32_t d1 = s_mullo(c2, kM1);
+  const uint32_t d2 = w.bhi ^ s_xor(c3, k.k1[1]);
+  // round 3: (hi(M1 d2) ^ d1 ^ k0[2], lo(M1 d2), hi(M0 d0) ^ blo ^ k1[2], lo(M0 d0))
+  const uint64_t r1 = (uint64_t)kM1 * d2;
+  uint32_t c0 = (uint32_t)(r1 >> 32) ^ s_xor(d1, k.k0[2]);
+  uint32_t c1 = (uint32_t)r1;
+  const uint32_t e2 = w.blo ^ s_xor(s_mulhi(d0, kM0), k.k1[2]);
+  const uint32_t e3 = s_mullo(d0, kM0);
+  // round 4: the last uniform word enters through a scalar XOR
+  const uint64_t s0 = (uint64_t)kM0 * c0;
+  const uint64_t s1 = (uint64_t)kM1 * e2;
+  c0 = __builtin_amdgcn_bitop3_b32((uint32_t)(s1 >> 32), c1, k.k0[3], 0x96);
+  c1 = (uint32_t)s1;
+  uint32_t c2l = (uint32_t)(s0 >> 32) ^ s_xor(e3, k.k1[3]);
+  uint32_t c3l = (uint32_t)s0;
+#pragma unroll
+  for (int r = 4; r < 10; ++r) philox_round(c0, c1, c2l, c3l, k.k0[r], k.k1[r]);
+  return make_uint4(c0, c1, c2l, c3l);
+}
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ uint32_t pick(const uint4& v, int s) {
   return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
@@ -320,25 +405,15 @@ struct Cold {
   uint4 pad;
 };
 
-// Shot-index words of the R words of group g: lane t of word r stands for
-// shot first_shot + 64 (g R + r) + t.  UHI: every lane's shot index has the
-// same high word (the usual case), which lets the first Philox rounds run on
-// the scalar unit.
+// The R words of group g: lane t of word r stands for shot
+// first_shot + 64 (g R + r) + t.  UHI: every lane's shot index has the same
+// high word (the usual case), which lets the first rounds of each draw run
+// on the scalar unit.
 template <int R, bool UHI>
-__device__ __forceinline__ void shot_words(const LaunchArgs& a, uint32_t g, uint32_t lane, uint32_t (&s_lo)[R],
-                                           uint32_t (&s_hi)[R]) {
+__device__ __forceinline__ void shot_words(const LaunchArgs& a, uint32_t g, uint32_t lane, const RoundKeys& k,
+                                           ShotWord (&w)[R]) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint64_t base = a.first_shot + (uint64_t)(g * R + r) * 64u;
-    if (UHI) {
-      s_lo[r] = (uint32_t)base + lane;
-      s_hi[r] = uniform((uint32_t)(base >> 32));
-    } else {
-      const uint64_t shot = base + lane;
-      s_lo[r] = (uint32_t)shot;
-      s_hi[r] = (uint32_t)(shot >> 32);
-    }
-  }
+  for (int r = 0; r < R; ++r) w[r] = shot_word<UHI>(a.first_shot + (uint64_t)(g * R + r) * 64u, lane, k);
 }
 
 // Evaluates every fired location of block b now (lane = entry of the
@@ -393,30 +468,33 @@ __device__ __forceinline__ void evaluate_block(const DevModel& m, uint64_t* slab
 template <int R, int DENSE, bool QUEUE, bool UHI>
 __device__ __forceinline__ Hot draw_block(const LaunchArgs& a, uint64_t* slab, const Queue& q, uint32_t& qn,
                                           const Hot& cur, const Hot* next, uint32_t b, const RoundKeys& keys,
-                                          const uint32_t (&s_lo)[R], const uint32_t (&s_hi)[R], uint32_t lane) {
+                                          const ShotWord (&w)[R], uint32_t lane4) {
   const DevModel& m = a.m;
   uint4 u[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) u[r] = philox4x32_10(cur.blk.x, s_lo[r], s_hi[r], 0u, keys);
+  for (int r = 0; r < R; ++r) u[r] = draw4<UHI>(cur.blk.x, w[r], keys);
   // Every word of `cur` is in registers here; keep the next load below.
   asm volatile("" ::"s"(cur.tm1.x), "s"(cur.tm1.y), "s"(cur.tm1.z), "s"(cur.tm1.w) : "memory");
   const Hot nx = load_uniform(next);
   // A slot without a drawn location has threshold 0: it "fires" only at
   // u = 0, and its empty list makes that a no-op.
+  bool c[R][4];
   uint64_t f[R][4], fr[R];
   uint64_t any = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    f[r][0] = ballot(u[r].x <= cur.tm1.x);
-    f[r][1] = ballot(u[r].y <= cur.tm1.y);
-    f[r][2] = ballot(u[r].z <= cur.tm1.z);
-    f[r][3] = ballot(u[r].w <= cur.tm1.w);
+    c[r][0] = u[r].x <= cur.tm1.x;
+    c[r][1] = u[r].y <= cur.tm1.y;
+    c[r][2] = u[r].z <= cur.tm1.z;
+    c[r][3] = u[r].w <= cur.tm1.w;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) f[r][s] = ballot(c[r][s]);
     fr[r] = f[r][0] | f[r][1] | f[r][2] | f[r][3];
     any |= fr[r];
   }
   if (!any) return nx;   // the usual case at p ~ 1e-3: nothing fired in this block
   if (!QUEUE) {
-    evaluate_block<R, DENSE>(m, slab, reinterpret_cast<const Cold*>(m.cold), b, u, f, lane);
+    evaluate_block<R, DENSE>(m, slab, reinterpret_cast<const Cold*>(m.cold), b, u, f, lane4 >> 2);
     return nx;
   }
   // Queue one record per fired lane and word.  A word's records always fit
@@ -426,13 +504,19 @@ __device__ __forceinline__ Hot draw_block(const LaunchArgs& a, uint64_t* slab, c
     if (R > 1 && !fr[r]) continue;
     const uint32_t n = (uint32_t)__builtin_popcountll(fr[r]);
     if (qn + n > sp::kQueueCap) {
-      flush_records(m, slab, q, qn, lane);
+      flush_records(m, slab, q, qn, lane4 >> 2);
       qn = 0;
     }
-    if ((fr[r] >> lane) & 1ull) {
-      const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(fr[r] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fr[r], qn));
-      q.u[pos] = u[r];
-      q.t[pos] = (b << 8) | (lane << 2) | (uint32_t)r;
+    uint32_t* ud = reinterpret_cast<uint32_t*>(q.u + qn);   // wave-uniform bases
+    uint32_t* td = q.t + qn;
+    const uint32_t tag = (b << 8) | (uint32_t)r;
+    if (c[r][0] | c[r][1] | c[r][2] | c[r][3]) {   // this lane's shot fired somewhere in the block
+      const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(fr[r] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fr[r], 0u));
+      ud[4 * pos + 0] = u[r].x;
+      ud[4 * pos + 1] = u[r].y;
+      ud[4 * pos + 2] = u[r].z;
+      ud[4 * pos + 3] = u[r].w;
+      td[pos] = tag | lane4;
     }
     qn += n;
   }
@@ -446,17 +530,17 @@ __device__ __forceinline__ Hot draw_block(const LaunchArgs& a, uint64_t* slab, c
 // block safe.
 template <int R, int DENSE, bool QUEUE, bool UHI>
 __device__ __forceinline__ void draw_range(const LaunchArgs& a, uint64_t* slab, const Queue& q, uint32_t& qn,
-                                           uint32_t b0, uint32_t b1, const RoundKeys& keys, const uint32_t (&s_lo)[R],
-                                           const uint32_t (&s_hi)[R], uint32_t wave, uint32_t n_waves, uint32_t lane) {
+                                           uint32_t b0, uint32_t b1, const RoundKeys& keys, const ShotWord (&w)[R],
+                                           uint32_t wave, uint32_t n_waves, uint32_t lane4) {
   uint32_t b = b0 + wave;
   if (b >= b1) return;
   const Hot* hot = reinterpret_cast<const Hot*>(a.m.hot);
   Hot h0 = load_uniform(hot + b);
   for (;;) {
-    const Hot h1 = draw_block<R, DENSE, QUEUE, UHI>(a, slab, q, qn, h0, hot + b + n_waves, b, keys, s_lo, s_hi, lane);
+    const Hot h1 = draw_block<R, DENSE, QUEUE, UHI>(a, slab, q, qn, h0, hot + b + n_waves, b, keys, w, lane4);
     b += n_waves;
     if (b >= b1) break;
-    h0 = draw_block<R, DENSE, QUEUE, UHI>(a, slab, q, qn, h1, hot + b + n_waves, b, keys, s_lo, s_hi, lane);
+    h0 = draw_block<R, DENSE, QUEUE, UHI>(a, slab, q, qn, h1, hot + b + n_waves, b, keys, w, lane4);
     b += n_waves;
     if (b >= b1) break;
   }
@@ -471,17 +555,18 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
                                            uint32_t wave, uint32_t n_waves, uint32_t lane) {
   const DevModel& m = a.m;
   if (wave >= m.nb) return;
-  uint32_t s_lo[R], s_hi[R];
-  shot_words<R, UHI>(a, g, lane, s_lo, s_hi);
   const RoundKeys keys = round_keys(a.key0, a.key1);
+  ShotWord w[R];
+  shot_words<R, UHI>(a, g, lane, keys, w);
+  const uint32_t lane4 = lane << 2;
   uint32_t qn = 0;   // queued records (wave-uniform)
   if (DENSE) {
-    draw_range<R, DENSE, false, UHI>(a, slab, q, qn, 0, m.nb, keys, s_lo, s_hi, wave, n_waves, lane);
+    draw_range<R, DENSE, false, UHI>(a, slab, q, qn, 0, m.nb, keys, w, wave, n_waves, lane4);
     return;
   }
-  draw_range<R, DENSE, true, UHI>(a, slab, q, qn, 0, m.nb_lazy, keys, s_lo, s_hi, wave, n_waves, lane);
+  draw_range<R, DENSE, true, UHI>(a, slab, q, qn, 0, m.nb_lazy, keys, w, wave, n_waves, lane4);
   if (qn) flush_records(m, slab, q, qn, lane);
-  draw_range<R, DENSE, false, UHI>(a, slab, q, qn, m.nb_lazy, m.nb, keys, s_lo, s_hi, wave, n_waves, lane);
+  draw_range<R, DENSE, false, UHI>(a, slab, q, qn, m.nb_lazy, m.nb, keys, w, wave, n_waves, lane4);
 }
 
 // blockIdx -> group, keeping consecutive groups on one XCD (workgroups are
