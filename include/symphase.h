@@ -25,7 +25,8 @@
  *     released by the matching *_free function, which accepts NULL.
  *   - The library allocates no device memory.  The device model lives in a
  *     caller-provided device buffer; sample outputs are caller-provided device
- *     buffers.  `stream` is a hipStream_t passed as void* (NULL = the null
+ *     buffers.  (sp_sample_batch_static uses a fixed array in the library's
+ *     device image instead of a work buffer.)  `stream` is a hipStream_t passed as void* (NULL = the null
  *     stream); device work is queued on it asynchronously.
  *
  * Circuit text: one instruction per line, '#' comments.
@@ -368,6 +369,23 @@ int sp_batch_info(const sp_batch* batch, uint32_t* n_jobs, uint32_t* total_group
  * a captured graph; launches of one batch must not overlap in time. */
 int sp_batch_launch(const sp_batch* batch, void* stream);
 void sp_batch_free(sp_batch* batch);
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the batched launch
+ * of sp_batch_create + sp_batch_launch in one call, with the batch's job
+ * table, task list or group map and work counters in a static device array
+ * of the library (4 MiB on each GPU it runs on, held until the process
+ * ends) instead of a caller's work buffer.  It allocates no device memory.
+ * Items, launch shape (NULL = default) and schedule are as for
+ * sp_batch_create, and every item's output is exactly what sp_sample writes
+ * for it.  The tables are copied on `stream` and the call waits for that
+ * copy (so also for earlier work on `stream`); the launch is then queued
+ * asynchronously.  All calls on one GPU share the array: calls in order on
+ * one stream are safe, calls on different streams or threads that overlap
+ * in time race.  Errors: SP_E_INVALID, SP_E_LIMIT (the tables exceed
+ * 4 MiB, or the slabs exceed the LDS), SP_E_NOMEM, SP_E_DEVICE. */
+int sp_sample_batch_static(const sp_batch_item* items, size_t n, const sp_launch* launch, int schedule,
+                           void* stream);
 
 /* Captured launch sequences (HIP graphs).  capture_batch records one
  * sp_batch_launch; capture_plain records one sp_sample per item, in order.

@@ -330,6 +330,15 @@ class Batch:
         _rel(self, "sp_batch_free")
 
 
+def sample_batch_static(jobs: list, launch=None, schedule: str = "persistent", stream=None) -> None:
+    """sp_sample_batch_static: the jobs' batched launch with the library's
+    static device scratch for its tables (no work buffer is allocated)."""
+    items = _items(jobs)
+    L = None if launch is None else ctypes.byref(sp_launch(int(launch[0]), int(launch[1])))
+    sched = {"persistent": SP_SCHED_PERSISTENT, "flat": SP_SCHED_FLAT}[schedule]
+    check(lib().sp_sample_batch_static(items, len(jobs), L, sched, ctypes.c_void_p(_stream_handle(stream))))
+
+
 class Graph:
     """A captured launch sequence (sp_graph_capture_batch / _plain)."""
 

@@ -31,6 +31,7 @@ EXPORTS = (
     "sp_model_upload", "sp_model_device_bytes_tiled", "sp_model_upload_tiled", "sp_dmodel_free", "sp_dmodel_dims",
     "sp_dmodel_tiles", "sp_dmodel_get_launch", "sp_dmodel_set_launch",
     "sp_sample", "sp_sample_host", "sp_batch_work_bytes", "sp_batch_create", "sp_batch_info", "sp_batch_launch", "sp_batch_free",
+    "sp_sample_batch_static",
     "sp_graph_capture_batch", "sp_graph_capture_plain", "sp_graph_launch", "sp_graph_free",
     "sp_server_work_bytes", "sp_server_create", "sp_server_submit", "sp_server_status", "sp_server_wait",
     "sp_server_release", "sp_server_stats", "sp_server_destroy", "sp_last_error",
@@ -126,6 +127,7 @@ def lib():
         "sp_batch_info": ([vp, P(u32), P(u32), P(u32), P(sp_launch)], ctypes.c_int),
         "sp_batch_launch": ([vp, vp], ctypes.c_int),
         "sp_batch_free": ([vp], None),
+        "sp_sample_batch_static": ([vp, sz, vp, ctypes.c_int, vp], ctypes.c_int),
         "sp_graph_capture_batch": ([vp, P(vp)], ctypes.c_int),
         "sp_graph_capture_plain": ([vp, sz, P(vp)], ctypes.c_int),
         "sp_graph_launch": ([vp, vp], ctypes.c_int),

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -267,6 +268,99 @@ int sp_batch_launch(const sp_batch* b, void* stream) {
 }
 
 void sp_batch_free(sp_batch* b) { delete b; }
+
+}  // extern "C"
+
+// ---- batched sampling without device allocation ---------------------------
+//
+// sp_sample_batch_static keeps a batch's job table, task list (or group map)
+// and work counters in `scratch`, a fixed array in the library's device
+// image: each GPU the library runs on holds its own copy for the life of the
+// process, and every call on that GPU reuses it.  In host code the array's
+// name is not a device address; the address comes from hipGetSymbolAddress,
+// taken once per device with that device current, and only that address is
+// handed to copies and kernels.
+
+namespace {
+
+constexpr size_t kScratchBytes = size_t(4) << 20;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this device's scratch (the current device).
+int scratch_ptr(int dev, uint8_t** out) {
+  if (dev < 0 || dev >= kMaxDevices) return set_error(SP_E_LIMIT, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(SP_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (uint8_t*)g_scratch_ptr[dev];
+  return SP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sp_sample_batch_static(const sp_batch_item* items, size_t n, const sp_launch* launch, int schedule,
+                           void* stream) {
+  Plan P;
+  std::vector<uint8_t> host;
+  try {
+    int rc = make_plan(items, n, launch, schedule, P);
+    if (rc) return rc;
+    if (P.n_sub == 0) return SP_OK;
+    if (P.total_bytes > kScratchBytes)
+      return set_error(SP_E_LIMIT, "batch tables of " + std::to_string(P.total_bytes) + " bytes exceed the " +
+                                       std::to_string(kScratchBytes) + "-byte static scratch");
+    host.assign(P.total_bytes, 0);   // the work counters start at zero
+    for (int i = 0; i < P.n_sub; ++i) {
+      const SubPlan& S = P.sub[i];
+      std::memcpy(&host[S.off_jobs], S.jobs.data(), sizeof(sp::BatchJob) * S.jobs.size());
+      if (!S.tasks.empty()) std::memcpy(&host[S.off_tasks], S.tasks.data(), sizeof(sp::BatchTask) * S.tasks.size());
+      if (!S.group_job.empty()) std::memcpy(&host[S.off_map], S.group_job.data(), sizeof(uint32_t) * S.group_job.size());
+    }
+  } catch (const std::bad_alloc&) {
+    return set_error(SP_E_NOMEM, "out of host memory");
+  }
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  uint8_t* base = nullptr;
+  if (int rc = scratch_ptr(dev, &base)) return rc;
+  uint32_t grids[2] = {0, 0};
+  if (schedule == SP_SCHED_PERSISTENT)
+    for (int i = 0; i < P.n_sub; ++i) {
+      int rc = sp::batch_grid(P.launch, P.sub[i].n_meas_max, P.sub[i].path, &grids[i]);
+      if (rc) return rc;
+    }
+  // Stream order puts this copy after any earlier launch on `stream` that
+  // still reads the scratch; the wait lets the host image go.
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(base, host.data(), P.total_bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int i = 0; i < P.n_sub; ++i) {
+    const SubPlan& S = P.sub[i];
+    const uint32_t n_tasks = (uint32_t)S.tasks.size();
+    const int rc =
+        schedule == SP_SCHED_PERSISTENT
+            ? sp::launch_batch_persistent((const sp::BatchJob*)(base + S.off_jobs),
+                                          (const sp::BatchTask*)(base + S.off_tasks), n_tasks,
+                                          (sp::BatchCounters*)(base + S.off_ctr), S.n_meas_max, S.path, P.launch,
+                                          std::min<uint32_t>(grids[i], std::max<uint32_t>(n_tasks, 1)), s)
+            : sp::launch_batch_flat((const sp::BatchJob*)(base + S.off_jobs), (const uint32_t*)(base + S.off_map),
+                                    (uint32_t)S.total_groups, S.n_meas_max, S.path, P.launch, s);
+    if (rc) return rc;
+  }
+  return SP_OK;
+}
 
 }  // extern "C"
 
