@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <iterator>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -214,19 +215,25 @@ __device__ __forceinline__ uint32_t pick(const uint4& v, int s) {
   return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
 }
 
+// A 32-bit word of a read-only device array at a per-lane index, addressed
+// as a uniform base plus a 32-bit byte offset (the arrays stay under 4 GiB).
+__device__ __forceinline__ uint32_t ld32(const uint32_t* base, uint32_t idx) {
+  return *(const SP_GLOBAL_AS uint32_t*)((const SP_GLOBAL_AS char*)base + (idx << 2));
+}
+
 // Pauli code of a fired draw u under channel ch1 - 1: the k with
 // T_{k-1} <= u < T_k (T_0 = 0).  The channel row holds kind | m << 8, then
 // T_1..T_{m-1}, then 0xFFFFFFFF; T_1..T_15 is thus nondecreasing and a
 // binary search counts j = #{k : T_k <= u}, so code = j + 1.  A draw of
 // u = 2^32 - 1 fires only when T_m = 2^32 (p = 1), and its code is m.
 __device__ __forceinline__ uint32_t lane_code(const uint32_t* chans, uint32_t ch1, uint32_t u) {
-  const guint32_p T = (guint32_p)chans + (ch1 - 1u) * 16u;
+  const uint32_t t = (ch1 - 1u) * 16u;
   uint32_t j = 0;
-  j += (T[j + 8] <= u) ? 8u : 0u;
-  j += (T[j + 4] <= u) ? 4u : 0u;
-  j += (T[j + 2] <= u) ? 2u : 0u;
-  j += (T[j + 1] <= u) ? 1u : 0u;
-  return min(j + 1u, T[0] >> 8);
+  j += (ld32(chans, t + j + 8) <= u) ? 8u : 0u;
+  j += (ld32(chans, t + j + 4) <= u) ? 4u : 0u;
+  j += (ld32(chans, t + j + 2) <= u) ? 2u : 0u;
+  j += (ld32(chans, t + j + 1) <= u) ? 1u : 0u;
+  return min(j + 1u, ld32(chans, t) >> 8);
 }
 
 // Code-bit masks of a fired location (fire = lanes with u < T_m): mask i
@@ -317,32 +324,45 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Walks the entry list [lo, hi) of one fired location for one shot: flips
-// the shot's bit (`bit`) in the slab rows of the entries whose code bit is
-// set in `code`.  Eight entry loads are kept in flight.
-__device__ __forceinline__ void walk_list(const DevModel& m, uint64_t* sl, uint32_t lo, uint32_t hi, uint32_t code,
-                                          uint64_t bit) {
-  const guint32_p p1 = (guint32_p)m.entries + hi;
-  guint32_p p = (guint32_p)m.entries + lo;
-  for (; p + 8 <= p1; p += 8) {
+// LDS byte address of a shared-memory pointer, and a 64-bit XOR at an LDS
+// byte address.
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+__device__ __forceinline__ void lds_xor(uint32_t addr, uint64_t v) {
+  __atomic_fetch_xor((__attribute__((address_space(3))) uint64_t*)addr, v, __ATOMIC_RELAXED);
+}
+
+// Walks the code list [lo, hi) of one fired location for one shot: the
+// entries are the byte offsets (row << 3) of the slab rows that the fired
+// Pauli flips, so each is one XOR of the shot's bit (`bit`) into the slab
+// at LDS address `base`.  Eight entry loads are kept in flight.  BASE0: the
+// slab starts at LDS address 0, so an entry is its row's address.
+template <bool BASE0>
+__device__ __forceinline__ void walk_code(const DevModel& m, uint32_t base, uint32_t lo, uint32_t hi, uint64_t bit) {
+  // 32-bit byte offsets from a uniform base, constant steps as immediates
+  const SP_GLOBAL_AS char* ce = (const SP_GLOBAL_AS char*)m.centries;
+  if (BASE0) base = 0;
+  uint32_t o = lo << 2;
+  const uint32_t o1 = hi << 2;
+  for (; o + 32 <= o1; o += 32) {
+    const SP_GLOBAL_AS uint32_t* pe = (const SP_GLOBAL_AS uint32_t*)(ce + o);
     uint32_t e[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) e[i] = p[i];
+    for (int k = 0; k < 8; ++k) e[k] = pe[k];
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (__builtin_amdgcn_ubfe(code, e[i], 1)) atomicXor((unsigned long long*)&row_of(sl, e[i]), (unsigned long long)bit);
+    for (int k = 0; k < 8; ++k) lds_xor(base + e[k], bit);
   }
-  for (; p + 4 <= p1; p += 4) {
-    const uint32_t e0 = p[0], e1 = p[1], e2 = p[2], e3 = p[3];
-    if (__builtin_amdgcn_ubfe(code, e0, 1)) atomicXor((unsigned long long*)&row_of(sl, e0), (unsigned long long)bit);
-    if (__builtin_amdgcn_ubfe(code, e1, 1)) atomicXor((unsigned long long*)&row_of(sl, e1), (unsigned long long)bit);
-    if (__builtin_amdgcn_ubfe(code, e2, 1)) atomicXor((unsigned long long*)&row_of(sl, e2), (unsigned long long)bit);
-    if (__builtin_amdgcn_ubfe(code, e3, 1)) atomicXor((unsigned long long*)&row_of(sl, e3), (unsigned long long)bit);
+  if (o + 16 <= o1) {
+    const SP_GLOBAL_AS uint32_t* pe = (const SP_GLOBAL_AS uint32_t*)(ce + o);
+    uint32_t e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e[k] = pe[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lds_xor(base + e[k], bit);
+    o += 16;
   }
-  for (; p < p1; ++p) {
-    const uint32_t e = *p;
-    if (__builtin_amdgcn_ubfe(code, e, 1)) atomicXor((unsigned long long*)&row_of(sl, e), (unsigned long long)bit);
-  }
+  for (; o < o1; o += 4) lds_xor(base + *(const SP_GLOBAL_AS uint32_t*)(ce + o), bit);
 }
 
 // A wave's record queue (sparse path): record i is the four draws of one
@@ -356,11 +376,12 @@ struct Queue {
 };
 
 // Evaluates the queued records, one per lane: the lane reloads its block's
-// thresholds and list bounds, and for every location that fired in its shot
-// finds the Pauli code from the draw (lane_code) and walks the location's
-// list, flipping its shot's bit in the rows of the code's set bits.  A lane
+// thresholds, channels and code-table starts, and for every location that
+// fired in its shot finds the Pauli code from the draw (lane_code) and walks
+// that code's list, flipping its shot's bit in every row it names.  A lane
 // with several fired locations takes them one after another.  Everything
 // but the queueing is shared by up to 64 records.
+template <int R>
 __device__ __forceinline__ void flush_records(const DevModel& m, uint64_t* slab, const Queue& q, uint32_t qn,
                                               uint32_t lane) {
   wave_sync();
@@ -368,24 +389,25 @@ __device__ __forceinline__ void flush_records(const DevModel& m, uint64_t* slab,
     const uint4 u = q.u[lane];
     const uint32_t tag = q.t[lane];
     const uint32_t b = tag >> 8;
-    const uint4 tm1 = ((guint4_p)m.hot)[(size_t)b * 2u];
-    const guint4_p cw = (guint4_p)m.cold + (size_t)b * 4u;   // meta[4] | lst[4] | end
-    const uint4 meta = cw[0], lst = cw[1];
-    const uint32_t end = ((guint32_p)cw)[8];
+    const uint4 tm1 = *(const SP_GLOBAL_AS uint4*)((const SP_GLOBAL_AS char*)m.hot + (b << 5));
+    const SP_GLOBAL_AS char* cw = (const SP_GLOBAL_AS char*)m.cold + (b << 6);   // meta | lst | end | ctab
+    const uint4 meta = *(const SP_GLOBAL_AS uint4*)cw, ct = *(const SP_GLOBAL_AS uint4*)(cw + 48);
     uint32_t fired = (uint32_t)(u.x <= tm1.x) | (uint32_t)(u.y <= tm1.y) << 1 | (uint32_t)(u.z <= tm1.z) << 2 |
                      (uint32_t)(u.w <= tm1.w) << 3;
     const uint64_t bit = 1ull << ((tag >> 2) & 63u);
-    uint64_t* sl = slab + (size_t)(tag & 3u) * m.n_meas;
+    const uint32_t base = lds_addr(R == 1 ? slab : slab + (size_t)(tag & 3u) * m.n_meas);
     while (fired) {
       const uint32_t s = (uint32_t)__builtin_ctz(fired);
       fired &= fired - 1u;
       const uint32_t us = s == 0 ? u.x : s == 1 ? u.y : s == 2 ? u.z : u.w;
       const uint32_t mt = s == 0 ? meta.x : s == 1 ? meta.y : s == 2 ? meta.z : meta.w;
-      const uint32_t lo = s == 0 ? lst.x : s == 1 ? lst.y : s == 2 ? lst.z : lst.w;
-      const uint32_t hi = s == 0 ? lst.y : s == 1 ? lst.z : s == 2 ? lst.w : end;
-      // A slot without a drawn location (threshold 0) fires at u = 0 only,
-      // and its list is empty.
-      if (lo != hi) walk_list(m, sl, lo, hi, lane_code(m.chans, mt & 0xFFu, us), bit);
+      const uint32_t c0 = s == 0 ? ct.x : s == 1 ? ct.y : s == 2 ? ct.z : ct.w;
+      // A slot without a drawn location (threshold 0, fires at u = 0 only)
+      // has the coin channel and an empty code list.
+      const uint32_t code = lane_code(m.chans, mt & 0xFFu, us);
+      const uint32_t lo = ld32(m.ctab, c0 + code - 1u), hi = ld32(m.ctab, c0 + code);
+      if (base == 0) walk_code<true>(m, base, lo, hi, bit);
+      else walk_code<false>(m, base, lo, hi, bit);
     }
   }
   wave_sync();
@@ -402,7 +424,7 @@ struct Cold {
   uint4 meta;   // var0 << 8 | channel + 1 per slot (1 and an empty list: no drawn location)
   uint4 lst;    // start of each slot's entry list
   uint4 end;    // .x = end of slot 3's list
-  uint4 pad;
+  uint4 ctab;   // per slot, where its code lists' bounds start in the code table
 };
 
 // The R words of group g: lane t of word r stands for shot
@@ -504,7 +526,7 @@ __device__ __forceinline__ Hot draw_block(const LaunchArgs& a, uint64_t* slab, c
     if (R > 1 && !fr[r]) continue;
     const uint32_t n = (uint32_t)__builtin_popcountll(fr[r]);
     if (qn + n > sp::kQueueCap) {
-      flush_records(m, slab, q, qn, lane4 >> 2);
+      flush_records<R>(m, slab, q, qn, lane4 >> 2);
       qn = 0;
     }
     uint32_t* ud = reinterpret_cast<uint32_t*>(q.u + qn);   // wave-uniform bases
@@ -565,7 +587,7 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
     return;
   }
   draw_range<R, DENSE, true, UHI>(a, slab, q, qn, 0, m.nb_lazy, keys, w, wave, n_waves, lane4);
-  if (qn) flush_records(m, slab, q, qn, lane);
+  if (qn) flush_records<R>(m, slab, q, qn, lane);
   draw_range<R, DENSE, false, UHI>(a, slab, q, qn, m.nb_lazy, m.nb, keys, w, wave, n_waves, lane4);
 }
 
@@ -747,12 +769,19 @@ constexpr uint64_t kEagerTm = 1ull << 29;
 //   [0..3]  meta per slot: var0 << 8 | (channel + 1); 1 (channel 0, with an
 //           empty list) for a slot without a drawn location
 //   [4..7]  start of the slot's entry list; [8] end of slot 3's list
+//   [12..15] per slot, the start of its code bounds in the code table (0
+//           for a slot without a drawn location: the empty range [0, 0])
 // Entry lists: for every variable of the location (bit b), for every row k
 // of its column of M, the word k << 5 | b (so that e >> 2 is the row's LDS
 // byte offset and bits 0..4 of e are the bit index).
+// Code lists: for every code k = 1..m of the location's channel, the rows
+// that the Pauli of code k flips -- the symmetric difference of the columns
+// of the code's set bits -- each as the row's byte offset k << 3; the code
+// table holds the m + 1 bounds of a location's code lists.
 struct HostBlocks {
   std::vector<uint32_t> hot, cold;
   std::vector<uint32_t> entries;
+  std::vector<uint32_t> ctab, centries;
   uint32_t nb_lazy = 0;
 };
 
@@ -776,6 +805,8 @@ HostBlocks build_blocks(const sp_model& m, uint32_t r0, uint32_t r1) {
   const bool whole = r0 == 0 && r1 >= m.n_meas;
   int64_t cur = -1;
   std::vector<uint8_t> eager;   // per block
+  H.ctab = {0u, 0u};            // the empty range of slots without a drawn location
+  std::vector<uint32_t> rows[4], acc, tmp;
   for (uint32_t l = 0; l < m.n_locs; ++l) {
     if (!sp::loc_drawn(m, l)) continue;   // never fires, or reaches no output row
     if (!whole && !loc_reaches(m, l, r0, r1)) continue;
@@ -800,12 +831,35 @@ HostBlocks build_blocks(const sp_model& m, uint32_t r0, uint32_t r1) {
     if (Tm >= kEagerTm) eager.back() = 1;
     w[s] = (var0 << 8) | (uint32_t)(ch + 1);
     w[4 + s] = (uint32_t)H.entries.size();
-    for (uint32_t b = 0; b < sp::loc_bits(m.loc_kind[l]); ++b)
+    const uint32_t nbits = sp::loc_bits(m.loc_kind[l]);
+    for (uint32_t b = 0; b < nbits; ++b) {
+      rows[b].clear();
       for (uint32_t i = m.col_ptr[var0 + b]; i < m.col_ptr[var0 + b + 1]; ++i) {
         const uint32_t k = m.row_idx[i];
-        if (k >= r0 && k < r1) H.entries.push_back(((k - r0) << 5) | b);
+        if (k >= r0 && k < r1) {
+          H.entries.push_back(((k - r0) << 5) | b);
+          rows[b].push_back(k - r0);
+        }
       }
+    }
+    // Code k flips the XOR of the columns of its set bits (rows ascend in
+    // each column, so the symmetric differences stay sorted).
+    w[12 + s] = (uint32_t)H.ctab.size();
+    H.ctab.push_back((uint32_t)H.centries.size());
+    for (uint32_t code = 1; code <= c.m; ++code) {
+      acc.clear();
+      for (uint32_t b = 0; b < nbits; ++b) {
+        if (!((code >> b) & 1u)) continue;
+        tmp.clear();
+        std::set_symmetric_difference(acc.begin(), acc.end(), rows[b].begin(), rows[b].end(), std::back_inserter(tmp));
+        acc.swap(tmp);
+      }
+      for (uint32_t k : acc) H.centries.push_back(k << 3);
+      H.ctab.push_back((uint32_t)H.centries.size());
+    }
     if (H.entries.size() >= (1ull << 32)) throw sp::Error(SP_E_LIMIT, "more than 2^32 entries in M");
+    if (H.centries.size() >= (1ull << 30) || H.ctab.size() >= (1ull << 30))
+      throw sp::Error(SP_E_LIMIT, "more than 2^30 code-list entries (kernels address them with 32-bit offsets)");
     for (uint32_t t = s + 1; t <= 4; ++t) w[4 + t] = (uint32_t)H.entries.size();
   }
   // Lazy blocks first, then eager ones, each part keeping its order.
@@ -844,7 +898,7 @@ constexpr uint32_t kOneTileRowsMax = (80u * 1024u - 8u * sp::kQueueCap * sp::kQu
 constexpr uint32_t kTileRowsAuto = 4096;
 
 struct TileLayout {
-  size_t hot, cold, entries, c_mask, dense;
+  size_t hot, cold, entries, ctab, centries, c_mask, dense;
   uint32_t r0, rows, nb, nb_lazy, dense_words;
 };
 
@@ -881,6 +935,8 @@ Layout plan(const sp_model& m, int path, uint32_t tile_rows) {
     T.hot = off;     off = align256(off + 32 * ((size_t)T.nb + sp::kHotPad));
     T.cold = off;    off = align256(off + 64 * std::max<size_t>(T.nb, 1));
     T.entries = off; off = align256(off + 4 * std::max<size_t>(H.entries.size(), 1));
+    T.ctab = off;    off = align256(off + 4 * std::max<size_t>(H.ctab.size(), 1));
+    T.centries = off; off = align256(off + 4 * std::max<size_t>(H.centries.size(), 1));
     T.c_mask = off;  off = align256(off + 8 * std::max<size_t>(T.dense_words, 1));
     T.dense = off;
     if (path == SP_PATH_DENSE) off = align256(off + 8 * (size_t)m.n_vars * T.dense_words);
@@ -1098,6 +1154,8 @@ int sp_model_upload_tiled(const sp_model* model, int path, uint32_t tile_rows, v
       if (!H.hot.empty()) std::memcpy(&host[T.hot], H.hot.data(), 4 * H.hot.size());
       if (!H.cold.empty()) std::memcpy(&host[T.cold], H.cold.data(), 4 * H.cold.size());
       if (!H.entries.empty()) std::memcpy(&host[T.entries], H.entries.data(), 4 * H.entries.size());
+      if (!H.ctab.empty()) std::memcpy(&host[T.ctab], H.ctab.data(), 4 * H.ctab.size());
+      if (!H.centries.empty()) std::memcpy(&host[T.centries], H.centries.data(), 4 * H.centries.size());
       // c of rows [r0, r0 + rows), shifted to start at bit 0
       uint64_t* cm = reinterpret_cast<uint64_t*>(&host[T.c_mask]);
       for (uint32_t k = 0; k < T.rows; ++k) {
@@ -1128,6 +1186,8 @@ int sp_model_upload_tiled(const sp_model* model, int path, uint32_t tile_rows, v
       m.hot = (const uint4*)(base + T.hot);
       m.cold = (const uint4*)(base + T.cold);
       m.entries = (const uint32_t*)(base + T.entries);
+      m.ctab = (const uint32_t*)(base + T.ctab);
+      m.centries = (const uint32_t*)(base + T.centries);
       m.chans = (const uint32_t*)(base + L.chans);
       m.c_mask = (const uint64_t*)(base + T.c_mask);
       m.dense = p == SP_PATH_DENSE ? (const uint64_t*)(base + T.dense) : nullptr;
