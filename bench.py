@@ -3,12 +3,15 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
+The workload is the rotated surface-code memory experiment at distance 15,
+15 rounds (449 qubits, 3,585 measurements, about 10^5 fault variables),
+circuit-level noise at p = 1e-3 and at p = 5e-3, 10^7 shots per noise rate
+sampled in batches of 2^20 shots (nine full batches and one of 562,816).
 A step is one pass of the whole path -- keyed Philox draws, threshold
 select, 64-shot packing, out = M s + c over GF(2), store -- over one batch
-of 10^6 shots of the rotated surface-code memory experiment, distance 5,
-5 rounds (49 qubits, 145 measurements), circuit-level noise p = 1e-3.  Each
-step samples the next 10^6 shots (first_shot advances), with the model
-resident in HBM.  Prints one JSON line.
+at both noise rates (two launches, models resident in HBM, outputs into a
+resident buffer); step i samples batch i mod 10, so ten steps cover the
+10^7 shots of both rates.  Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -26,30 +29,39 @@ sys.path.insert(0, ROOT)
 
 METRIC = "measurement bits sampled/s (shots×meas), batched vs plain; p50/p99 latency"
 PEAK_VALU = 256 * 4 * 16 * 2.4e9      # int32 lane-ops/s: CUs x SIMDs x lanes x clock
-PHILOX_OPS = 40                         # 20 products 32x32->64 + 20 three-input XORs per block
+# Per-lane ALU work of one Philox4x32-10 block.  The counter is (l/4, shot
+# lo, shot hi, 0) and a wave of 64 shots shares l/4, the key and (almost
+# always) the high word, so round 1 and half of rounds 2-4 are wave-uniform
+# or independent of the block: what is left for each shot is 15 products
+# 32x32->64 and 17 three-input XORs.
+WORK_PER_BLOCK = 32
 KERNEL_SRC = os.path.join(ROOT, "paper_2311_03906_amd", "csrc", "sample.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sample_kernel_surface_d5_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sample_kernel_surface_d15_traffic.json")
+D15_TOTAL, D15_BATCH = 10_000_000, 1 << 20
+D15_PS = ("0.001", "0.005")
 
 
 def parse_args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU legs (profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
-    ap.add_argument("--legs", default="rep,d15,outputs,init,fig3,mix,small,serving",
-                    help="comma list of the other workloads to run (rep, d15, outputs, init, fig3, mix, small, serving)")
+    ap.add_argument("--legs", default="rep,d5,dense15,outputs,init,fig3,mix,small,serving",
+                    help="comma list of the other workloads to run "
+                         "(rep, d5, dense15, outputs, init, fig3, mix, small, serving, serving_steady)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
 
 
-def model_draw_work(m) -> tuple:
-    """(Philox blocks per shot, drawn locations per shot): one block per l/4
-    holding a drawn location, one threshold compare per drawn location."""
-    return int(m.dims.n_draw_blocks), int(m.dims.n_drawn)
+def work_ops(m, shots: int) -> int:
+    """Algorithmic ALU work of sampling `shots` shots of model m: per shot,
+    WORK_PER_BLOCK per Philox block and one threshold compare per drawn
+    location."""
+    return shots * (WORK_PER_BLOCK * int(m.dims.n_draw_blocks) + int(m.dims.n_drawn))
 
 
 def kernel_hash() -> str:
@@ -80,18 +92,44 @@ def pct(xs, q):
     return xs[min(len(xs) - 1, int(math.ceil(q / 100 * len(xs))) - 1)]
 
 
+def host_threads() -> int:
+    """Host threads the CPU legs use: the CPUs this process may run on,
+    at most 16 (one GPU's share of a shared host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(text: str, n_meas: int) -> dict:
+    """The oracle (a concrete Aaronson-Gottesman tableau run per shot) on a
+    fixed 2^12-shot subset of the workload: shots 0..4095 at p = 1e-3."""
     import oracle
     oracle.build(force=False)
     c = oracle.Circuit(text)
-    cores = os.cpu_count() or 1
-    shots = 64 * 2048
+    cores = host_threads()
+    shots = 1 << 12
     t0 = time.perf_counter()
     c.sample(seed=0, first_shot=0, shots=shots, n_threads=cores)
     dt = time.perf_counter() - t0
     return {"value": shots * n_meas / dt, "unit": "bits/s", "cores": cores, "kind": "oracle",
-            "sample": f"{shots} shots of the same circuit (seed 0), concrete A-G tableau per shot, "
-                      f"{cores} threads, {dt:.2f} s", "cpu": _cpu_model()}
+            "sample": f"subset: shots 0..{shots - 1} (2^12) of the d=15, p=1e-3 circuit, seed 0, concrete "
+                      f"A-G tableau per shot, {cores} threads, {dt:.2f} s", "cpu": _cpu_model()}
+
+
+def cpu_host_sampler(model, n_meas: int) -> dict:
+    """The paper's method on the host CPU (sp_sample_host: the same keyed
+    draws and the sparse product out = M s + c), one thread and all threads."""
+    cores = host_threads()
+    res = {"unit": "bits/s", "cpu": _cpu_model()}
+    for key, threads, shots in (("one_core", 1, 1 << 14), ("all_cores", cores, 1 << 18)):
+        model.sample_host(64, seed=0, first_shot=0, n_threads=threads)   # warm
+        t0 = time.perf_counter()
+        model.sample_host(shots, seed=0, first_shot=0, n_threads=threads)
+        dt = time.perf_counter() - t0
+        res[key] = {"value": shots * n_meas / dt, "threads": threads, "shots": shots, "seconds": dt}
+    return res
 
 
 def _cpu_model() -> str:
@@ -103,6 +141,17 @@ def _cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def traffic_per_launch():
+    """Scaled HBM bytes (FETCH_SIZE + WRITE_SIZE) per full-batch launch from
+    the committed counter profile, when it was taken of this sample.hip."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE))
+    if t.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
 
 
 def main():
@@ -127,32 +176,55 @@ def main():
     import paper_2311_03906_amd as sp
     from workloads import surface_memory, repetition_memory
 
-    shots = 1_000_000
-    text = surface_memory(5, 5, "0.001").text()
-    model = sp.Model(text)
-    dm = sp.DeviceModel(model, path="sparse")
-    n_meas = model.n_meas
-    n_blocks, n_drawn = model_draw_work(model)
-    out = torch.empty((n_meas, (shots + 63) // 64), dtype=torch.int64, device="cuda")
+    texts = {p: surface_memory(15, 15, p).text() for p in D15_PS}
+    models = {p: sp.Model(texts[p]) for p in D15_PS}
+    dms = {p: sp.DeviceModel(models[p], path="sparse") for p in D15_PS}
+    n_meas = models[D15_PS[0]].n_meas
+    out = torch.empty((n_meas, D15_BATCH // 64), dtype=torch.int64, device="cuda")
+    batches = [(f, min(D15_BATCH, D15_TOTAL - f)) for f in range(0, D15_TOTAL, D15_BATCH)]
+    # per-launch events on the stream the kernels run on (torch's current stream)
+    launches = []   # (p, shots, start event, end event) of the timed steps
+    timing = [False]
 
     def step(i):
-        dm.sample(shots, seed=0, first_shot=i * shots, out=out)
+        first, shots = batches[i % len(batches)]
+        for p in D15_PS:
+            if timing[0]:
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                dms[p].sample(shots, seed=0, first_shot=first, out=out)
+                b.record()
+                launches.append((p, shots, a, b))
+            else:
+                dms[p].sample(shots, seed=0, first_shot=first, out=out)
 
-    wall, lat = time_steps(step, args.steps, args.warmup, torch)
-    value = shots * n_meas * args.steps / wall
-    avg_ms = sum(lat) / len(lat)
-    ops = shots * (PHILOX_OPS * n_blocks + n_drawn)
-    achieved = ops / (avg_ms * 1e-3)
-
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        t = json.load(open(TRAFFIC_FILE))
-        if t.get("kernel_sha256_16") == kernel_hash():
-            traffic = t.get("hbm_bytes_per_launch")
-
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    timing[0] = True
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bits = sum(shots * n_meas for _, shots, _, _ in launches)
+    per_p = {}
+    for p in D15_PS:
+        ls = [(shots, a.elapsed_time(b)) for q, shots, a, b in launches if q == p]
+        ms = [t for _, t in ls]
+        ops = sum(work_ops(models[p], shots) for shots, _ in ls)
+        full = [t for shots, t in ls if shots == D15_BATCH]
+        per_p[p] = {"ms_per_launch_mean": sum(ms) / len(ms), "ms_full_batch_p50": pct(full, 50) if full else None,
+                    "ms_full_batch_p99": pct(full, 99) if full else None, "launches": len(ls),
+                    "bits_per_s_kernel": sum(s for s, _ in ls) * n_meas / (sum(ms) * 1e-3),
+                    "valu_frac": ops / (sum(ms) * 1e-3) / PEAK_VALU, "ops": ops}
+    kernel_ms = sum(v["ms_per_launch_mean"] * v["launches"] for v in per_p.values())
+    ops_total = sum(v["ops"] for v in per_p.values())
+    achieved = ops_total / (kernel_ms * 1e-3)
+    m0 = models[D15_PS[0]]
     rec = {
         "metric": METRIC,
-        "value": value,
+        "value": bits / wall,
         "unit": "bits/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -163,26 +235,35 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "rotated surface-code memory-Z, d=5, 5 rounds, p=1e-3 circuit-level noise, "
-                               "10^6 shots per step", "n_qubits": model.dims.n_qubits, "n_meas": n_meas,
-                   "n_vars": model.n_vars, "drawn_locations": n_drawn, "philox_blocks": n_blocks,
-                   "shots_per_step": shots, "path": "sparse", "launch": list(dm.launch), "seed": 0},
-        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": avg_ms},
+        "config": {"workload": "rotated surface-code memory-Z, d=15, 15 rounds, circuit-level noise p=1e-3 and "
+                               "p=5e-3, 10^7 shots per rate in 2^20-shot batches; one step = one batch at both rates",
+                   "n_qubits": m0.dims.n_qubits, "n_meas": n_meas,
+                   "n_vars": {p: models[p].n_vars for p in D15_PS}, "drawn_locations": int(m0.dims.n_drawn),
+                   "philox_blocks": int(m0.dims.n_draw_blocks), "shots_per_rate": D15_TOTAL,
+                   "batch_shots": D15_BATCH, "path": "sparse", "launch": list(dms[D15_PS[0]].launch), "seed": 0},
+        "latency_ms": {"per_rate": per_p},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "Tops/s",
-                     "frac": achieved / PEAK_VALU, "traffic": traffic,
-                     "kernel": "sample_kernel<1 or 2 words, sparse>",
-                     "ops_per_launch": ops},
+                     "frac": achieved / PEAK_VALU, "traffic": traffic_per_launch(),
+                     "kernel": "sample_kernel<1, 0>", "ops_per_full_launch": work_ops(m0, D15_BATCH),
+                     "work_model": f"{WORK_PER_BLOCK} lane-ops per (shot, Philox block) + 1 per (shot, drawn location)",
+                     "kernel_ms_mean": kernel_ms / len(launches)},
     }
+    step_ms = [sum(a.elapsed_time(b) for _, _, a, b in launches[k:k + len(D15_PS)])
+               for k in range(0, len(launches), len(D15_PS))]
+    rec["latency_ms"]["step_p50"] = pct(step_ms, 50)
+    rec["latency_ms"]["step_p99"] = pct(step_ms, 99)
+    del out
 
     legs = set() if args.no_extra else {x.strip() for x in args.legs.split(",") if x.strip()}
     if args.no_serving:
         legs.discard("serving")
-    unknown = legs - {"rep", "d15", "outputs", "init", "fig3", "mix", "small", "serving"}
+    known = {"rep", "d5", "dense15", "outputs", "init", "fig3", "mix", "small", "serving", "serving_steady"}
+    unknown = legs - known
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
         sys.exit(2)
     if legs:
-        rec["extra"] = extra_workloads(sp, torch, surface_memory, repetition_memory, legs)
+        rec["extra"] = extra_workloads(sp, torch, surface_memory, repetition_memory, legs, texts)
         if "init" in legs:
             rec["extra"]["initialization_d15"] = init_leg(sp, torch, surface_memory)
         if "fig3" in legs:
@@ -193,18 +274,23 @@ def main():
             rec["extra"]["batched_small_jobs_256"] = small_jobs_leg(sp, torch, surface_memory, repetition_memory)
         if "serving" in legs:
             rec["extra"]["serving_d15_pool16"] = serving_leg(sp, torch)
+        if "serving_steady" in legs:
+            rec["extra"]["serving_d15_pool16_steady"] = serving_steady_leg(sp, torch)
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(text, n_meas)
+        rec["cpu_baseline"] = cpu_baseline(texts["0.001"], n_meas)
+        rec["cpu_host_sampler"] = cpu_host_sampler(models["0.001"], n_meas)
     print(json.dumps(rec))
 
 
-def extra_workloads(sp, torch, surface_memory, repetition_memory, legs) -> dict:
+def extra_workloads(sp, torch, surface_memory, repetition_memory, legs, d15_texts) -> dict:
     """Other configurations, each timed over a few repetitions."""
     res = {}
     if "rep" in legs:
         res.update(_repetition_leg(sp, torch, repetition_memory))
-    if "d15" in legs:
-        res.update(_d15_leg(sp, torch, surface_memory))
+    if "d5" in legs:
+        res.update(_d5_leg(sp, torch, surface_memory))
+    if "dense15" in legs:
+        res.update(_dense15_leg(sp, torch, d15_texts))
     if "outputs" in legs:
         res.update(_outputs_leg(sp, torch, surface_memory))
     return res
@@ -222,11 +308,26 @@ def _repetition_leg(sp, torch, repetition_memory) -> dict:
     return res
 
 
+def _d5_leg(sp, torch, surface_memory) -> dict:
+    """Rotated surface code d=5, 5 rounds (49 qubits, 145 measurements),
+    p = 1e-3, 10^6 shots per launch, 200 launches advancing first_shot."""
+    m = sp.Model(surface_memory(5, 5, "0.001").text())
+    dm = sp.DeviceModel(m, path="sparse")
+    shots = 1_000_000
+    out = torch.empty((m.n_meas, (shots + 63) // 64), dtype=torch.int64, device="cuda")
+    wall, lat = time_steps(lambda i: dm.sample(shots, seed=0, first_shot=i * shots, out=out), 200, 10, torch)
+    mean = sum(lat) / len(lat)
+    return {"surface_d5_r5_p0.001_1e6_shots": {
+        "bits_per_s": shots * m.n_meas * 200 / wall, "ms_per_call": wall / 200 * 1e3, "p50_ms": pct(lat, 50),
+        "p99_ms": pct(lat, 99), "launch": list(dm.launch),
+        "valu_frac": work_ops(m, shots) / (mean * 1e-3) / PEAK_VALU}}
+
+
 def _d15_run(sp, torch, text, outputs="measurements") -> dict:
     """10^7 shots of one d=15 model in 2^20-shot launches."""
     m = sp.Model(text, outputs=outputs)
     dm = sp.DeviceModel(m, path="sparse")
-    total, batch = 10_000_000, 1 << 20
+    total, batch = D15_TOTAL, D15_BATCH
     out = torch.empty((m.n_meas, batch // 64), dtype=torch.int64, device="cuda")
     starts = list(range(0, total, batch))
 
@@ -241,16 +342,28 @@ def _d15_run(sp, torch, text, outputs="measurements") -> dict:
         one(i)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ops = total * (PHILOX_OPS * m.dims.n_draw_blocks + m.dims.n_drawn)
     return {"bits_per_s": total * m.n_meas / dt, "rows": m.n_meas, "seconds": dt, "batches": len(starts),
-            "launch": list(dm.launch), "valu_frac": ops / dt / PEAK_VALU, "nnz": int(m.dims.nnz)}
+            "launch": list(dm.launch), "valu_frac": work_ops(m, total) / dt / PEAK_VALU, "nnz": int(m.dims.nnz)}
 
 
-def _d15_leg(sp, torch, surface_memory) -> dict:
-    """Distance-15 surface code, 15 rounds, 10^7 shots in 2^20-shot batches."""
+def _dense15_leg(sp, torch, d15_texts) -> dict:
+    """The d=15 workload's dense form of M (per fired variable, XOR into
+    the rows set in its 3,585-bit column mask): three 2^20-shot launches
+    per noise rate.  Its work grows with the rows per fired variable, so it
+    is not the algorithmic path at this size; its own figure is the mask
+    words it reads per launch."""
     res = {}
-    for p in ("0.001", "0.005"):
-        res[f"surface_d15_r15_p{p}_1e7_shots"] = _d15_run(sp, torch, surface_memory(15, 15, p).text())
+    for p, text in d15_texts.items():
+        m = sp.Model(text)
+        dm = sp.DeviceModel(m, path="dense")
+        out = torch.empty((m.n_meas, D15_BATCH // 64), dtype=torch.int64, device="cuda")
+        lat = _event_ms(lambda: dm.sample(D15_BATCH, seed=0, first_shot=0, out=out), 3, torch)
+        ms = pct(lat, 50)
+        res[f"surface_d15_r15_p{p}_dense_2^20_shots"] = {
+            "ms_per_launch": ms, "bits_per_s": D15_BATCH * m.n_meas / (ms * 1e-3),
+            "valu_frac_vs_sparse_work": work_ops(m, D15_BATCH) / (ms * 1e-3) / PEAK_VALU,
+            "launch": list(dm.launch), "mask_words_per_variable": (m.n_meas + 63) // 64}
+        del out, dm
     return res
 
 
@@ -370,7 +483,7 @@ def _plain_vs_batched(sp, torch, jobs, reps=10) -> dict:
     schedule) and its graph replay."""
     from paper_2311_03906_amd import autotune
     bits = sum(j.shots * j.model.n_meas for j in jobs)
-    ops = sum(j.shots * (PHILOX_OPS * j.model.dims.n_draw_blocks + j.model.dims.n_drawn) for j in jobs)
+    ops = sum(j.shots * (WORK_PER_BLOCK * j.model.dims.n_draw_blocks + j.model.dims.n_drawn) for j in jobs)
 
     def plain():
         for j in jobs:
@@ -439,7 +552,7 @@ def serving_leg(sp, torch) -> dict:
     sat = loadgen.run(srv, models, burst, first_id=1_000_000)
     mu = sat["bits_per_s"] / mean_bits
     blocks = [m.dims.n_draw_blocks for m in models]
-    sat_ops = sum(int(s) * (PHILOX_OPS * blocks[mi] + models[mi].dims.n_drawn) for mi, s in zip(burst[1], burst[2]))
+    sat_ops = sum(int(s) * (WORK_PER_BLOCK * blocks[mi] + models[mi].dims.n_drawn) for mi, s in zip(burst[1], burst[2]))
     out = {"saturation": {"bits_per_s": sat["bits_per_s"], "requests_per_s": mu, "p50_ms": sat["p50_ms"],
                           "p99_ms": sat["p99_ms"], "requests": sat["requests"],
                           "valu_frac": sat_ops / sat["span_s"] / PEAK_VALU if sat["span_s"] > 0 else None},
@@ -447,11 +560,47 @@ def serving_leg(sp, torch) -> dict:
     for k, f in enumerate((0.25, 0.5, 0.75, 0.9, 1.0, 1.2)):
         plan = loadgen.poisson_plan(240, f * mu, len(models), 1_000, 1_000_000, seed=10 + k)
         r = loadgen.run(srv, models, plan, first_id=k * 10_000)
-        ops = sum(int(s) * (PHILOX_OPS * blocks[mi] + models[mi].dims.n_drawn) for mi, s in zip(plan[1], plan[2]))
+        ops = sum(int(s) * (WORK_PER_BLOCK * blocks[mi] + models[mi].dims.n_drawn) for mi, s in zip(plan[1], plan[2]))
         r["valu_frac"] = ops / r["span_s"] / PEAK_VALU if r["span_s"] > 0 else None
         r["rate_factor"] = f
         r["offered_requests_per_s"] = f * mu
         out["sweep"].append(r)
+    srv.close()
+    return out
+
+
+def serving_steady_leg(sp, torch) -> dict:
+    """The serving sweep of serving_leg at steady state: per rate factor,
+    two seeds, each at least 2,000 requests and at least 10 s of offered
+    load; reported over the middle 80% of completions (sustained bits/s,
+    p50, p99) with the spread over the seeds."""
+    from paper_2311_03906_amd import loadgen
+    from workloads.circuits import serving_pool
+    pool = serving_pool(0)
+    models = [sp.DeviceModel(sp.Model(c["circuit"].text()), path="sparse") for c in pool]
+    srv = sp.Server(arena_bytes=16 << 30, max_active=16)
+    mean_bits = (1e6 - 1e3) / math.log(1e3) * models[0].n_meas
+    burst = loadgen.poisson_plan(1024, 1e9, len(models), 1_000, 1_000_000, seed=1)
+    sat = loadgen.run(srv, models, burst, first_id=1_000_000)
+    cap = sat["steady"]["bits_per_s"]
+    mu = cap / mean_bits
+    out = {"saturation": {"bits_per_s": cap, "requests_per_s": mu, "requests": sat["requests"],
+                          "p50_ms": sat["steady"]["p50_ms"], "p99_ms": sat["steady"]["p99_ms"]},
+           "arena_bytes": 16 << 30, "max_active": 16, "sweep": []}
+    for k, f in enumerate((0.25, 0.5, 0.75, 0.9, 1.0, 1.2)):
+        n = int(max(2000, 10.0 * f * mu))
+        runs = []
+        for seed in (100 + k, 200 + k):
+            print(f"serving steady f={f} seed={seed} n={n}", file=sys.stderr, flush=True)
+            r = loadgen.run(srv, models, loadgen.poisson_plan(n, f * mu, len(models), 1_000, 1_000_000, seed=seed),
+                            first_id=seed * 100_000)
+            runs.append({"seed": seed, "requests": r["requests"], "offered_s": n / (f * mu), **r["steady"]})
+        row = {"rate_factor": f, "offered_requests_per_s": f * mu, "offered_bits_per_s": f * cap, "runs": runs}
+        for key in ("bits_per_s", "p50_ms", "p99_ms"):
+            v = [x[key] for x in runs]
+            row[key] = sum(v) / len(v)
+            row[key + "_spread"] = max(v) - min(v)
+        out["sweep"].append(row)
     srv.close()
     return out
 

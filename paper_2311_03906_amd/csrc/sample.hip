@@ -330,7 +330,7 @@ __device__ __forceinline__ uint32_t lds_addr(const void* p) {
   return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
 }
 __device__ __forceinline__ void lds_xor(uint32_t addr, uint64_t v) {
-  __atomic_fetch_xor((__attribute__((address_space(3))) uint64_t*)addr, v, __ATOMIC_RELAXED);
+  __atomic_fetch_xor((__attribute__((address_space(3))) uint64_t*)(uintptr_t)addr, v, __ATOMIC_RELAXED);
 }
 
 // Walks the code list [lo, hi) of one fired location for one shot: the

@@ -27,8 +27,10 @@ def poisson_plan(n: int, rate: float, n_models: int, shots_lo: int, shots_hi: in
     return arrivals, models, shots
 
 
-def run(server, models: list, plan, first_id: int = 0) -> dict:
-    """Drives `server` with `plan`; returns latencies and throughput."""
+def run(server, models: list, plan, first_id: int = 0, trim: float = 0.1) -> dict:
+    """Drives `server` with `plan`; returns latencies and throughput over the
+    whole run, and (`steady`) over its middle: the requests completing
+    between the completions of the first and last `trim` fraction."""
     arrivals, midx, shots = plan
     n = len(arrivals)
     tickets = [None] * n
@@ -69,8 +71,21 @@ def run(server, models: list, plan, first_id: int = 0) -> dict:
     last = max(r["t_done_ns"] for r, _, _ in done)
     bits = sum(s * m for _, s, m in done)
     span = (last - first) * 1e-9
-    return {"requests": len(done), "refused": len(err), "bits": bits, "span_s": span,
-            "bits_per_s": bits / span if span > 0 else 0.0,
-            "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
-            "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
-            "mean_ms": float(lat.mean()) if len(lat) else None}
+    res = {"requests": len(done), "refused": len(err), "bits": bits, "span_s": span,
+           "bits_per_s": bits / span if span > 0 else 0.0,
+           "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+           "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+           "mean_ms": float(lat.mean()) if len(lat) else None}
+    # steady part: completions between the k0-th and k1-th completion
+    order = sorted(range(len(done)), key=lambda i: done[i][0]["t_done_ns"])
+    k0, k1 = int(trim * len(order)), int((1.0 - trim) * len(order)) - 1
+    if k1 > k0:
+        t0 = done[order[k0]][0]["t_done_ns"]
+        t1 = done[order[k1]][0]["t_done_ns"]
+        mid = order[k0 + 1: k1 + 1]
+        mbits = sum(done[i][1] * done[i][2] for i in mid)
+        mlat = lat[mid]
+        res["steady"] = {"requests": len(mid), "window_s": (t1 - t0) * 1e-9,
+                         "bits_per_s": mbits / ((t1 - t0) * 1e-9) if t1 > t0 else 0.0,
+                         "p50_ms": float(np.percentile(mlat, 50)), "p99_ms": float(np.percentile(mlat, 99))}
+    return res
