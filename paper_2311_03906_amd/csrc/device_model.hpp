@@ -17,8 +17,8 @@ struct DevModel {
   const uint4* hot;          // [nb + kHotPad][2]: tm1[4] | (blk, 0, 0, 0), read for every block
   const uint4* cold;         // [nb][4]: meta[4] | lst[0..3] | (lst[4], 0, 0, 0) | 0, read when a block fires
   const uint32_t* entries;   // merged (row << 5 | bit) lists, one per drawn location
-  const uint32_t* ctab;      // per drawn location, the m + 1 bounds of its code lists in centries
-  const uint32_t* centries;  // per location and code, the flipped rows' byte offsets (row << 3)
+  const uint32_t* btab;      // per drawn location, the bounds of its code bits' lists in bentries
+  const uint32_t* bentries;  // per location and code bit, its column's rows as byte offsets (row << 3)
   const uint32_t* chans;     // [nch][16]: kind | m << 8, T_1..T_{m-1}, then 0xFFFFFFFF
   const uint64_t* c_mask;    // [ceil(n_meas/64)]
   const uint64_t* dense;     // [n_vars][dense_words] (dense path only)

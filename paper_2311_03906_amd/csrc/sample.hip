@@ -26,7 +26,6 @@
 
 #include <algorithm>
 #include <cstring>
-#include <iterator>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -333,15 +332,15 @@ __device__ __forceinline__ void lds_xor(uint32_t addr, uint64_t v) {
   __atomic_fetch_xor((__attribute__((address_space(3))) uint64_t*)(uintptr_t)addr, v, __ATOMIC_RELAXED);
 }
 
-// Walks the code list [lo, hi) of one fired location for one shot: the
-// entries are the byte offsets (row << 3) of the slab rows that the fired
-// Pauli flips, so each is one XOR of the shot's bit (`bit`) into the slab
-// at LDS address `base`.  Eight entry loads are kept in flight.  BASE0: the
-// slab starts at LDS address 0, so an entry is its row's address.
+// Walks bentries[lo, hi) for one shot: each entry is the byte offset
+// (row << 3) of a slab row to flip, so each is one XOR of the shot's bit
+// (`bit`) into the slab at LDS address `base`.  Eight entry loads are kept
+// in flight.  BASE0: the slab starts at LDS address 0, so an entry is its
+// row's address.
 template <bool BASE0>
-__device__ __forceinline__ void walk_code(const DevModel& m, uint32_t base, uint32_t lo, uint32_t hi, uint64_t bit) {
+__device__ __forceinline__ void walk_rows(const DevModel& m, uint32_t base, uint32_t lo, uint32_t hi, uint64_t bit) {
   // 32-bit byte offsets from a uniform base, constant steps as immediates
-  const SP_GLOBAL_AS char* ce = (const SP_GLOBAL_AS char*)m.centries;
+  const SP_GLOBAL_AS char* ce = (const SP_GLOBAL_AS char*)m.bentries;
   if (BASE0) base = 0;
   uint32_t o = lo << 2;
   const uint32_t o1 = hi << 2;
@@ -376,11 +375,11 @@ struct Queue {
 };
 
 // Evaluates the queued records, one per lane: the lane reloads its block's
-// thresholds, channels and code-table starts, and for every location that
-// fired in its shot finds the Pauli code from the draw (lane_code) and walks
-// that code's list, flipping its shot's bit in every row it names.  A lane
-// with several fired locations takes them one after another.  Everything
-// but the queueing is shared by up to 64 records.
+// thresholds, channels and bit-list bounds, and for every location that
+// fired in its shot finds the Pauli code from the draw (lane_code) and flips
+// its shot's bit in the rows of the code's set bits' columns.  A lane with
+// several fired locations takes them one after another.  Everything but the
+// queueing is shared by up to 64 records.
 template <int R>
 __device__ __forceinline__ void flush_records(const DevModel& m, uint64_t* slab, const Queue& q, uint32_t qn,
                                               uint32_t lane) {
@@ -390,8 +389,8 @@ __device__ __forceinline__ void flush_records(const DevModel& m, uint64_t* slab,
     const uint32_t tag = q.t[lane];
     const uint32_t b = tag >> 8;
     const uint4 tm1 = *(const SP_GLOBAL_AS uint4*)((const SP_GLOBAL_AS char*)m.hot + (b << 5));
-    const SP_GLOBAL_AS char* cw = (const SP_GLOBAL_AS char*)m.cold + (b << 6);   // meta | lst | end | ctab
-    const uint4 meta = *(const SP_GLOBAL_AS uint4*)cw, ct = *(const SP_GLOBAL_AS uint4*)(cw + 48);
+    const SP_GLOBAL_AS char* cw = (const SP_GLOBAL_AS char*)m.cold + (b << 6);   // meta | lst | end | btab
+    const uint4 meta = *(const SP_GLOBAL_AS uint4*)cw, bt = *(const SP_GLOBAL_AS uint4*)(cw + 48);
     uint32_t fired = (uint32_t)(u.x <= tm1.x) | (uint32_t)(u.y <= tm1.y) << 1 | (uint32_t)(u.z <= tm1.z) << 2 |
                      (uint32_t)(u.w <= tm1.w) << 3;
     const uint64_t bit = 1ull << ((tag >> 2) & 63u);
@@ -401,13 +400,22 @@ __device__ __forceinline__ void flush_records(const DevModel& m, uint64_t* slab,
       fired &= fired - 1u;
       const uint32_t us = s == 0 ? u.x : s == 1 ? u.y : s == 2 ? u.z : u.w;
       const uint32_t mt = s == 0 ? meta.x : s == 1 ? meta.y : s == 2 ? meta.z : meta.w;
-      const uint32_t c0 = s == 0 ? ct.x : s == 1 ? ct.y : s == 2 ? ct.z : ct.w;
-      // A slot without a drawn location (threshold 0, fires at u = 0 only)
-      // has the coin channel and an empty code list.
-      const uint32_t code = lane_code(m.chans, mt & 0xFFu, us);
-      const uint32_t lo = ld32(m.ctab, c0 + code - 1u), hi = ld32(m.ctab, c0 + code);
-      if (base == 0) walk_code<true>(m, base, lo, hi, bit);
-      else walk_code<false>(m, base, lo, hi, bit);
+      const uint32_t c0 = s == 0 ? bt.x : s == 1 ? bt.y : s == 2 ? bt.z : bt.w;
+      // The Pauli of the code flips the XOR of the columns of its set bits:
+      // walking each set bit's column flips every row the right number of
+      // times (a row in two of them twice, which cancels).  The bits' lists
+      // lie one after another, so a run of consecutive set bits is one
+      // range.  A slot without a drawn location (threshold 0, fires at u = 0
+      // only) has the coin channel and an empty list.
+      uint32_t code = lane_code(m.chans, mt & 0xFFu, us);
+      while (code) {
+        const uint32_t j = (uint32_t)__builtin_ctz(code);
+        const uint32_t n = (uint32_t)__builtin_ctz(~(code >> j));   // length of the run from bit j
+        code &= ~(((1u << n) - 1u) << j);
+        const uint32_t lo = ld32(m.btab, c0 + j), hi = ld32(m.btab, c0 + j + n);
+        if (base == 0) walk_rows<true>(m, base, lo, hi, bit);
+        else walk_rows<false>(m, base, lo, hi, bit);
+      }
     }
   }
   wave_sync();
@@ -424,7 +432,7 @@ struct Cold {
   uint4 meta;   // var0 << 8 | channel + 1 per slot (1 and an empty list: no drawn location)
   uint4 lst;    // start of each slot's entry list
   uint4 end;    // .x = end of slot 3's list
-  uint4 ctab;   // per slot, where its code lists' bounds start in the code table
+  uint4 btab;   // per slot, where its bit lists' bounds start in btab
 };
 
 // The R words of group g: lane t of word r stands for shot
@@ -769,19 +777,17 @@ constexpr uint64_t kEagerTm = 1ull << 29;
 //   [0..3]  meta per slot: var0 << 8 | (channel + 1); 1 (channel 0, with an
 //           empty list) for a slot without a drawn location
 //   [4..7]  start of the slot's entry list; [8] end of slot 3's list
-//   [12..15] per slot, the start of its code bounds in the code table (0
-//           for a slot without a drawn location: the empty range [0, 0])
+//   [12..15] per slot, the start of its bit-list bounds in btab (0 for a
+//           slot without a drawn location: the empty range [0, 0])
 // Entry lists: for every variable of the location (bit b), for every row k
 // of its column of M, the word k << 5 | b (so that e >> 2 is the row's LDS
 // byte offset and bits 0..4 of e are the bit index).
-// Code lists: for every code k = 1..m of the location's channel, the rows
-// that the Pauli of code k flips -- the symmetric difference of the columns
-// of the code's set bits -- each as the row's byte offset k << 3; the code
-// table holds the m + 1 bounds of a location's code lists.
+// Bit lists: the same columns without the bit tags, each row as its byte
+// offset k << 3, bit after bit; btab holds a location's nbits + 1 bounds.
 struct HostBlocks {
   std::vector<uint32_t> hot, cold;
   std::vector<uint32_t> entries;
-  std::vector<uint32_t> ctab, centries;
+  std::vector<uint32_t> btab, bentries;
   uint32_t nb_lazy = 0;
 };
 
@@ -805,8 +811,8 @@ HostBlocks build_blocks(const sp_model& m, uint32_t r0, uint32_t r1) {
   const bool whole = r0 == 0 && r1 >= m.n_meas;
   int64_t cur = -1;
   std::vector<uint8_t> eager;   // per block
-  H.ctab = {0u, 0u};            // the empty range of slots without a drawn location
-  std::vector<uint32_t> rows[4], acc, tmp;
+  H.btab = {0u, 0u};            // the empty range of slots without a drawn location
+  std::vector<uint32_t> rows[4];
   for (uint32_t l = 0; l < m.n_locs; ++l) {
     if (!sp::loc_drawn(m, l)) continue;   // never fires, or reaches no output row
     if (!whole && !loc_reaches(m, l, r0, r1)) continue;
@@ -842,24 +848,15 @@ HostBlocks build_blocks(const sp_model& m, uint32_t r0, uint32_t r1) {
         }
       }
     }
-    // Code k flips the XOR of the columns of its set bits (rows ascend in
-    // each column, so the symmetric differences stay sorted).
-    w[12 + s] = (uint32_t)H.ctab.size();
-    H.ctab.push_back((uint32_t)H.centries.size());
-    for (uint32_t code = 1; code <= c.m; ++code) {
-      acc.clear();
-      for (uint32_t b = 0; b < nbits; ++b) {
-        if (!((code >> b) & 1u)) continue;
-        tmp.clear();
-        std::set_symmetric_difference(acc.begin(), acc.end(), rows[b].begin(), rows[b].end(), std::back_inserter(tmp));
-        acc.swap(tmp);
-      }
-      for (uint32_t k : acc) H.centries.push_back(k << 3);
-      H.ctab.push_back((uint32_t)H.centries.size());
+    w[12 + s] = (uint32_t)H.btab.size();
+    H.btab.push_back((uint32_t)H.bentries.size());
+    for (uint32_t b = 0; b < nbits; ++b) {
+      for (uint32_t k : rows[b]) H.bentries.push_back(k << 3);
+      H.btab.push_back((uint32_t)H.bentries.size());
     }
     if (H.entries.size() >= (1ull << 32)) throw sp::Error(SP_E_LIMIT, "more than 2^32 entries in M");
-    if (H.centries.size() >= (1ull << 30) || H.ctab.size() >= (1ull << 30))
-      throw sp::Error(SP_E_LIMIT, "more than 2^30 code-list entries (kernels address them with 32-bit offsets)");
+    if (H.bentries.size() >= (1ull << 30) || H.btab.size() >= (1ull << 30))
+      throw sp::Error(SP_E_LIMIT, "more than 2^30 bit-list entries (kernels address them with 32-bit offsets)");
     for (uint32_t t = s + 1; t <= 4; ++t) w[4 + t] = (uint32_t)H.entries.size();
   }
   // Lazy blocks first, then eager ones, each part keeping its order.
@@ -898,7 +895,7 @@ constexpr uint32_t kOneTileRowsMax = (80u * 1024u - 8u * sp::kQueueCap * sp::kQu
 constexpr uint32_t kTileRowsAuto = 4096;
 
 struct TileLayout {
-  size_t hot, cold, entries, ctab, centries, c_mask, dense;
+  size_t hot, cold, entries, btab, bentries, c_mask, dense;
   uint32_t r0, rows, nb, nb_lazy, dense_words;
 };
 
@@ -935,8 +932,8 @@ Layout plan(const sp_model& m, int path, uint32_t tile_rows) {
     T.hot = off;     off = align256(off + 32 * ((size_t)T.nb + sp::kHotPad));
     T.cold = off;    off = align256(off + 64 * std::max<size_t>(T.nb, 1));
     T.entries = off; off = align256(off + 4 * std::max<size_t>(H.entries.size(), 1));
-    T.ctab = off;    off = align256(off + 4 * std::max<size_t>(H.ctab.size(), 1));
-    T.centries = off; off = align256(off + 4 * std::max<size_t>(H.centries.size(), 1));
+    T.btab = off;    off = align256(off + 4 * std::max<size_t>(H.btab.size(), 1));
+    T.bentries = off; off = align256(off + 4 * std::max<size_t>(H.bentries.size(), 1));
     T.c_mask = off;  off = align256(off + 8 * std::max<size_t>(T.dense_words, 1));
     T.dense = off;
     if (path == SP_PATH_DENSE) off = align256(off + 8 * (size_t)m.n_vars * T.dense_words);
@@ -1154,8 +1151,8 @@ int sp_model_upload_tiled(const sp_model* model, int path, uint32_t tile_rows, v
       if (!H.hot.empty()) std::memcpy(&host[T.hot], H.hot.data(), 4 * H.hot.size());
       if (!H.cold.empty()) std::memcpy(&host[T.cold], H.cold.data(), 4 * H.cold.size());
       if (!H.entries.empty()) std::memcpy(&host[T.entries], H.entries.data(), 4 * H.entries.size());
-      if (!H.ctab.empty()) std::memcpy(&host[T.ctab], H.ctab.data(), 4 * H.ctab.size());
-      if (!H.centries.empty()) std::memcpy(&host[T.centries], H.centries.data(), 4 * H.centries.size());
+      if (!H.btab.empty()) std::memcpy(&host[T.btab], H.btab.data(), 4 * H.btab.size());
+      if (!H.bentries.empty()) std::memcpy(&host[T.bentries], H.bentries.data(), 4 * H.bentries.size());
       // c of rows [r0, r0 + rows), shifted to start at bit 0
       uint64_t* cm = reinterpret_cast<uint64_t*>(&host[T.c_mask]);
       for (uint32_t k = 0; k < T.rows; ++k) {
@@ -1186,8 +1183,8 @@ int sp_model_upload_tiled(const sp_model* model, int path, uint32_t tile_rows, v
       m.hot = (const uint4*)(base + T.hot);
       m.cold = (const uint4*)(base + T.cold);
       m.entries = (const uint32_t*)(base + T.entries);
-      m.ctab = (const uint32_t*)(base + T.ctab);
-      m.centries = (const uint32_t*)(base + T.centries);
+      m.btab = (const uint32_t*)(base + T.btab);
+      m.bentries = (const uint32_t*)(base + T.bentries);
       m.chans = (const uint32_t*)(base + L.chans);
       m.c_mask = (const uint64_t*)(base + T.c_mask);
       m.dense = p == SP_PATH_DENSE ? (const uint64_t*)(base + T.dense) : nullptr;
