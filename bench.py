@@ -51,7 +51,7 @@ def parse_args():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
     ap.add_argument("--legs", default="rep,d5,dense15,outputs,init,fig3,mix,small,serving",
                     help="comma list of the other workloads to run "
-                         "(rep, d5, dense15, outputs, init, fig3, mix, small, serving, serving_steady)")
+                         "(rep, d5, dense15, outputs, init, fig3, mix, small, serving)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -246,7 +246,9 @@ def main():
                      "frac": achieved / PEAK_VALU, "traffic": traffic_per_launch(),
                      "kernel": "sample_kernel<1, 0>", "ops_per_full_launch": work_ops(m0, D15_BATCH),
                      "work_model": f"{WORK_PER_BLOCK} lane-ops per (shot, Philox block) + 1 per (shot, drawn location)",
-                     "kernel_ms_mean": kernel_ms / len(launches)},
+                     "kernel_ms_mean": kernel_ms / len(launches),
+                     "per_rate": {p: {"frac": v["valu_frac"], "ms_full_batch_p50": v["ms_full_batch_p50"],
+                                      "bits_per_s_kernel": v["bits_per_s_kernel"]} for p, v in per_p.items()}},
     }
     step_ms = [sum(a.elapsed_time(b) for _, _, a, b in launches[k:k + len(D15_PS)])
                for k in range(0, len(launches), len(D15_PS))]
@@ -257,7 +259,7 @@ def main():
     legs = set() if args.no_extra else {x.strip() for x in args.legs.split(",") if x.strip()}
     if args.no_serving:
         legs.discard("serving")
-    known = {"rep", "d5", "dense15", "outputs", "init", "fig3", "mix", "small", "serving", "serving_steady"}
+    known = {"rep", "d5", "dense15", "outputs", "init", "fig3", "mix", "small", "serving"}
     unknown = legs - known
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
@@ -274,11 +276,10 @@ def main():
             rec["extra"]["batched_small_jobs_256"] = small_jobs_leg(sp, torch, surface_memory, repetition_memory)
         if "serving" in legs:
             rec["extra"]["serving_d15_pool16"] = serving_leg(sp, torch)
-        if "serving_steady" in legs:
-            rec["extra"]["serving_d15_pool16_steady"] = serving_steady_leg(sp, torch)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(texts["0.001"], n_meas)
-        rec["cpu_host_sampler"] = cpu_host_sampler(models["0.001"], n_meas)
+        # the paper's method on the host CPU, beside the oracle
+        rec["cpu_baseline"]["host_sampler"] = cpu_host_sampler(models["0.001"], n_meas)
     print(json.dumps(rec))
 
 
@@ -364,6 +365,11 @@ def _dense15_leg(sp, torch, d15_texts) -> dict:
             "valu_frac_vs_sparse_work": work_ops(m, D15_BATCH) / (ms * 1e-3) / PEAK_VALU,
             "launch": list(dm.launch), "mask_words_per_variable": (m.n_meas + 63) // 64}
         del out, dm
+        from paper_2311_03906_amd import autotune
+        tuned, times = autotune.tune_path(m, shots=1 << 18, reps=2, cache=None)
+        res[f"surface_d15_r15_p{p}_tuned"] = {"path": tuned.path, "launch": list(tuned.launch),
+                                              "ms_2^18_shots": times}
+        del tuned
     return res
 
 
@@ -513,16 +519,29 @@ def _plain_vs_batched(sp, torch, jobs, reps=10) -> dict:
 def batched_mix_leg(sp, torch) -> dict:
     """64 circuits: repetition d 3..25 and rotated surface d 3..11 (odd),
     rounds = d, p log-uniform in [1e-4, 1e-2], shots log-uniform in
-    [1e4, 1e6], sampling seed = circuit index (the mix is seeded, seed 0)."""
+    [1e4, 1e6], sampling seed = circuit index (the mix is seeded, seed 0).
+    Each model's evaluation path and launch shape come from the autotuner
+    (tune_path: both paths timed on 2^18 shots, cached per circuit class)."""
+    from paper_2311_03906_amd import autotune
     from workloads.circuits import batched_mix
-    jobs, models = [], {}
+    jobs, models, classes = [], {}, {}
+    cache = autotune.Cache(path=None)
+    t0 = time.perf_counter()
     for m in batched_mix(0):
         text = m["circuit"].text()
         if text not in models:
             mod = sp.Model(text)
-            models[text] = sp.DeviceModel(mod)
+            dm, times = autotune.tune_path(mod, shots=1 << 18, reps=2, cache=cache)
+            models[text] = dm
+            classes[autotune.path_class(mod)] = {"path": dm.path, "launch": list(dm.launch),
+                                                 "ms_2^18_shots": times}
         jobs.append(sp.Job(models[text], m["shots"], seed=m["seed"]))
-    return _plain_vs_batched(sp, torch, jobs)
+    res = _plain_vs_batched(sp, torch, jobs)
+    res["tuning_s"] = time.perf_counter() - t0
+    res["paths"] = {p: sum(1 for j in jobs if j.model.path == p) for p in ("sparse", "dense")}
+    res["tuned_classes"] = len(classes)
+    res["dense_classes"] = sorted(c for c, v in classes.items() if v["path"] == "dense")
+    return res
 
 
 def small_jobs_leg(sp, torch, surface_memory, repetition_memory) -> dict:
@@ -539,41 +558,11 @@ def serving_leg(sp, torch) -> dict:
     circuits (p log-uniform in [1e-3, 5e-3], the first two 1e-3 and 5e-3):
     Poisson arrivals, circuit uniform over the pool, shots log-uniform in
     [1e3, 1e6], seed = request id, outputs in a 16 GiB HBM arena.  The
-    saturation rate is measured with a burst; the open-loop sweep runs at
-    0.25 .. 1.2 of it."""
-    from paper_2311_03906_amd import loadgen
-    from workloads.circuits import serving_pool
-    pool = serving_pool(0)
-    models = [sp.DeviceModel(sp.Model(c["circuit"].text()), path="sparse") for c in pool]
-    srv = sp.Server(arena_bytes=16 << 30, max_active=16)
-    mean_shots = (1e6 - 1e3) / math.log(1e3)
-    mean_bits = mean_shots * models[0].n_meas
-    burst = loadgen.poisson_plan(128, 1e9, len(models), 1_000, 1_000_000, seed=1)
-    sat = loadgen.run(srv, models, burst, first_id=1_000_000)
-    mu = sat["bits_per_s"] / mean_bits
-    blocks = [m.dims.n_draw_blocks for m in models]
-    sat_ops = sum(int(s) * (WORK_PER_BLOCK * blocks[mi] + models[mi].dims.n_drawn) for mi, s in zip(burst[1], burst[2]))
-    out = {"saturation": {"bits_per_s": sat["bits_per_s"], "requests_per_s": mu, "p50_ms": sat["p50_ms"],
-                          "p99_ms": sat["p99_ms"], "requests": sat["requests"],
-                          "valu_frac": sat_ops / sat["span_s"] / PEAK_VALU if sat["span_s"] > 0 else None},
-           "arena_bytes": 16 << 30, "max_active": 16, "sweep": []}
-    for k, f in enumerate((0.25, 0.5, 0.75, 0.9, 1.0, 1.2)):
-        plan = loadgen.poisson_plan(240, f * mu, len(models), 1_000, 1_000_000, seed=10 + k)
-        r = loadgen.run(srv, models, plan, first_id=k * 10_000)
-        ops = sum(int(s) * (WORK_PER_BLOCK * blocks[mi] + models[mi].dims.n_drawn) for mi, s in zip(plan[1], plan[2]))
-        r["valu_frac"] = ops / r["span_s"] / PEAK_VALU if r["span_s"] > 0 else None
-        r["rate_factor"] = f
-        r["offered_requests_per_s"] = f * mu
-        out["sweep"].append(r)
-    srv.close()
-    return out
-
-
-def serving_steady_leg(sp, torch) -> dict:
-    """The serving sweep of serving_leg at steady state: per rate factor,
-    two seeds, each at least 2,000 requests and at least 10 s of offered
-    load; reported over the middle 80% of completions (sustained bits/s,
-    p50, p99) with the spread over the seeds."""
+    saturation rate is measured with a burst of 1,024 requests; the
+    open-loop sweep runs at 0.25 .. 1.2 of it, per rate two seeds of at
+    least 2,000 requests and 10 s of offered load each, reported over the
+    middle 80% of completions (sustained bits/s, p50, p99) with the spread
+    over the seeds."""
     from paper_2311_03906_amd import loadgen
     from workloads.circuits import serving_pool
     pool = serving_pool(0)

@@ -184,3 +184,25 @@ def test_batch_with_row_tiled_models(schedule):
     b.launch()
     torch.cuda.synchronize()
     _check_against_oracle(jobs)
+
+
+def test_autotuner_path_search_and_cache():
+    """tune_path times both evaluation paths, keeps the faster, caches the
+    choice per circuit class; the tuned model samples exactly the oracle's
+    bits, and a cache hit rebuilds the same path and launch shape."""
+    from paper_2311_03906_amd import autotune
+    text = surface_memory(5, 5, "0.003").text()
+    _say("autotune path search")
+    m = sp.Model(text)
+    cache = autotune.Cache(path=None)
+    dm, times = autotune.tune_path(m, shots=64 * 512, reps=1, cache=cache,
+                                   candidates=((4, 1), (8, 1), (8, 2)))
+    assert set(times) == {"sparse", "dense"} and dm.path == min(times, key=times.get)
+    got = sp.to_numpy_bits(dm.sample(5000, seed=3, first_shot=64))[: m.n_meas]
+    torch.cuda.synchronize()
+    want = oracle.Circuit(text).sample(seed=3, first_shot=64, shots=5000)
+    assert np.array_equal(got, want)
+    hit = cache.get(autotune.path_class(m))
+    assert hit["path"] == dm.path and tuple(hit["launch"]) == dm.launch
+    dm2, times2 = autotune.tune_path(m, cache=cache)
+    assert dm2.path == dm.path and dm2.launch == dm.launch and times2 == times
