@@ -673,7 +673,75 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
         // chunk): thread tid takes word tid % RW of chunk tid / RW, so a
         // wave's loads cover consecutive words and every lane works.
         const uint32_t nch = min(kMaxChunks, kThreads / RW);   // column chunks
-        {
+        if (!TAB_LDS) {
+          // A tableau in global memory: in the columns where row p has x or
+          // z, one pass reads each word once, adds it to the g sums and
+          // writes it updated (rows with x_a take row p's x/z; destabilizer
+          // p-n becomes row p; row p becomes Z_a), with eight columns' loads
+          // in flight.  Word w of such a column q belongs to thread
+          // (w, q mod nch) alone, and the mask comes from LDS, so no thread
+          // reads a word another one writes.  In the other columns only
+          // destabilizer p-n changes (it becomes row p's zeros), one thread
+          // per column.
+          const uint32_t w = tid % RW, chunk = tid / RW;
+          const uint32_t dr = p - n, dw = dr >> 6;
+          const uint64_t db = 1ull << (dr & 63);
+          for (uint32_t q = tid; q < n; q += kThreads) {
+            if (((s_rpx[q >> 6] | s_rpz[q >> 6]) >> (q & 63)) & 1u) continue;
+            const uint64_t vx = X[(size_t)q * RW + dw], vz = Z[(size_t)q * RW + dw];
+            if (vx & db) X[(size_t)q * RW + dw] = vx & ~db;
+            if (vz & db) Z[(size_t)q * RW + dw] = vz & ~db;
+          }
+          if (chunk < nch) {
+            uint64_t c0 = 0, c1 = 0;
+            const uint64_t mw = s_mask[w];   // x_a of every row but p
+            const bool fix = w == pw || w == dw;   // words every such column rewrites
+            if (mw || fix) {
+              for (uint32_t q0 = chunk; q0 < n; q0 += 8 * nch) {
+                uint64_t vx[8], vz[8], lx[8], lz[8];
+                bool act[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                  const uint32_t q = q0 + (uint32_t)i * nch;
+                  lx[i] = lz[i] = 0;
+                  if (q < n) {
+                    lx[i] = ((s_rpx[q >> 6] >> (q & 63)) & 1u) ? ~0ull : 0ull;
+                    lz[i] = ((s_rpz[q >> 6] >> (q & 63)) & 1u) ? ~0ull : 0ull;
+                  }
+                  act[i] = q < n && (lx[i] | lz[i]) && (fix || mw);
+                  vx[i] = act[i] ? X[(size_t)q * RW + w] : 0ull;
+                  vz[i] = act[i] ? Z[(size_t)q * RW + w] : 0ull;
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                  if (!act[i]) continue;
+                  const uint32_t q = q0 + (uint32_t)i * nch;
+                  if (mw && (lx[i] | lz[i])) {
+                    uint64_t plus, minus;
+                    g_masks(lx[i], lz[i], vx[i], vz[i], plus, minus);
+                    c1 ^= c0 & plus;
+                    c0 ^= plus;
+                    c1 ^= ~c0 & minus;
+                    c0 ^= minus;
+                  }
+                  uint64_t nx = vx[i] ^ (mw & lx[i]), nz = vz[i] ^ (mw & lz[i]);
+                  if (w == dw) {
+                    nx = (nx & ~db) | (lx[i] & db);
+                    nz = (nz & ~db) | (lz[i] & db);
+                  }
+                  if (w == pw) {
+                    nx &= ~pb;
+                    nz = (nz & ~pb) | (q == a ? pb : 0ull);
+                  }
+                  if (nx != vx[i]) X[(size_t)q * RW + w] = nx;
+                  if (nz != vz[i]) Z[(size_t)q * RW + w] = nz;
+                }
+              }
+            }
+            s_c0[w * nch + chunk] = c0;
+            s_c1[w * nch + chunk] = c1;
+          }
+        } else {
           const uint32_t w = tid % RW, chunk = tid / RW;
           if (chunk < nch) {
             uint64_t c0 = 0, c1 = 0;
@@ -763,37 +831,19 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
           }
         }
         // Tableau, one thread per column: rows with x_a take row p's x/z;
-        // destabilizer p-n becomes row p; row p becomes Z_a.
-        for (uint32_t q = tid; q < n; q += kThreads) {
+        // destabilizer p-n becomes row p; row p becomes Z_a (a tableau in
+        // global memory was updated in the pass above).
+        for (uint32_t q = tid; TAB_LDS && q < n; q += kThreads) {
           uint64_t* xq = X + (size_t)q * RW;
           uint64_t* zq = Z + (size_t)q * RW;
           const uint64_t bx = ((s_rpx[q >> 6] >> (q & 63)) & 1u) ? pb : 0ull;
           const uint64_t bz = ((s_rpz[q >> 6] >> (q & 63)) & 1u) ? pb : 0ull;
           const uint64_t lx = bx ? ~0ull : 0ull, lz = bz ? ~0ull : 0ull;
-          if ((bx | bz) && TAB_LDS) {   // otherwise the column keeps its words
+          if (bx | bz) {   // otherwise the column keeps its words
             for (uint32_t w = 0; w < RW; ++w) {
               const uint64_t m = s_mask[w];
               xq[w] ^= m & lx;
               zq[w] ^= m & lz;
-            }
-          } else if (bx | bz) {
-            // A tableau in global memory: eight words' loads are issued before
-            // any store (X and Z may alias as far as the compiler knows, so it
-            // would not hoist them), and words the mask leaves alone are not
-            // written.
-            for (uint32_t w0 = 0; w0 < RW; w0 += 8) {
-              uint64_t xv[8], zv[8];
-#pragma unroll
-              for (uint32_t u = 0; u < 8; ++u) {
-                xv[u] = w0 + u < RW ? xq[w0 + u] : 0ull;
-                zv[u] = w0 + u < RW ? zq[w0 + u] : 0ull;
-              }
-#pragma unroll
-              for (uint32_t u = 0; u < 8; ++u) {
-                const uint64_t m = w0 + u < RW ? s_mask[w0 + u] : 0ull;
-                if (m & lx) xq[w0 + u] = xv[u] ^ m;
-                if (m & lz) zq[w0 + u] = zv[u] ^ m;
-              }
             }
           }
           const uint32_t dr = p - n, dw = dr >> 6;
