@@ -677,8 +677,8 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
           // A tableau in global memory: in the columns where row p has x or
           // z, one pass reads each word once, adds it to the g sums and
           // writes it updated (rows with x_a take row p's x/z; destabilizer
-          // p-n becomes row p; row p becomes Z_a), with eight columns' loads
-          // in flight.  Word w of such a column q belongs to thread
+          // p-n becomes row p; row p becomes Z_a), several columns' loads in
+          // flight.  Word w of such a column q belongs to thread
           // (w, q mod nch) alone, and the mask comes from LDS, so no thread
           // reads a word another one writes.  In the other columns only
           // destabilizer p-n changes (it becomes row p's zeros), one thread
@@ -697,37 +697,46 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
             const uint64_t mw = s_mask[w];   // x_a of every row but p
             const bool fix = w == pw || w == dw;   // words every such column rewrites
             if (mw || fix) {
-              for (uint32_t q0 = chunk; q0 < n; q0 += 8 * nch) {
-                uint64_t vx[8], vz[8], lx[8], lz[8];
-                bool act[8];
+              // Columns' loads in flight (fewer where the one-pass kernel
+              // keeps more registers live for the phase rows).
+              constexpr uint32_t kF = LOG ? 8 : 4;
+              for (uint32_t q0 = chunk; q0 < n; q0 += kF * nch) {
+                // Bit i: column q0 + i nch has row p's x (bx), z (bz), and is
+                // read and written (act).
+                uint32_t bx = 0, bz = 0, act = 0;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                  const uint32_t q = q0 + (uint32_t)i * nch;
-                  lx[i] = lz[i] = 0;
+                for (uint32_t i = 0; i < kF; ++i) {
+                  const uint32_t q = q0 + i * nch;
                   if (q < n) {
-                    lx[i] = ((s_rpx[q >> 6] >> (q & 63)) & 1u) ? ~0ull : 0ull;
-                    lz[i] = ((s_rpz[q >> 6] >> (q & 63)) & 1u) ? ~0ull : 0ull;
+                    bx |= (uint32_t)((s_rpx[q >> 6] >> (q & 63)) & 1u) << i;
+                    bz |= (uint32_t)((s_rpz[q >> 6] >> (q & 63)) & 1u) << i;
                   }
-                  act[i] = q < n && (lx[i] | lz[i]) && (fix || mw);
-                  vx[i] = act[i] ? X[(size_t)q * RW + w] : 0ull;
-                  vz[i] = act[i] ? Z[(size_t)q * RW + w] : 0ull;
+                }
+                act = (fix || mw) ? (bx | bz) : 0u;
+                uint64_t vx[kF], vz[kF];
+#pragma unroll
+                for (uint32_t i = 0; i < kF; ++i) {
+                  const size_t o = (size_t)(q0 + i * nch) * RW + w;
+                  vx[i] = ((act >> i) & 1u) ? X[o] : 0ull;
+                  vz[i] = ((act >> i) & 1u) ? Z[o] : 0ull;
                 }
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                  if (!act[i]) continue;
-                  const uint32_t q = q0 + (uint32_t)i * nch;
-                  if (mw && (lx[i] | lz[i])) {
+                for (uint32_t i = 0; i < kF; ++i) {
+                  if (!((act >> i) & 1u)) continue;
+                  const uint32_t q = q0 + i * nch;
+                  const uint64_t lx = ((bx >> i) & 1u) ? ~0ull : 0ull, lz = ((bz >> i) & 1u) ? ~0ull : 0ull;
+                  if (mw) {
                     uint64_t plus, minus;
-                    g_masks(lx[i], lz[i], vx[i], vz[i], plus, minus);
+                    g_masks(lx, lz, vx[i], vz[i], plus, minus);
                     c1 ^= c0 & plus;
                     c0 ^= plus;
                     c1 ^= ~c0 & minus;
                     c0 ^= minus;
                   }
-                  uint64_t nx = vx[i] ^ (mw & lx[i]), nz = vz[i] ^ (mw & lz[i]);
+                  uint64_t nx = vx[i] ^ (mw & lx), nz = vz[i] ^ (mw & lz);
                   if (w == dw) {
-                    nx = (nx & ~db) | (lx[i] & db);
-                    nz = (nz & ~db) | (lz[i] & db);
+                    nx = (nx & ~db) | (lx & db);
+                    nz = (nz & ~db) | (lz & db);
                   }
                   if (w == pw) {
                     nx &= ~pb;
