@@ -70,6 +70,7 @@ constexpr uint32_t kMaxDW = kMaxQubits / 64;       // words of a phase-row mask 
 constexpr uint32_t kChunks = 32;                   // kMaxRW x kChunks: the random branch's chunk counters
 constexpr uint32_t kMaxChunks = 64;                // column chunks of the random-branch g sums, at most
 constexpr size_t kStaticLds = 32 * 1024;           // at least the kernel's static LDS
+constexpr uint32_t kPairStride = 34;               // a wave's column pairs: 64 columns and three pads, rounded up
 
 // Device instruction stream: a header word (opcode | count << 8), then
 // `count` items.
@@ -188,6 +189,27 @@ __device__ __forceinline__ T ld(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Raw buffer access to one tableau half (n columns of RW words).  The
+// hardware range check reads 0 for a byte offset at or beyond the buffer's
+// size and drops such a store, so a lane with nothing to do is given an
+// offset with bit 31 set instead of a branch.
+constexpr uint32_t kBufWord3 = 0x00020000u;   // descriptor word 3: 32-bit data format, no swizzle
+constexpr uint32_t kBeyond = 0x80000000u;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tab_rsrc(uint64_t* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, (int)kBufWord3);
+}
+__device__ __forceinline__ uint64_t buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+  return (uint64_t)v.x | (uint64_t)v.y << 32;
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, uint64_t x) {
+  u32x2 v;
+  v.x = (uint32_t)x;
+  v.y = (uint32_t)(x >> 32);
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+}
+
 // TAB_LDS: the tableau lives in dynamic LDS (2 n RW words), else in the
 // work buffer.  LOG: the logged pass, which leaves the phase rows to the
 // replay kernel and writes the row-operation log instead.
@@ -205,6 +227,7 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
   __shared__ uint32_t s_red[kThreads / 64];
   __shared__ uint32_t s_scan[kThreads / 64];
   __shared__ uint32_t s_tgt[kTargetChunk];   // targets of the current measurement instruction
+  __shared__ uint32_t s_pair[kThreads / 64 * kPairStride];   // random outcome, tableau in global memory: each wave's column pairs
   const uint32_t tid = threadIdx.x;
   const uint32_t n = d.n, RW = d.RW, W = d.W;
 
@@ -656,99 +679,129 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
         }
         // Row p's x and z in every column, one thread per column: only the
         // columns where row p has x or z add to the g sums below.
-        {
-          uint64_t bxq = 0, bzq = 0;
-          if (tid < n) {
-            bxq = X[(size_t)tid * RW + pw] & pb;
-            bzq = Z[(size_t)tid * RW + pw] & pb;
+        uint64_t bxq = 0, bzq = 0, mx, mz;
+        if (tid < n) {
+          bxq = X[(size_t)tid * RW + pw] & pb;
+          bzq = Z[(size_t)tid * RW + pw] & pb;
+        }
+        mx = __ballot(bxq != 0);
+        mz = __ballot(bzq != 0);
+        if (lane == 0) {
+          s_rpx[wave] = mx;
+          s_rpz[wave] = mz;
+        }
+        // Tableau in global memory: each wave lists its own 64 columns where
+        // row p has x or z in pairs by row p's Pauli there (X, then Z, then
+        // Y, each padded to an even count with an entry that names no
+        // column); the wave then updates exactly those columns below.
+        const uint32_t kxn = (uint32_t)__builtin_popcountll(mx & ~mz), kzn = (uint32_t)__builtin_popcountll(mz & ~mx),
+                       kyn = (uint32_t)__builtin_popcountll(mx & mz);
+        const uint32_t o1 = (kxn + 1) & ~1u, o2 = o1 + ((kzn + 1) & ~1u), npair = (o2 + ((kyn + 1) & ~1u)) / 2;
+        if (!TAB_LDS) {
+          uint16_t* const col = reinterpret_cast<uint16_t*>(s_pair + wave * kPairStride);
+          const uint64_t below = (1ull << lane) - 1ull;
+          if (bxq | bzq) {
+            const uint32_t at = bzq == 0   ? (uint32_t)__builtin_popcountll(mx & ~mz & below)
+                                : bxq == 0 ? o1 + (uint32_t)__builtin_popcountll(mz & ~mx & below)
+                                           : o2 + (uint32_t)__builtin_popcountll(mx & mz & below);
+            col[at] = (uint16_t)tid;
           }
-          const uint64_t mx = __ballot(bxq != 0), mz = __ballot(bzq != 0);
           if (lane == 0) {
-            s_rpx[wave] = mx;
-            s_rpz[wave] = mz;
+            if (kxn & 1u) col[kxn] = 0xFFFFu;
+            if (kzn & 1u) col[o1 + kzn] = 0xFFFFu;
+            if (kyn & 1u) col[o2 + kyn] = 0xFFFFu;
           }
         }
         __syncthreads();
         // g sums of every row against row p, bit-sliced mod 4, per (word, column
-        // chunk): thread tid takes word tid % RW of chunk tid / RW, so a
-        // wave's loads cover consecutive words and every lane works.
-        const uint32_t nch = min(kMaxChunks, kThreads / RW);   // column chunks
+        // chunk), then added over the chunks.
+        // Tableau in LDS: thread tid takes word tid % RW of chunk tid / RW, so
+        // a wave's loads cover consecutive words and every lane works.
+        // Tableau in global memory: a chunk is a wave (lane = word, both
+        // halves added).
+        const uint32_t nch = TAB_LDS ? min(kMaxChunks, kThreads / RW) : kThreads / 64;   // column chunks
         if (!TAB_LDS) {
-          // A tableau in global memory: in the columns where row p has x or
-          // z, one pass reads each word once, adds it to the g sums and
-          // writes it updated (rows with x_a take row p's x/z; destabilizer
-          // p-n becomes row p; row p becomes Z_a), several columns' loads in
-          // flight.  Word w of such a column q belongs to thread
-          // (w, q mod nch) alone, and the mask comes from LDS, so no thread
-          // reads a word another one writes.  In the other columns only
-          // destabilizer p-n changes (it becomes row p's zeros), one thread
-          // per column.
-          const uint32_t w = tid % RW, chunk = tid / RW;
+          // In the columns where row p has x or z, one pass reads each word
+          // once, adds it to the g sums and writes it updated: rows with x_a
+          // take row p's x/z, destabilizer p-n becomes row p, row p becomes
+          // Z_a.  A wave takes its own listed columns a pair at a time, one
+          // column per half-wave: the g terms and the update then have one
+          // form per pair and no branch, and a half-wave's loads and stores
+          // cover a column's words (lane w: word w).  No other wave reads or
+          // writes these columns before the next barrier.  In the other
+          // columns only destabilizer p-n changes (it becomes row p's zeros).
           const uint32_t dr = p - n, dw = dr >> 6;
           const uint64_t db = 1ull << (dr & 63);
-          for (uint32_t q = tid; q < n; q += kThreads) {
-            if (((s_rpx[q >> 6] | s_rpz[q >> 6]) >> (q & 63)) & 1u) continue;
-            const uint64_t vx = X[(size_t)q * RW + dw], vz = Z[(size_t)q * RW + dw];
-            if (vx & db) X[(size_t)q * RW + dw] = vx & ~db;
-            if (vz & db) Z[(size_t)q * RW + dw] = vz & ~db;
+          if (tid < n && !(bxq | bzq)) {
+            const uint64_t vx = X[(size_t)tid * RW + dw], vz = Z[(size_t)tid * RW + dw];
+            if (vx & db) X[(size_t)tid * RW + dw] = vx & ~db;
+            if (vz & db) Z[(size_t)tid * RW + dw] = vz & ~db;
           }
-          if (chunk < nch) {
-            uint64_t c0 = 0, c1 = 0;
-            const uint64_t mw = s_mask[w];   // x_a of every row but p
-            const bool fix = w == pw || w == dw;   // words every such column rewrites
-            if (mw || fix) {
-              // Columns' loads in flight (fewer where the one-pass kernel
-              // keeps more registers live for the phase rows).
-              constexpr uint32_t kF = LOG ? 8 : 4;
-              for (uint32_t q0 = chunk; q0 < n; q0 += kF * nch) {
-                // Bit i: column q0 + i nch has row p's x (bx), z (bz), and is
-                // read and written (act).
-                uint32_t bx = 0, bz = 0, act = 0;
+          const uint32_t w = lane & 31u, half = lane >> 5;
+          const uint64_t mw = w < RW ? s_mask[w] : 0ull;   // x_a of every row but p
+          const uint64_t dbm = w == dw ? db : 0ull, pbm = w == pw ? pb : 0ull;
+          const uint64_t keep = ~(dbm | pbm), m1 = mw & keep;   // m1: rows taking row p, but the rewritten two
+          // Byte offset of word w in a column, beyond the buffer where the
+          // column's word cannot change; `fix` (added to the store offset of
+          // the half that changes only at the rewritten rows) likewise.
+          const uint32_t live = (w < RW && (mw | dbm | pbm)) ? w * 8u : kBeyond;
+          const uint32_t fix = (dbm | pbm) ? 0u : kBeyond;
+          const uint32_t cb = RW * 8u;   // bytes per column
+          const __amdgpu_buffer_rsrc_t rx = tab_rsrc(X, n * cb), rz = tab_rsrc(Z, n * cb);
+          uint64_t c0 = 0, c1 = 0;
+          // c += plus; c -= minus (mod 4, per bit)
+          auto add = [&](uint64_t plus, uint64_t minus) {
+            c1 ^= c0 & plus;
+            c0 ^= plus;
+            c1 ^= ~c0 & minus;
+            c0 ^= minus;
+          };
+          // Pairs' loads in flight (fewer where the one-pass kernel keeps more
+          // registers live for the phase rows).
+          constexpr uint32_t kF = LOG ? 4 : 2;
+          const uint32_t* const pairs = s_pair + wave * kPairStride;
+          for (uint32_t s0 = 0; s0 < npair; s0 += kF) {
+            uint32_t off[kF];
+            uint64_t vx[kF], vz[kF];
+            uint32_t isa = 0;   // bit i: pair i's column in this half is column a
 #pragma unroll
-                for (uint32_t i = 0; i < kF; ++i) {
-                  const uint32_t q = q0 + i * nch;
-                  if (q < n) {
-                    bx |= (uint32_t)((s_rpx[q >> 6] >> (q & 63)) & 1u) << i;
-                    bz |= (uint32_t)((s_rpz[q >> 6] >> (q & 63)) & 1u) << i;
-                  }
-                }
-                act = (fix || mw) ? (bx | bz) : 0u;
-                uint64_t vx[kF], vz[kF];
+            for (uint32_t i = 0; i < kF; ++i) {
+              const uint32_t s = s0 + i;
+              const uint32_t q = s < npair ? (pairs[s] >> (16u * half)) & 0xFFFFu : 0xFFFFu;
+              off[i] = q * cb + live;   // beyond the tableau for a pad (q * cb >= n cb) or a dead lane
+              isa |= (q == a ? 1u : 0u) << i;
+              vx[i] = buf_ld(rx, off[i]);
+              vz[i] = buf_ld(rz, off[i]);
+            }
 #pragma unroll
-                for (uint32_t i = 0; i < kF; ++i) {
-                  const size_t o = (size_t)(q0 + i * nch) * RW + w;
-                  vx[i] = ((act >> i) & 1u) ? X[o] : 0ull;
-                  vz[i] = ((act >> i) & 1u) ? Z[o] : 0ull;
-                }
-#pragma unroll
-                for (uint32_t i = 0; i < kF; ++i) {
-                  if (!((act >> i) & 1u)) continue;
-                  const uint32_t q = q0 + i * nch;
-                  const uint64_t lx = ((bx >> i) & 1u) ? ~0ull : 0ull, lz = ((bz >> i) & 1u) ? ~0ull : 0ull;
-                  if (mw) {
-                    uint64_t plus, minus;
-                    g_masks(lx, lz, vx[i], vz[i], plus, minus);
-                    c1 ^= c0 & plus;
-                    c0 ^= plus;
-                    c1 ^= ~c0 & minus;
-                    c0 ^= minus;
-                  }
-                  uint64_t nx = vx[i] ^ (mw & lx), nz = vz[i] ^ (mw & lz);
-                  if (w == dw) {
-                    nx = (nx & ~db) | (lx & db);
-                    nz = (nz & ~db) | (lz & db);
-                  }
-                  if (w == pw) {
-                    nx &= ~pb;
-                    nz = (nz & ~pb) | (q == a ? pb : 0ull);
-                  }
-                  if (nx != vx[i]) X[(size_t)q * RW + w] = nx;
-                  if (nz != vz[i]) Z[(size_t)q * RW + w] = nz;
-                }
+            for (uint32_t i = 0; i < kF; ++i) {
+              const uint32_t s = s0 + i;
+              if (s >= npair) break;
+              const uint64_t x = vx[i], z = vz[i];
+              const uint64_t pa = ((isa >> i) & 1u) ? pbm : 0ull;   // row p becomes Z_a
+              if (2 * s < o1) {   // row p has X: +1 on Y, -1 on Z
+                add(x & z, ~x & z);
+                buf_st(rx, off[i], ((x ^ m1) & keep) | dbm);
+                buf_st(rz, off[i] | fix, (z & keep) | pa);
+              } else if (2 * s < o2) {   // Z: +1 on X, -1 on Y
+                add(x & ~z, x & z);
+                buf_st(rx, off[i] | fix, x & keep);
+                buf_st(rz, off[i], ((z ^ m1) & keep) | dbm);
+              } else {   // Y: +1 on Z, -1 on X
+                add(~x & z, x & ~z);
+                buf_st(rx, off[i], ((x ^ m1) & keep) | dbm);
+                buf_st(rz, off[i], ((z ^ m1) & keep) | dbm | pa);
               }
             }
-            s_c0[w * nch + chunk] = c0;
-            s_c1[w * nch + chunk] = c1;
+          }
+          {   // the other half-wave's columns
+            const uint64_t b0 = shfl_xor64(c0, 32), b1 = shfl_xor64(c1, 32);
+            c1 ^= b1 ^ (c0 & b0);
+            c0 ^= b0;
+          }
+          if (half == 0 && w < RW) {
+            s_c0[w * nch + wave] = c0;
+            s_c1[w * nch + wave] = c1;
           }
         } else {
           const uint32_t w = tid % RW, chunk = tid / RW;
@@ -805,6 +858,7 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
           const uint32_t w = tid / 4, qt = tid % 4;
           uint64_t c0 = 0, c1 = 0;
           if (w < RW) {
+#pragma unroll 4
             for (uint32_t ch = qt; ch < nch; ch += 4) {
               const uint64_t b0 = s_c0[w * nch + ch], b1 = s_c1[w * nch + ch];
               c1 ^= b1 ^ (c0 & b0);
