@@ -88,7 +88,7 @@ int set_error(int code, const std::string& msg);
 
 // Records a wave queues before it evaluates them (sparse path): one per
 // (block, word, lane) with a fired location, 16 bytes of draws and a 4-byte
-// tag.
+// tag, stored as five arrays of kQueueCap words (draw 0..3, tag).
 constexpr uint32_t kQueueCap = 64;
 constexpr uint32_t kQueueRecBytes = 20;
 

@@ -365,13 +365,14 @@ __device__ __forceinline__ void walk_rows(const DevModel& m, uint32_t base, uint
 }
 
 // A wave's record queue (sparse path): record i is the four draws of one
-// lane in one block and word, u[i], and its tag t[i] = block << 8 | lane << 2
-// | word.  A lane appends a record when any location of the block fired in
-// its shot; the four draws say which ones did (u <= T_m - 1, with T_m from
-// the block's hot record).
+// lane in one block and word, w[i], w[C + i], w[2C + i], w[3C + i] (C =
+// kQueueCap), and its tag w[4C + i] = block << 8 | lane << 2 | word, so that a
+// lane writes or reads a record at one address and constant offsets.  A lane
+// appends a record when any location of the block fired in its shot; the
+// four draws say which ones did (u <= T_m - 1, with T_m from the block's hot
+// record).
 struct Queue {
-  uint4* u;
-  uint32_t* t;
+  uint32_t* w;
 };
 
 // Evaluates the queued records, one per lane: the lane reloads its block's
@@ -385,8 +386,9 @@ __device__ __forceinline__ void flush_records(const DevModel& m, uint64_t* slab,
                                               uint32_t lane) {
   wave_sync();
   if (lane < qn) {
-    const uint4 u = q.u[lane];
-    const uint32_t tag = q.t[lane];
+    constexpr uint32_t C = sp::kQueueCap;
+    const uint4 u = make_uint4(q.w[lane], q.w[C + lane], q.w[2 * C + lane], q.w[3 * C + lane]);
+    const uint32_t tag = q.w[4 * C + lane];
     const uint32_t b = tag >> 8;
     const uint4 tm1 = *(const SP_GLOBAL_AS uint4*)((const SP_GLOBAL_AS char*)m.hot + (b << 5));
     const SP_GLOBAL_AS char* cw = (const SP_GLOBAL_AS char*)m.cold + (b << 6);   // meta | lst | end | btab
@@ -537,16 +539,16 @@ __device__ __forceinline__ Hot draw_block(const LaunchArgs& a, uint64_t* slab, c
       flush_records<R>(m, slab, q, qn, lane4 >> 2);
       qn = 0;
     }
-    uint32_t* ud = reinterpret_cast<uint32_t*>(q.u + qn);   // wave-uniform bases
-    uint32_t* td = q.t + qn;
+    constexpr uint32_t C = sp::kQueueCap;
+    uint32_t* qd = q.w + qn;   // wave-uniform base
     const uint32_t tag = (b << 8) | (uint32_t)r;
     if (c[r][0] | c[r][1] | c[r][2] | c[r][3]) {   // this lane's shot fired somewhere in the block
       const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(fr[r] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fr[r], 0u));
-      ud[4 * pos + 0] = u[r].x;
-      ud[4 * pos + 1] = u[r].y;
-      ud[4 * pos + 2] = u[r].z;
-      ud[4 * pos + 3] = u[r].w;
-      td[pos] = tag | lane4;
+      qd[pos] = u[r].x;
+      qd[C + pos] = u[r].y;
+      qd[2 * C + pos] = u[r].z;
+      qd[3 * C + pos] = u[r].w;
+      qd[4 * C + pos] = tag | lane4;
     }
     qn += n;
   }
@@ -625,10 +627,10 @@ __device__ __forceinline__ void process_group(const LaunchArgs& a, uint64_t* sla
   const uint64_t first = a.first_shot + (uint64_t)g * R * 64u;
   const uint64_t last = first + (uint64_t)R * 64u - 1u;
   // The waves' record queues follow the slabs (16-byte aligned): per wave,
-  // kQueueCap 16-byte draw records, then their 4-byte tags.
+  // kQueueCap records of five words.
   char* qbase = reinterpret_cast<char*>(slab + (((size_t)R * m.n_meas + 1u) & ~(size_t)1)) +
                 (size_t)wave * sp::kQueueCap * sp::kQueueRecBytes;
-  const Queue queue{reinterpret_cast<uint4*>(qbase), reinterpret_cast<uint32_t*>(qbase + sp::kQueueCap * 16u)};
+  const Queue queue{reinterpret_cast<uint32_t*>(qbase)};
   if ((first >> 32) == (last >> 32)) run_blocks<R, DENSE, true>(a, slab, queue, g, wave, n_waves, lane);
   else run_blocks<R, DENSE, false>(a, slab, queue, g, wave, n_waves, lane);
   __syncthreads();
