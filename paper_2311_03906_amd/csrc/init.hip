@@ -1350,6 +1350,16 @@ __global__ void __launch_bounds__(kReplayThreads) replay_kernel(ReplayArgs r) {
       const bool in = (var >> 6) >= w_lo && (var >> 6) < w_lo + Ks;
       const uint32_t vk = (var >> 6) - w_lo;
       const uint64_t vb = 1ull << (var & 63);
+      // Row p zero in the slice and the variable elsewhere: nothing here
+      // changes (most entries, for most slices).  Every wave reads the same
+      // words, so all skip alike; the read needs no barrier unless wave 0
+      // wrote alone since the last one, and the entry's own writes, if it is
+      // not skipped, wait for every wave's read (read_pending).
+      if (!in && !solo_wrote) {
+        const uint64_t vp = lane < Ks ? s_P[p * K + lane] : 0ull;
+        read_pending = true;
+        if (__ballot(vp != 0) == 0) continue;
+      }
       // The listed rows (row p is not among them) take row p's symbols; row p
       // becomes the fresh variable, which a reset then adds to the rows with
       // z_a instead.

@@ -214,6 +214,20 @@ def test_surface_d15_detectors_device_model(mode):
     _same_model(_device_model(text, "detectors", mode), sp.Model(text, outputs="detectors"))
 
 
+@pytest.mark.parametrize("outputs,p", [("detectors", "0.005"), ("measurements", "0.001")])
+def test_two_pass_replay_repeats_exactly(outputs, p):
+    """Surface d=15 in two passes, four times in a row: every build equals
+    the host model.  The replay's workgroups skip log entries that leave
+    their slice unchanged without a barrier, and a missing one shows up as
+    builds that differ from run to run."""
+    text = surface_memory(15, 15, p, detectors=outputs == "detectors").text()
+    host = sp.Model(text, outputs=outputs)
+    circ = sp.Circuit(text)
+    for i in range(4):
+        _say(f"two-pass surface d15 {outputs} build {i}")
+        _same_model(sp.Model(circ, outputs=outputs, init="device", init_mode="two_pass"), host)
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_max_qubits(mode):
     """1024 qubits (the limit: 32 tableau words per column) with
