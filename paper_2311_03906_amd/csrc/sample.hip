@@ -88,6 +88,13 @@ struct RoundKeys {
   uint32_t k0[10], k1[10];
 };
 
+// A uniform value held in a vector register.
+__device__ __forceinline__ uint32_t to_vgpr(uint32_t x) {
+  uint32_t v;
+  asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+  return v;
+}
+
 __device__ __forceinline__ RoundKeys round_keys(uint32_t key0, uint32_t key1) {
   RoundKeys k;
 #pragma unroll
@@ -587,7 +594,15 @@ __device__ __forceinline__ void run_blocks(const LaunchArgs& a, uint64_t* slab, 
                                            uint32_t wave, uint32_t n_waves, uint32_t lane) {
   const DevModel& m = a.m;
   if (wave >= m.nb) return;
-  const RoundKeys keys = round_keys(a.key0, a.key1);
+  RoundKeys keys = round_keys(a.key0, a.key1);
+  // Rounds 4..9 run on the vector unit alone: their keys in VGPRs (a copy in
+  // every lane) leave the scalar registers to the rest, so that eight waves
+  // per SIMD fit.
+#pragma unroll
+  for (int r = 4; r < 10; ++r) {
+    keys.k0[r] = to_vgpr(keys.k0[r]);
+    keys.k1[r] = to_vgpr(keys.k1[r]);
+  }
   ShotWord w[R];
   shot_words<R, UHI>(a, g, lane, keys, w);
   const uint32_t lane4 = lane << 2;
@@ -646,9 +661,14 @@ __device__ __forceinline__ void process_group(const LaunchArgs& a, uint64_t* sla
   }
 }
 
+// With one word per group the sampling kernels ask for eight waves per SIMD
+// (at most 64 VGPRs and 96 SGPRs): a CU then holds four 8-wave workgroups
+// where their LDS fits, which hides the record flush's load latency far
+// better than three.  With more words per group the slabs' LDS limits the
+// waves anyway, and the limit would spill vector registers.
 // One job per launch: workgroup b owns group xcd_group(b).
 template <int R, int DENSE>
-__global__ void __launch_bounds__(1024) sample_kernel(LaunchArgs a) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(R == 1 ? 8 : 1))) sample_kernel(LaunchArgs a) {
   extern __shared__ uint64_t slab[];
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
   const uint32_t wave = uniform(tid >> 6), n_waves = blockDim.x >> 6;
@@ -661,7 +681,7 @@ __global__ void __launch_bounds__(1024) sample_kernel(LaunchArgs a) {
 // together (tiles of unequal cost then share every XCD); each workgroup
 // reads its tile's record from the table with scalar loads.
 template <int R, int DENSE>
-__global__ void __launch_bounds__(1024) sample_tiles_kernel(TiledArgs t) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(R == 1 ? 8 : 1))) sample_tiles_kernel(TiledArgs t) {
   extern __shared__ uint64_t slab[];
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
   const uint32_t wave = uniform(tid >> 6), n_waves = blockDim.x >> 6;
@@ -703,7 +723,7 @@ __device__ __forceinline__ void process_job_group(const BatchJob& job, uint64_t*
 // can be replayed (for example from a captured graph) without any host-side
 // reset.
 template <int R, int DENSE>
-__global__ void __launch_bounds__(1024) batch_persistent_kernel(const BatchJob* __restrict__ jobs,
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(R == 1 ? 8 : 1))) batch_persistent_kernel(const BatchJob* __restrict__ jobs,
                                                                 const sp::BatchTask* __restrict__ tasks,
                                                                 uint32_t n_tasks, BatchCounters* ctr) {
   extern __shared__ uint64_t slab[];
@@ -749,7 +769,7 @@ __device__ __forceinline__ uint32_t run_swizzle(uint32_t b, uint32_t n) {
 // ordered heaviest first, so the hardware dispatcher hands out the
 // expensive groups first).
 template <int R, int DENSE>
-__global__ void __launch_bounds__(1024) batch_flat_kernel(const BatchJob* __restrict__ jobs,
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(R == 1 ? 8 : 1))) batch_flat_kernel(const BatchJob* __restrict__ jobs,
                                                           const uint32_t* __restrict__ group_job, uint32_t total) {
   extern __shared__ uint64_t slab[];
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
