@@ -661,11 +661,14 @@ __device__ __forceinline__ void process_group(const LaunchArgs& a, uint64_t* sla
   }
 }
 
-// With one word per group the sampling kernels ask for eight waves per SIMD
-// (at most 64 VGPRs and 96 SGPRs): a CU then holds four 8-wave workgroups
-// where their LDS fits, which hides the record flush's load latency far
-// better than three.  With more words per group the slabs' LDS limits the
-// waves anyway, and the limit would spill vector registers.
+// With one word per group the single-job kernels ask for eight waves per
+// SIMD (at most 64 VGPRs and 96 SGPRs): a CU then holds four 8-wave
+// workgroups where their LDS fits, which hides the record flush's load
+// latency far better than three.  With more words per group the slabs' LDS
+// limits the waves anyway, and the limit would spill vector registers; the
+// batched kernels, which keep a job's pointers in scalar registers, keep
+// the compiler's default too (under the limit those spill, and served
+// batches ran 5% slower).
 // One job per launch: workgroup b owns group xcd_group(b).
 template <int R, int DENSE>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(R == 1 ? 8 : 1))) sample_kernel(LaunchArgs a) {
@@ -723,7 +726,7 @@ __device__ __forceinline__ void process_job_group(const BatchJob& job, uint64_t*
 // can be replayed (for example from a captured graph) without any host-side
 // reset.
 template <int R, int DENSE>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(R == 1 ? 8 : 1))) batch_persistent_kernel(const BatchJob* __restrict__ jobs,
+__global__ void __launch_bounds__(1024) batch_persistent_kernel(const BatchJob* __restrict__ jobs,
                                                                 const sp::BatchTask* __restrict__ tasks,
                                                                 uint32_t n_tasks, BatchCounters* ctr) {
   extern __shared__ uint64_t slab[];
@@ -769,7 +772,7 @@ __device__ __forceinline__ uint32_t run_swizzle(uint32_t b, uint32_t n) {
 // ordered heaviest first, so the hardware dispatcher hands out the
 // expensive groups first).
 template <int R, int DENSE>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(R == 1 ? 8 : 1))) batch_flat_kernel(const BatchJob* __restrict__ jobs,
+__global__ void __launch_bounds__(1024) batch_flat_kernel(const BatchJob* __restrict__ jobs,
                                                           const uint32_t* __restrict__ group_job, uint32_t total) {
   extern __shared__ uint64_t slab[];
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
