@@ -261,9 +261,10 @@ int sp_model_device_bytes(const sp_model* model, int path, size_t* bytes);
  * returns (staging is internal and synchronous with respect to the host).
  *
  * Row tiles: the sampling kernel keeps a 64-shot word's output rows in one
- * LDS slab (19,456 rows at most on gfx950 with room for 16 waves' event
- * queues).  A model of more than 9,216 rows (two workgroups' slabs per CU)
- * is stored as row tiles of 4,096 rows; each tile holds only the locations
+ * LDS slab (17,920 rows at most on gfx950 with room for 16 waves' record
+ * queues).  A model of more than 8,960 rows (two 8-wave workgroups' slabs
+ * and queues per CU) is stored as row tiles of 3,840 rows (four per CU);
+ * each tile holds only the locations
  * that reach its rows, and sp_sample samples every tile in one launch (the
  * buffer then also holds a table of the tiles' descriptors).  The draws are
  * keyed by location, so the output is the same bit for bit whatever the

@@ -913,11 +913,12 @@ int choose_path(const sp_model& m, int path) {
 // (160 KB of LDS per workgroup on gfx950): the largest tile.  The automatic
 // choice keeps one tile while two 8-wave workgroups' slabs and queues fit a
 // CU (8,960 rows); past that, a single slab leaves too few waves per SIMD to
-// hide the draw's latency, and tiles of 4,096 rows sample faster despite the
-// draws that several tiles repeat.
+// hide the draw's latency, and tiles of 3,840 rows (four workgroups' slabs
+// and queues per CU) sample faster despite the draws that several tiles
+// repeat.
 constexpr uint32_t kSlabRowsMax = (160u * 1024u - 16u * sp::kQueueCap * sp::kQueueRecBytes) / 8u;
 constexpr uint32_t kOneTileRowsMax = (80u * 1024u - 8u * sp::kQueueCap * sp::kQueueRecBytes) / 8u;
-constexpr uint32_t kTileRowsAuto = 4096;
+constexpr uint32_t kTileRowsAuto = 3840;
 
 struct TileLayout {
   size_t hot, cold, entries, btab, bentries, c_mask, dense;

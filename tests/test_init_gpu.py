@@ -228,24 +228,41 @@ def test_two_pass_replay_repeats_exactly(outputs, p):
         _same_model(sp.Model(circ, outputs=outputs, init="device", init_mode="two_pass"), host)
 
 
-@pytest.mark.parametrize("mode", MODES)
-def test_max_qubits(mode):
-    """1024 qubits (the limit: 32 tableau words per column) with
-    measurements, resets and faults on the highest qubits."""
-    n = 1024
-    rng = np.random.default_rng(7)
+def _scrambled(n, seed=7):
+    """n qubits scrambled by layers of CNOTs, S and depolarizing faults,
+    with random-outcome measurements, Paulis controlled by them, resets
+    and faults on the highest qubits."""
+    rng = np.random.default_rng(seed)
     lines = [f"H {' '.join(map(str, range(0, n, 2)))}"]
     for _ in range(6):
-        perm = rng.permutation(n)
+        perm = rng.permutation(n)[: n - n % 2]
         lines.append("CX " + " ".join(map(str, perm)))
         lines.append("DEPOLARIZE1(0.001) " + " ".join(map(str, rng.choice(n, 64, replace=False))))
         lines.append("S " + " ".join(map(str, rng.choice(n, 300, replace=False))))
         lines.append("M " + " ".join(map(str, rng.choice(n, 40, replace=False))))
-        lines.append("CX rec[-1] 1023 rec[-2] 1000")
-    lines.append("MR 1023 1022 0")
+        lines.append(f"CX rec[-1] {n - 1} rec[-2] {n - 24}")
+    lines.append(f"MR {n - 1} {n - 2} 0")
     lines.append("M " + " ".join(map(str, range(n))))
-    text = "\n".join(lines) + "\n"
+    return "\n".join(lines) + "\n"
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_max_qubits(mode):
+    """1024 qubits (the limit: 32 tableau words per column) with
+    measurements, resets and faults on the highest qubits."""
+    text = _scrambled(1024)
     _say(f"device init 1024 qubits {mode}")
+    _same_model(_device_model(text, mode=mode), sp.Model(text))
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("n", [520, 600, 777])
+def test_global_tableau_ragged_words(n, mode):
+    """Tableaux too large for LDS whose columns fill 17, 19 and 25 of a
+    half-wave's 32 lanes (the random outcome's column pass leaves the rest
+    idle): the device model equals the host's."""
+    text = _scrambled(n, seed=n)
+    _say(f"device init {n} qubits {mode}")
     _same_model(_device_model(text, mode=mode), sp.Model(text))
 
 

@@ -488,14 +488,14 @@ def _many_rows_circuit(rounds=5000):
 
 def test_auto_row_tiles_beyond_one_slab():
     """25,000 output rows, more than one LDS slab holds: the upload splits
-    them into row tiles of 4,096 rows, and 2,048 shots equal the oracle's
+    them into row tiles of 3,840 rows, and 2,048 shots equal the oracle's
     word for word (every tile, every row)."""
     text = _many_rows_circuit()
     _say("auto row tiles 25000 rows 2048 shots")
     m = sp.Model(text)
     assert m.n_meas == 25_000
     dm = sp.DeviceModel(m)
-    assert (dm.n_tiles, dm.tile_rows_max) == (7, 4096)
+    assert (dm.n_tiles, dm.tile_rows_max) == (7, 3840)
     got = _gpu(dm, 2048, seed=21, first_shot=64)
     assert np.array_equal(got, oracle.Circuit(text).sample(seed=21, first_shot=64, shots=2048))
 
@@ -520,7 +520,7 @@ def test_paper_fig3_n700_device_init_and_row_tiles():
     for x, y in zip(m.export_csc(), host.export_csc()):
         assert np.array_equal(x, y)
     dm = sp.DeviceModel(m)
-    assert dm.n_tiles == math.ceil(m.n_meas / 4096)
+    assert dm.n_tiles == math.ceil(m.n_meas / 3840)
     shots = 1 << 16
     got = _gpu(dm, shots, seed=5)
     ids = np.sort(np.random.default_rng(0).choice(shots, 48, replace=False))

@@ -193,7 +193,7 @@ def test_wait_timeout_and_unknown_ticket():
 
 def test_serves_row_tiled_models_in_a_mix():
     """Row-tiled models (surface d=5 in 64-row tiles, the last one partial;
-    25,000 rows in automatic 4,096-row tiles) served together with one-tile
+    25,000 rows in automatic 3,840-row tiles) served together with one-tile
     models, with a small tick budget so that requests are split over many
     ticks: every output equals sp_sample's for the request alone, and one
     tiled request equals the oracle's."""
