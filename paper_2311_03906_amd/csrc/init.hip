@@ -742,7 +742,7 @@ __global__ void __launch_bounds__(kThreads) init_kernel(InitDev d) {
           const uint64_t dbm = w == dw ? db : 0ull, pbm = w == pw ? pb : 0ull;
           const uint64_t keep = ~(dbm | pbm), m1 = mw & keep;   // m1: rows taking row p, but the rewritten two
           // Byte offset of word w in a column, beyond the buffer where the
-          // column's word cannot change; `fix` (added to the store offset of
+          // column's word cannot change; `fix` (or-ed into the store offset of
           // the half that changes only at the rewritten rows) likewise.
           const uint32_t live = (w < RW && (mw | dbm | pbm)) ? w * 8u : kBeyond;
           const uint32_t fix = (dbm | pbm) ? 0u : kBeyond;
