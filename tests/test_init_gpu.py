@@ -214,17 +214,24 @@ def test_surface_d15_detectors_device_model(mode):
     _same_model(_device_model(text, "detectors", mode), sp.Model(text, outputs="detectors"))
 
 
-@pytest.mark.parametrize("outputs,p", [("detectors", "0.005"), ("measurements", "0.001")])
-def test_two_pass_replay_repeats_exactly(outputs, p):
-    """Surface d=15 in two passes, four times in a row: every build equals
-    the host model.  The replay's workgroups skip log entries that leave
-    their slice unchanged without a barrier, and a missing one shows up as
-    builds that differ from run to run."""
-    text = surface_memory(15, 15, p, detectors=outputs == "detectors").text()
+@pytest.mark.parametrize("case", ["surface_d15_detectors", "surface_d15_measurements", "fig3c_n200"])
+def test_two_pass_replay_repeats_exactly(case):
+    """Surface d=15 (resets, runs of determined outcomes) and Fig. 3c at
+    n = 200 (82,084 fault variables, mostly random outcomes) in two passes,
+    four times in a row: every build equals the host model.  The replay's
+    workgroups skip log entries that leave their slice unchanged without a
+    barrier, and a missing one shows up as builds that differ from run to
+    run."""
+    if case == "fig3c_n200":
+        outputs, text = "measurements", random_layered_circuit(200, seed=5, p_dep="0.001").text()
+    else:
+        outputs = case.split("_")[-1]
+        text = surface_memory(15, 15, "0.005" if outputs == "detectors" else "0.001",
+                              detectors=outputs == "detectors").text()
     host = sp.Model(text, outputs=outputs)
     circ = sp.Circuit(text)
     for i in range(4):
-        _say(f"two-pass surface d15 {outputs} build {i}")
+        _say(f"two-pass {case} build {i}")
         _same_model(sp.Model(circ, outputs=outputs, init="device", init_mode="two_pass"), host)
 
 
@@ -256,11 +263,12 @@ def test_max_qubits(mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
-@pytest.mark.parametrize("n", [520, 600, 777])
+@pytest.mark.parametrize("n", [513, 520, 600, 777, 1023])
 def test_global_tableau_ragged_words(n, mode):
-    """Tableaux too large for LDS whose columns fill 17, 19 and 25 of a
+    """Tableaux too large for LDS whose columns fill 17 to 32 of a
     half-wave's 32 lanes (the random outcome's column pass leaves the rest
-    idle): the device model equals the host's."""
+    idle), with the last wave holding 1 to 64 columns: the device model
+    equals the host's."""
     text = _scrambled(n, seed=n)
     _say(f"device init {n} qubits {mode}")
     _same_model(_device_model(text, mode=mode), sp.Model(text))
