@@ -21,7 +21,8 @@ struct DevModel {
   const uint32_t* bentries;  // per location and code bit, its column's rows as byte offsets (row << 3)
   const uint32_t* chans;     // [nch][16]: kind | m << 8, T_1..T_{m-1}, then 0xFFFFFFFF
   const uint64_t* c_mask;    // [ceil(n_meas/64)]
-  const uint64_t* dense;     // [n_vars][dense_words] (dense path only)
+  const uint64_t* dense;     // per variable: a bitmap of its non-zero words (ceil(dense_words/64)), then
+                             // its dense_words mask words (dense path only)
   uint32_t nb, n_meas, dense_words, nch;
   uint32_t nb_lazy;          // blocks [0, nb_lazy) are lazy, [nb_lazy, nb) eager (sparse path)
 };

@@ -267,11 +267,33 @@ __device__ __forceinline__ Masks decode(const uint32_t* chans, uint32_t meta, ui
 
 // Evaluate a fired location: XOR its code-bit masks into the slab rows of
 // its variables' columns of M.
+// Words of a dense column's bitmap of its non-zero words (bit c of the
+// bitmap: mask word c is not zero); the column stores the bitmap, then its
+// mask words.
+__device__ __forceinline__ uint32_t nz_words(uint32_t dense_words) { return (dense_words + 63u) >> 6; }
+
+// Only the column's non-zero words are visited (the bitmap read with scalar
+// loads), four at a time so that their loads are in flight together.
 __device__ __forceinline__ void xor_dense(const DevModel& m, uint64_t* slab, uint32_t var, uint64_t s, uint32_t lane) {
-  const cuint64_p col = (cuint64_p)m.dense + (size_t)var * m.dense_words;
-  for (uint32_t c = 0; c < m.dense_words; ++c) {
-    const uint64_t bits = col[c];
-    if ((bits >> lane) & 1ull) atomicXor((unsigned long long*)&slab[c * 64 + lane], (unsigned long long)s);
+  const uint32_t nzw = nz_words(m.dense_words);
+  const cuint64_p col = (cuint64_p)m.dense + (size_t)var * (m.dense_words + nzw);
+  const uint64_t lb = 1ull << lane;
+  for (uint32_t k = 0; k < nzw; ++k) {
+    uint64_t nz = col[k];
+    while (nz) {
+      uint32_t c[4];
+      uint64_t bits[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        c[i] = nz ? k * 64u + (uint32_t)__builtin_ctzll(nz) : 0xFFFFFFFFu;
+        nz &= nz - 1;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bits[i] = c[i] != 0xFFFFFFFFu ? col[nzw + c[i]] : 0ull;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (bits[i] & lb) atomicXor((unsigned long long*)&slab[c[i] * 64 + lane], (unsigned long long)s);
+    }
   }
 }
 
@@ -962,7 +984,7 @@ Layout plan(const sp_model& m, int path, uint32_t tile_rows) {
     T.bentries = off; off = align256(off + 4 * std::max<size_t>(H.bentries.size(), 1));
     T.c_mask = off;  off = align256(off + 8 * std::max<size_t>(T.dense_words, 1));
     T.dense = off;
-    if (path == SP_PATH_DENSE) off = align256(off + 8 * (size_t)m.n_vars * T.dense_words);
+    if (path == SP_PATH_DENSE) off = align256(off + 8 * (size_t)m.n_vars * (T.dense_words + (T.dense_words + 63) / 64));
     L.tiles.push_back(T);
   }
   L.table = off;
@@ -1186,12 +1208,16 @@ int sp_model_upload_tiled(const sp_model* model, int path, uint32_t tile_rows, v
         if ((model->c_bits[g >> 6] >> (g & 63)) & 1ull) cm[k >> 6] |= 1ull << (k & 63);
       }
       if (p == SP_PATH_DENSE) {
+        // Per variable: the bitmap of its non-zero words, then the words.
         uint64_t* d = reinterpret_cast<uint64_t*>(&host[T.dense]);
+        const size_t nzw = (T.dense_words + 63) / 64, stride = T.dense_words + nzw;
         for (uint32_t j = 0; j < model->n_vars; ++j)
           for (uint32_t i = model->col_ptr[j]; i < model->col_ptr[j + 1]; ++i) {
             const uint32_t k = model->row_idx[i];
             if (k < T.r0 || k >= T.r0 + T.rows) continue;
-            d[(size_t)j * T.dense_words + ((k - T.r0) >> 6)] |= 1ull << ((k - T.r0) & 63);
+            const uint32_t w = (k - T.r0) >> 6;
+            d[(size_t)j * stride + nzw + w] |= 1ull << ((k - T.r0) & 63);
+            d[(size_t)j * stride + (w >> 6)] |= 1ull << (w & 63);
           }
       }
     }
