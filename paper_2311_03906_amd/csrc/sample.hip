@@ -457,7 +457,7 @@ __device__ __forceinline__ void flush_records(const DevModel& m, uint64_t* slab,
 // (channels, variables and list bounds, 64 bytes).
 struct Hot {
   uint4 tm1;    // T_m - 1 per slot; 0 for a slot without a drawn location
-  uint4 blk;    // .x = l / 4
+  uint4 blk;    // .x = l / 4; .y bit 0: every drawn slot's channel has a single code
 };
 struct Cold {
   uint4 meta;   // var0 << 8 | channel + 1 per slot (1 and an empty list: no drawn location)
@@ -475,6 +475,33 @@ __device__ __forceinline__ void shot_words(const LaunchArgs& a, uint32_t g, uint
                                            ShotWord (&w)[R]) {
 #pragma unroll
   for (int r = 0; r < R; ++r) w[r] = shot_word<UHI>(a.first_shot + (uint64_t)(g * R + r) * 64u, lane, k);
+}
+
+// Evaluates an eager block whose drawn slots all have single-code channels
+// (random measurements, X, Y or Z flips): the mask of each of its variables
+// is its slot's fire mask, so the four consecutive entry lists are walked in
+// one pass, one entry per lane, each taking its slot's mask.
+template <int R>
+__device__ __forceinline__ void evaluate_single(const DevModel& m, uint64_t* slab, const Cold* cold, uint32_t b,
+                                                const uint64_t (&f)[R][4], uint32_t lane) {
+  const Cold c = load_uniform(cold + b);
+  const uint32_t lo = c.lst.x, n = c.end.x - lo;
+  const uint32_t e1 = c.lst.y - lo, e2 = c.lst.z - lo, e3 = c.lst.w - lo;   // where slots 1..3 start
+  const guint32_p entries = (guint32_p)m.entries;
+  for (uint32_t i = lane; i < n; i += 64) {
+    const uint32_t e = entries[lo + i];
+    // All ones from slot k's first entry on (e1 <= e2 <= e3), so that the
+    // slot's mask is a telescoping XOR (written as masked XORs, the masks
+    // stay scalar operands and no lookup table is formed).
+    const uint64_t s1 = (uint64_t)(int64_t)(int32_t)(0u - (uint32_t)(i >= e1));
+    const uint64_t s2 = (uint64_t)(int64_t)(int32_t)(0u - (uint32_t)(i >= e2));
+    const uint64_t s3 = (uint64_t)(int64_t)(int32_t)(0u - (uint32_t)(i >= e3));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t mk = f[r][0] ^ ((f[r][0] ^ f[r][1]) & s1) ^ ((f[r][1] ^ f[r][2]) & s2) ^ ((f[r][2] ^ f[r][3]) & s3);
+      if (mk) atomicXor((unsigned long long*)&row_of(slab + (size_t)r * m.n_meas, e), (unsigned long long)mk);
+    }
+  }
 }
 
 // Evaluates every fired location of block b now (lane = entry of the
@@ -555,7 +582,8 @@ __device__ __forceinline__ Hot draw_block(const LaunchArgs& a, uint64_t* slab, c
   }
   if (!any) return nx;   // the usual case at p ~ 1e-3: nothing fired in this block
   if (!QUEUE) {
-    evaluate_block<R, DENSE>(m, slab, reinterpret_cast<const Cold*>(m.cold), b, u, f, lane4 >> 2);
+    if (!DENSE && (cur.blk.y & 1u)) evaluate_single<R>(m, slab, reinterpret_cast<const Cold*>(m.cold), b, f, lane4 >> 2);
+    else evaluate_block<R, DENSE>(m, slab, reinterpret_cast<const Cold*>(m.cold), b, u, f, lane4 >> 2);
     return nx;
   }
   // Queue one record per fired lane and word.  A word's records always fit
@@ -819,6 +847,8 @@ constexpr uint64_t kEagerTm = 1ull << 29;
 //   [0..3]  T_m - 1 per slot (fire when u <= T_m - 1, i.e. u < T_m); 0 for
 //           a slot without a drawn location
 //   [4]     the Philox block index l/4
+//   [5]     1 when every drawn slot's channel has a single code (its
+//           variable's mask is the fire mask), else 0
 // followed, after the last block, by kHotPad zero records (read, never used),
 // and a cold record of 16 words:
 //   [0..3]  meta per slot: var0 << 8 | (channel + 1); 1 (channel 0, with an
@@ -874,6 +904,7 @@ HostBlocks build_blocks(const sp_model& m, uint32_t r0, uint32_t r1) {
       for (int i = 0; i < 4; ++i) w[i] = 1u;   // empty slot: the coin channel, empty list
       for (int i = 4; i <= 8; ++i) w[i] = (uint32_t)H.entries.size();
       H.hot[H.hot.size() - 8 + 4] = (uint32_t)blk;
+      H.hot[H.hot.size() - 8 + 5] = 1u;   // every drawn slot single-code, until one is not
       eager.push_back(0);
       cur = blk;
     }
@@ -881,6 +912,7 @@ HostBlocks build_blocks(const sp_model& m, uint32_t r0, uint32_t r1) {
     uint32_t* w = &H.cold[H.cold.size() - 16];
     const uint32_t s = l & 3u, var0 = (uint32_t)m.loc_var0[l];
     h[s] = (uint32_t)(Tm - 1);
+    if (c.m != 1) h[5] = 0u;
     if (Tm >= kEagerTm) eager.back() = 1;
     w[s] = (var0 << 8) | (uint32_t)(ch + 1);
     w[4 + s] = (uint32_t)H.entries.size();
