@@ -143,13 +143,30 @@ def _cpu_model() -> str:
     return "unknown"
 
 
+def padded_ld(words: int) -> int:
+    """Row stride (in words) for rows of `words` 64-shot words: an odd number
+    of 128-byte lines.  A workgroup writes one word of every row, so with a
+    stride of a large power of two (2^20 shots put rows 128 KiB apart) the
+    lines it and its neighbours write fall into a few L2 sets, which evict
+    them half-written and write each back several times."""
+    ld = -(-words // 16) * 16
+    return ld + 16 if (ld // 16) % 2 == 0 else ld
+
+
+def packed_out(torch, n_meas: int, words: int):
+    """Measurement-major output of n_meas rows of `words` words, row stride
+    padded_ld(words)."""
+    return torch.empty((n_meas, padded_ld(words)), dtype=torch.int64, device="cuda")[:, :words]
+
+
 def traffic_per_launch():
     """Scaled HBM bytes (FETCH_SIZE + WRITE_SIZE) per full-batch launch from
-    the committed counter profile, when it was taken of this sample.hip."""
+    the committed counter profile, when it was taken of this sample.hip and
+    this output row stride."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     t = json.load(open(TRAFFIC_FILE))
-    if t.get("kernel_sha256_16") != kernel_hash():
+    if t.get("kernel_sha256_16") != kernel_hash() or t.get("out_ld_words") != padded_ld(D15_BATCH // 64):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -180,7 +197,7 @@ def main():
     models = {p: sp.Model(texts[p]) for p in D15_PS}
     dms = {p: sp.DeviceModel(models[p], path="sparse") for p in D15_PS}
     n_meas = models[D15_PS[0]].n_meas
-    out = torch.empty((n_meas, D15_BATCH // 64), dtype=torch.int64, device="cuda")
+    out = packed_out(torch, n_meas, D15_BATCH // 64)
     batches = [(f, min(D15_BATCH, D15_TOTAL - f)) for f in range(0, D15_TOTAL, D15_BATCH)]
     # per-launch events on the stream the kernels run on (torch's current stream)
     launches = []   # (p, shots, start event, end event) of the timed steps
@@ -240,7 +257,8 @@ def main():
                    "n_qubits": m0.dims.n_qubits, "n_meas": n_meas,
                    "n_vars": {p: models[p].n_vars for p in D15_PS}, "drawn_locations": int(m0.dims.n_drawn),
                    "philox_blocks": int(m0.dims.n_draw_blocks), "shots_per_rate": D15_TOTAL,
-                   "batch_shots": D15_BATCH, "path": "sparse", "launch": list(dms[D15_PS[0]].launch), "seed": 0},
+                   "batch_shots": D15_BATCH, "out_ld_words": padded_ld(D15_BATCH // 64), "path": "sparse",
+                   "launch": list(dms[D15_PS[0]].launch), "seed": 0},
         "latency_ms": {"per_rate": per_p},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "Tops/s",
                      "frac": achieved / PEAK_VALU, "traffic": traffic_per_launch(),
@@ -329,7 +347,7 @@ def _d15_run(sp, torch, text, outputs="measurements") -> dict:
     m = sp.Model(text, outputs=outputs)
     dm = sp.DeviceModel(m, path="sparse")
     total, batch = D15_TOTAL, D15_BATCH
-    out = torch.empty((m.n_meas, batch // 64), dtype=torch.int64, device="cuda")
+    out = packed_out(torch, m.n_meas, batch // 64)
     starts = list(range(0, total, batch))
 
     def one(i):
@@ -357,7 +375,7 @@ def _dense15_leg(sp, torch, d15_texts) -> dict:
     for p, text in d15_texts.items():
         m = sp.Model(text)
         dm = sp.DeviceModel(m, path="dense")
-        out = torch.empty((m.n_meas, D15_BATCH // 64), dtype=torch.int64, device="cuda")
+        out = packed_out(torch, m.n_meas, D15_BATCH // 64)
         lat = _event_ms(lambda: dm.sample(D15_BATCH, seed=0, first_shot=0, out=out), 3, torch)
         ms = pct(lat, 50)
         res[f"surface_d15_r15_p{p}_dense_2^20_shots"] = {

@@ -291,6 +291,11 @@ int sp_dmodel_tiles(const sp_dmodel* dmodel, uint32_t* n_tiles, uint32_t* rows_m
  * (device, n_meas rows of ld_words words, 8-byte aligned,
  * ld_words >= ceil(shots/64)).  Asynchronous on `stream`.  The result is a
  * pure function of (model, seed, first_shot, shots).  shots = 0 is a no-op.
+ * Each workgroup writes one word (or 2 or 4) of every row, so a row stride
+ * of a large power of two (ld_words = 16,384 for 2^20 shots) sends the
+ * lines written together to a few L2 sets, which write them back several
+ * times; a stride of an odd number of 128-byte lines (ld_words = 16,400
+ * there) writes each line once.
  * Errors: SP_E_INVALID, SP_E_LIMIT, SP_E_DEVICE. */
 int sp_sample(const sp_dmodel* dmodel, uint64_t seed, uint64_t first_shot, uint64_t shots,
               uint64_t* d_out, size_t ld_words, void* stream);
