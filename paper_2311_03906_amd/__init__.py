@@ -248,7 +248,9 @@ class DeviceModel:
 
     def sample(self, shots: int, seed: int = 0, first_shot: int = 0, out: torch.Tensor | None = None,
                ld: int | None = None, stream=None) -> torch.Tensor:
-        """Packed outcomes (n_meas, ld) int64 (bit patterns of uint64 words)."""
+        """Packed outcomes (n_meas, ld) int64 (bit patterns of uint64 words).
+        `out` may be a row-strided view; rows an odd number of 128-byte lines
+        apart (ld = words + 16 for 2^20 shots) write each output line once."""
         words = (shots + 63) // 64
         if out is None:
             ld = max(words, 1) if ld is None else ld
