@@ -364,8 +364,10 @@ __device__ __forceinline__ void lds_xor(uint32_t addr, uint64_t v) {
 // Walks bentries[lo, hi) for one shot: each entry is the byte offset
 // (row << 3) of a slab row to flip, so each is one XOR of the shot's bit
 // (`bit`) into the slab at LDS address `base`.  Eight entry loads are kept
-// in flight.  BASE0: the slab starts at LDS address 0, so an entry is its
-// row's address.
+// in flight, and the last 1..7 entries are loaded together as well: the
+// table has 8 entries of slack after its end, so the loads that run past the
+// list stay inside it (their values are not used).  BASE0: the slab starts
+// at LDS address 0, so an entry is its row's address.
 template <bool BASE0>
 __device__ __forceinline__ void walk_rows(const DevModel& m, uint32_t base, uint32_t lo, uint32_t hi, uint64_t bit) {
   // 32-bit byte offsets from a uniform base, constant steps as immediates
@@ -381,16 +383,16 @@ __device__ __forceinline__ void walk_rows(const DevModel& m, uint32_t base, uint
 #pragma unroll
     for (int k = 0; k < 8; ++k) lds_xor(base + e[k], bit);
   }
-  if (o + 16 <= o1) {
+  if (o < o1) {   // the last 1..7 entries: seven loads at once, r XORs
     const SP_GLOBAL_AS uint32_t* pe = (const SP_GLOBAL_AS uint32_t*)(ce + o);
-    uint32_t e[4];
+    const uint32_t r = (o1 - o) >> 2;
+    uint32_t e[7];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) e[k] = pe[k];
+    for (int k = 0; k < 7; ++k) e[k] = pe[k];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) lds_xor(base + e[k], bit);
-    o += 16;
+    for (int k = 0; k < 7; ++k)
+      if ((uint32_t)k < r) lds_xor(base + e[k], bit);
   }
-  for (; o < o1; o += 4) lds_xor(base + *(const SP_GLOBAL_AS uint32_t*)(ce + o), bit);
 }
 
 // A wave's record queue (sparse path): record i is the four draws of one
@@ -1013,7 +1015,7 @@ Layout plan(const sp_model& m, int path, uint32_t tile_rows) {
     T.cold = off;    off = align256(off + 64 * std::max<size_t>(T.nb, 1));
     T.entries = off; off = align256(off + 4 * std::max<size_t>(H.entries.size(), 1));
     T.btab = off;    off = align256(off + 4 * std::max<size_t>(H.btab.size(), 1));
-    T.bentries = off; off = align256(off + 4 * std::max<size_t>(H.bentries.size(), 1));
+    T.bentries = off; off = align256(off + 4 * (H.bentries.size() + 8));   // + slack read by walk_rows
     T.c_mask = off;  off = align256(off + 8 * std::max<size_t>(T.dense_words, 1));
     T.dense = off;
     if (path == SP_PATH_DENSE) off = align256(off + 8 * (size_t)m.n_vars * (T.dense_words + (T.dense_words + 63) / 64));
