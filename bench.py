@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "measurement bits sampled/s (shots×meas), batched vs plain; p50/p99 latency"
 PEAK_VALU = 256 * 4 * 16 * 2.4e9      # int32 lane-ops/s: CUs x SIMDs x lanes x clock
+PEAK_HBM = 8.0e12                      # bytes/s, MI355X HBM3E
 # Per-lane ALU work of one Philox4x32-10 block.  The counter is (l/4, shot
 # lo, shot hi, 0) and a wave of 64 shots shares l/4, the key and (almost
 # always) the high word, so round 1 and half of rounds 2-4 are wave-uniform
@@ -239,6 +240,10 @@ def main():
     ops_total = sum(v["ops"] for v in per_p.values())
     achieved = ops_total / (kernel_ms * 1e-3)
     m0 = models[D15_PS[0]]
+    # HBM bytes per full launch (counter profile) over the full launches' mean duration
+    traffic = traffic_per_launch()
+    full_ms = sum(v["ms_full_batch_p50"] for v in per_p.values()) / len(per_p)
+    hbm_rate = traffic / (full_ms * 1e-3) if traffic else 0.0
     rec = {
         "metric": METRIC,
         "value": bits / wall,
@@ -261,7 +266,9 @@ def main():
                    "launch": list(dms[D15_PS[0]].launch), "seed": 0},
         "latency_ms": {"per_rate": per_p},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "Tops/s",
-                     "frac": achieved / PEAK_VALU, "traffic": traffic_per_launch(),
+                     "frac": achieved / PEAK_VALU, "traffic": traffic,
+                     "hbm_GB_per_s": hbm_rate / 1e9 if traffic else None,
+                     "hbm_frac_of_8TB_per_s": hbm_rate / PEAK_HBM if traffic else None,
                      "kernel": "sample_kernel<1, 0>", "ops_per_full_launch": work_ops(m0, D15_BATCH),
                      "work_model": f"{WORK_PER_BLOCK} lane-ops per (shot, Philox block) + 1 per (shot, drawn location)",
                      "kernel_ms_mean": kernel_ms / len(launches),
