@@ -50,9 +50,9 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU legs (profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
-    ap.add_argument("--legs", default="rep,d5,dense15,outputs,init,fig3,mix,small,serving",
+    ap.add_argument("--legs", default="rep,d5,draw,dense15,outputs,init,fig3,mix,small,serving",
                     help="comma list of the other workloads to run "
-                         "(rep, d5, dense15, outputs, init, fig3, mix, small, serving)")
+                         "(rep, d5, draw, dense15, outputs, init, fig3, mix, small, serving)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -284,7 +284,7 @@ def main():
     legs = set() if args.no_extra else {x.strip() for x in args.legs.split(",") if x.strip()}
     if args.no_serving:
         legs.discard("serving")
-    known = {"rep", "d5", "dense15", "outputs", "init", "fig3", "mix", "small", "serving"}
+    known = {"rep", "d5", "draw", "dense15", "outputs", "init", "fig3", "mix", "small", "serving"}
     unknown = legs - known
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
@@ -315,6 +315,8 @@ def extra_workloads(sp, torch, surface_memory, repetition_memory, legs, d15_text
         res.update(_repetition_leg(sp, torch, repetition_memory))
     if "d5" in legs:
         res.update(_d5_leg(sp, torch, surface_memory))
+    if "draw" in legs:
+        res.update(_draw_only_leg(sp, torch, surface_memory))
     if "dense15" in legs:
         res.update(_dense15_leg(sp, torch, d15_texts))
     if "outputs" in legs:
@@ -370,6 +372,24 @@ def _d15_run(sp, torch, text, outputs="measurements") -> dict:
     dt = time.perf_counter() - t0
     return {"bits_per_s": total * m.n_meas / dt, "rows": m.n_meas, "seconds": dt, "batches": len(starts),
             "launch": list(dm.launch), "valu_frac": work_ops(m, total) / dt / PEAK_VALU, "nnz": int(m.dims.nnz)}
+
+
+def _draw_only_leg(sp, torch, surface_memory) -> dict:
+    """The draw's own ceiling: the d=15 circuit at p = 1e-9 has the same
+    Philox blocks, drawn locations and threshold compares as the headline,
+    but next to nothing fires (the random first-round measurements still do),
+    so five 2^20-shot launches time the draw and select alone."""
+    m = sp.Model(surface_memory(15, 15, "1e-9").text())
+    dm = sp.DeviceModel(m, path="sparse")
+    out = packed_out(torch, m.n_meas, D15_BATCH // 64)
+    lat = _event_ms(lambda: dm.sample(D15_BATCH, seed=0, first_shot=0, out=out), 5, torch)
+    ms = pct(lat, 50)
+    res = {"surface_d15_r15_p1e-9_draw_only_2^20_shots": {
+        "ms_per_launch": ms, "bits_per_s": D15_BATCH * m.n_meas / (ms * 1e-3),
+        "valu_frac": work_ops(m, D15_BATCH) / (ms * 1e-3) / PEAK_VALU,
+        "philox_blocks": int(m.dims.n_draw_blocks), "drawn_locations": int(m.dims.n_drawn)}}
+    del out, dm
+    return res
 
 
 def _dense15_leg(sp, torch, d15_texts) -> dict:
